@@ -1,0 +1,200 @@
+"""Benchmark of the pseudo-Verlet SPH density loop on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one pass of the whole hot path over the resident particle set:
+build_cells (binning into cells, explicit grid) + sort_cells (13 per-axis
+sorts) + density (sorted-pair sweep with in-place finalisation).  The plain
+cell-list comparator (build_cells + density with the 27-cell brute force) is
+timed the same way.  Inputs are seeded synthetic particle sets already in HBM.
+
+Prints one JSON line: pair-interactions/s of the sorted-pair path (value), the
+plain comparator, ns/particle, the sweep kernel's roofline and the fp64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Peak VALU rate of MI355X without packed fp32: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.3e12 lane-operations per second (an FMA counts once).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+# Algorithmic VALU work of the sweep: lane-operations per pair that passes the
+# projected-distance test (3 differences, 3 products for r^2, compare, key
+# test) and per pair in range (square root at quarter rate = 4, scaling, both
+# spline pieces and the select, 3 accumulations and the count).
+OPS_PER_CANDIDATE = 8
+OPS_PER_INTERACTION = 25
+
+
+def _args():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform-1m-lognormal")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def _time_loop(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return start.elapsed_time(stop) / steps, wall / steps * 1e3
+
+
+def main():
+    a = _args()
+    if a.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
+              "the path runs on a single MI355X and has no multi-GPU mode.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1804_06231_amd as pvl
+    from synth import workload, finest_grid
+
+    print(f"[bench] generating {a.workload}", file=sys.stderr, flush=True)
+    t0 = time.time()
+    s = workload(a.workload)
+    print(f"[bench] inputs ready in {time.time() - t0:.1f}s (n={s.n})", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    pos = torch.from_numpy(s.pos).to(dev)
+    h = torch.from_numpy(s.h).to(dev)
+    m = torch.from_numpy(s.m).to(dev)
+    ctx = pvl.Context(0)
+
+    # grid: the workload's own, else the finest legal one (found once, then the
+    # cell structure is rebuilt in place every step with that grid)
+    cells = ctx.build_cells(pos, h, m, s.box, s.grid)
+    grid = cells.info()["grid"]
+    ctx.sort_cells(cells)
+    out_s = ctx.density(cells, "sorted")
+    out_p = ctx.density(cells, "plain")
+    ctx.check()
+    torch.cuda.synchronize()
+    pairs = int(out_s[3].sum().item())
+    assert pairs == int(out_p[3].sum().item()), "sorted and plain neighbour counts differ"
+
+    # candidate census (untimed)
+    ctx.set_census(True)
+    ctx.density(cells, "sorted")
+    cand_sorted, inr = ctx.census()
+    ctx.density(cells, "plain")
+    cand_plain, _ = ctx.census()
+    ctx.set_census(False)
+
+    def step_sorted():
+        ctx.build_cells(pos, h, m, s.box, grid, cells)
+        ctx.sort_cells(cells)
+        ctx.density(cells, "sorted", out_s)
+
+    def step_plain():
+        ctx.build_cells(pos, h, m, s.box, grid, cells)
+        ctx.density(cells, "plain", out_p)
+
+    print("[bench] timing sorted-pair path", file=sys.stderr, flush=True)
+    ms_sorted, wall_sorted = _time_loop(step_sorted, a.steps, a.warmup, torch)
+    print("[bench] timing plain cell-list path", file=sys.stderr, flush=True)
+    ms_plain, _ = _time_loop(step_plain, a.steps, a.warmup, torch)
+    ctx.check()
+
+    # stage times (events on the stream the library launches on)
+    ctx.build_cells(pos, h, m, s.box, grid, cells)
+    ms_build, _ = _time_loop(lambda: ctx.build_cells(pos, h, m, s.box, grid, cells), a.steps, 1, torch)
+    ms_sort, _ = _time_loop(lambda: ctx.sort_cells(cells), a.steps, 1, torch)
+    ms_sweep, _ = _time_loop(lambda: ctx.density(cells, "sorted", out_s), a.steps, 1, torch)
+    ms_sweep_plain, _ = _time_loop(lambda: ctx.density(cells, "plain", out_p), a.steps, 1, torch)
+    ctx.check()
+
+    n = s.n
+    value = pairs / (ms_sorted * 1e-3)
+    alg_ops = OPS_PER_CANDIDATE * cand_sorted + OPS_PER_INTERACTION * inr
+    achieved = alg_ops / (ms_sweep * 1e-3) / 1e12
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("[bench] timing the fp64 CPU oracle on a sample", file=sys.stderr, flush=True)
+        cpu = _cpu_baseline(s, a.cpu_seconds)
+
+    rec = {
+        "metric": "density pair-interactions/s + ns/particle, sorted-pair vs cell-list, 1 GPU",
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_sorted,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": s.name, "n": n, "grid": list(grid), "seed": s.seed,
+                   "box": list(s.box), "h": "lognormal sigma 0.2 around the 48-neighbour value"
+                   if "lognormal" in s.name else "see workload"},
+        "ns_per_particle": ms_sorted * 1e6 / n,
+        "pairs_in_range": pairs,
+        "plain_cell_list": {"ms_per_step": ms_plain, "value": pairs / (ms_plain * 1e-3),
+                            "ns_per_particle": ms_plain * 1e6 / n,
+                            "sweep_ms": ms_sweep_plain},
+        "speedup_sorted_vs_plain": ms_plain / ms_sorted,
+        "stages_ms": {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep},
+        "candidates_per_particle": {"sorted": cand_sorted / n, "plain": cand_plain / n,
+                                    "in_range": inr / n},
+        "wall_ms_per_step": wall_sorted,
+        "roofline": {"kernel": "k_sweep_sorted", "bound": "alu", "achieved": achieved,
+                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
+                     "traffic": None,
+                     "work": f"{OPS_PER_CANDIDATE} lane-ops per tested pair + "
+                             f"{OPS_PER_INTERACTION} per pair in range"},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec))
+
+
+def _cpu_baseline(s, target_seconds):
+    """fp64 oracle (C + OpenMP cell-list brute force) on a sample of receivers."""
+    from oracle import Oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    o = Oracle(s.pos, s.h, s.m, s.box)
+    rng = np.random.Generator(np.random.PCG64(123))
+    k = 16384
+    while True:
+        idx = np.sort(rng.choice(s.n, min(k, s.n), replace=False))
+        t0 = time.perf_counter()
+        d = o.density(idx)
+        dt = time.perf_counter() - t0
+        if dt > 0.4 * target_seconds or k >= s.n:
+            break
+        k = min(s.n, int(k * max(2.0, 0.5 * target_seconds / max(dt, 1e-3))))
+    pairs = int(d["ncount"].sum())
+    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+            "sample": f"{idx.size} of {s.n} receivers (uniform random), full 27-cell fp64 "
+                      f"brute force, {dt:.2f}s", "ns_per_particle": dt * 1e9 / idx.size}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * pvl.h -- pseudo-Verlet (sorted cell-pair) SPH density loop on AMD gfx950.
+ *
+ * C ABI of libpvl.so.  Every entry point takes plain pointers and sizes; no C++
+ * types or exceptions cross it.  Particle arrays are device pointers owned by
+ * the caller.  Cell structures (pv_cells) and scratch memory are owned by the
+ * library.  All calls are asynchronous on the context's HIP stream unless
+ * stated otherwise.  A context is not thread-safe; use one per host thread.
+ *
+ * What is computed (Willis et al., "An Efficient SIMD Implementation of
+ * Pseudo-Verlet Lists for Neighbour Interactions in Particle-Based Codes"):
+ * the density loop of Fig. 1's caption -- each particle's density as a
+ * kernel-weighted sum over every neighbour closer than its cut-off -- found
+ * with the cell list of Section 2 (cells of edge >= cut-off) and the
+ * pseudo-Verlet pruning of Section 2 / Listing 2 (project both cells on the
+ * axis joining their centres, sort, and test only pairs whose projected
+ * separation is below the receiver's cut-off), with the loop bounds of
+ * Section 3.3 and the cache of Section 3.2.
+ *
+ * Conventions shared by every entry point:
+ *   - h is the SPH smoothing length; the cut-off radius is H = 1.825742 h
+ *     (cubic-spline support in 3D).  The paper's own "h" is this cut-off.
+ *   - W(r, H) = 8 / (pi H^3) w(r/H) with the M4 cubic spline
+ *     w(u) = 1 - 6u^2 + 6u^3 (u < 1/2), 2 (1-u)^3 (1/2 <= u < 1), 0 otherwise.
+ *   - A pair is in range when r_ij < H_i (strict, as in Listings 1-2); the
+ *     receiver's own cut-off decides (gather form).
+ *   - Boxes are periodic with the minimum-image convention; positions may lie
+ *     anywhere and are wrapped into [0, L).
+ *   - Arithmetic is fp32.  Positions are stored relative to their cell's
+ *     origin before any difference is taken (Section 3.2's shift-then-convert,
+ *     with the cell origin in place of the pair centre).
+ */
+#ifndef PVL_H
+#define PVL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pv_ctx pv_ctx;
+typedef struct pv_cells pv_cells;
+
+typedef enum {
+    PV_OK = 0,
+    PV_EINVAL = -1,     /* bad argument (NULL pointer, n < 0, box <= 0, ...)         */
+    PV_ENOMEM = -2,     /* device allocation failed                                  */
+    PV_EHIP = -3,       /* a HIP runtime call failed; pv_last_error has the text      */
+    PV_EGRID = -4,      /* fewer than 3 cells on an axis, or a cell edge < max cut-off */
+    PV_EOVERFLOW = -5,  /* a cell holds more particles than PV_MAX_CELL               */
+    PV_ESTATE = -6      /* call out of order (e.g. density before sort_cells)         */
+} pv_status;
+
+typedef enum {
+    PV_SORTED_PAIR = 0, /* pseudo-Verlet sweep over the 13 sorted axes (Section 2-3)  */
+    PV_PLAIN_CELL = 1   /* plain 27-cell brute force (Listing 1), the comparator       */
+} pv_algo;
+
+/* Largest supported cell occupancy (particles in one cell). */
+#define PV_MAX_CELL 4096
+/* Largest supported number of cells per axis. */
+#define PV_MAX_GRID 1024
+
+/* Create a context on HIP device `device`, issuing work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context.
+ * device = -1 creates an argument-checking context that touches no device:
+ * every entry point validates its arguments as usual and then returns
+ * PV_ESTATE (useful on hosts without a GPU). */
+pv_status pv_create(int device, void *hip_stream, pv_ctx **out);
+
+/* Release the context and its scratch memory.  NULL is accepted. */
+void pv_destroy(pv_ctx *ctx);
+
+/* Change the stream later calls are issued on. */
+pv_status pv_set_stream(pv_ctx *ctx, void *hip_stream);
+
+/* Text of the last error on this context ("" if none).  Owned by the context. */
+const char *pv_last_error(const pv_ctx *ctx);
+
+/* Bin particles into cells (Section 2: the domain is cut into cells of edge
+ * >= the cut-off and each cell's particles are stored together).
+ *
+ *   n         particles in the box, n >= 0
+ *   pos       device, n x 3 fp32, array of structures (x0 y0 z0 x1 ...)
+ *   h         device, n fp32 smoothing lengths (> 0)
+ *   mass      device, n fp32 masses
+ *   box       host, 3 doubles, box edge per axis (> 0)
+ *   grid      host, 3 ints: cells per axis, or NULL / {0,0,0} for the finest
+ *             legal grid floor(L / H_max) (this reads H_max back: one
+ *             stream synchronisation)
+ *   cells     in/out.  *cells == NULL: a new pv_cells is allocated.  Otherwise
+ *             the given one is rebuilt in place, re-using its memory when it is
+ *             large enough (no allocation then, so the call can be captured in a
+ *             HIP graph together with sort_cells and density).
+ *
+ * Errors: PV_EINVAL, PV_EGRID (grid < 3 per axis, > PV_MAX_GRID, or edge below
+ * the largest cut-off -- checked on the host in auto mode, on the device
+ * otherwise and then reported by pv_check), PV_EOVERFLOW (reported by pv_check
+ * or by the auto-grid read-back), PV_ENOMEM, PV_EHIP.
+ * The input arrays are read during the call's kernels only. */
+pv_status pv_build_cells(pv_ctx *ctx, int64_t n, const float *pos, const float *h,
+                         const float *mass, const double box[3], const int grid[3],
+                         pv_cells **cells);
+
+/* Same for nbox independent periodic boxes in one structure.  Box b owns
+ * particles [offsets[b], offsets[b+1]) of the concatenated device arrays.
+ *   offsets   host, nbox + 1 int64, offsets[0] = 0, non-decreasing
+ *   box       host, nbox x 3 doubles
+ *   grid      host, nbox x 3 ints, or NULL for the finest legal grid per box
+ *             (one stream synchronisation) */
+pv_status pv_build_cells_batched(pv_ctx *ctx, int nbox, const int64_t *offsets,
+                                 const float *pos, const float *h, const float *mass,
+                                 const double *box, const int *grid, pv_cells **cells);
+
+/* Sort every cell's particles by their projection on each of the 13 unique
+ * cell-pair axes (Section 2: the dist and index arrays, pre-computed for the 13
+ * directions left once the +-symmetry of the 26 neighbours is used).  Axis s
+ * joins the centres of a cell and its neighbour at offset d_s, where d_s runs
+ * over the offsets in {-1,0,1}^3 whose first non-zero component is positive. */
+pv_status pv_sort_cells(pv_ctx *ctx, pv_cells *cells);
+
+/* Density loop.  Outputs are device arrays of n fp32 (int32 for ncount) in the
+ * caller's original particle order; any of them may be NULL.
+ *   rho       sum_j m_j W(r_ij, H_i) over r_ij < H_i, j = i included
+ *   wcount    sum_j W(r_ij, H_i), j = i included (units of 1 / volume)
+ *   drho_dh   d rho_i / d h_i = -8/(pi H_i^3 h_i) sum_j m_j [3 w(u) + u w'(u)]
+ *   ncount    #{ j != i : r_ij < H_i }
+ * PV_SORTED_PAIR needs pv_sort_cells first (else PV_ESTATE). */
+pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rho,
+                     float *wcount, float *drho_dh, int32_t *ncount);
+
+/* Adjoint of rho: given grad_rho = dL/drho (device, n fp32, original order),
+ * write grad_pos = dL/dx (device, n x 3 fp32) and grad_h = dL/dh (device, n
+ * fp32), either may be NULL:
+ *   dL/dh_k = G_k drho_dh_k
+ *   dL/dx_k = sum_{j != k} [G_k m_j W_r(r_kj, H_k) + G_j m_k W_r(r_kj, H_j)]
+ *             (x_k - x_j) / r_kj,   W_r = 8 / (pi H^4) w'(r/H),
+ * i.e. the pair set is the union r < max(H_k, H_j).  Uses the sorted lists
+ * (pv_sort_cells first).  Masses are treated as constants. */
+pv_status pv_density_backward(pv_ctx *ctx, const pv_cells *cells, const float *grad_rho,
+                              float *grad_pos, float *grad_h);
+
+/* Synchronise the context's stream and report device-detected errors
+ * (PV_EOVERFLOW, PV_EGRID) raised since the last check. */
+pv_status pv_check(pv_ctx *ctx);
+
+/* Describe a cell structure (host outputs, any may be NULL; box 0 for grid).
+ * max_occupancy and hmax need a synchronisation. */
+pv_status pv_cells_info(pv_ctx *ctx, const pv_cells *cells, int grid[3], int64_t *ncell,
+                        int32_t *max_occupancy, float *hmax, int *nbox, int64_t *n);
+
+/* Copy the cell-ordered layout to caller device buffers (tests and tools):
+ * cell_start (ncell + 1 int32), order (n int32: original index of each
+ * cell-ordered slot), sorted (13 x n uint16: in-cell rank lists per axis).
+ * Any may be NULL. */
+pv_status pv_cells_export(pv_ctx *ctx, const pv_cells *cells, int32_t *cell_start,
+                          int32_t *order, uint16_t *sorted);
+
+/* Candidate census of the last pv_density call made with census enabled:
+ * counts[0] = pairs tested by the distance check, counts[1] = pairs in range
+ * (non-self).  pv_set_census(ctx, 1) enables counting (slower). */
+pv_status pv_set_census(pv_ctx *ctx, int enable);
+pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
+
+/* Release a cell structure.  NULL is accepted. */
+pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PVL_H */

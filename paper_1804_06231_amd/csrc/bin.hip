@@ -1,0 +1,221 @@
+// Cell binning: a counting sort of the particles into the cells of each box
+// (Section 2 of the paper: cells of edge >= the cut-off, each cell's particles
+// stored together), finished by a per-cell sort on the original index so that
+// the cell-ordered layout does not depend on atomic arrival order.
+//
+//   k_box_hmax    max cut-off per box (auto grid)
+//   k_bin_count   cell of every particle, per-cell counts and max cut-off
+//   k_scan        exclusive scan of the counts -> cell_start; occupancy check
+//   k_scatter     particles -> scatter-ordered staging records
+//   k_cell_finish per cell: order by original index, shift positions to the
+//                 cell origin, write the cell-ordered structure of arrays
+#include "device_util.h"
+
+namespace pvl {
+
+__global__ void k_box_hmax(const BoxDesc *__restrict__ box, int nbox, int64_t n,
+                           const float *__restrict__ h, uint32_t *__restrict__ box_hmax)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t v = 0;
+    int b = -1;
+    if (p < n) {
+        b = box_of_particle(box, nbox, p);
+        v = __float_as_uint(kGamma * h[p]);
+    }
+    // reduce within the wavefront when every lane has the same box
+    int b0 = __shfl(b, 0);
+    bool same = __all(b == b0);
+    if (same) {
+        for (int off = 32; off > 0; off >>= 1) {
+            uint32_t o = __shfl_xor(v, off);
+            v = v > o ? v : o;
+        }
+        if ((threadIdx.x & 63) == 0 && b0 >= 0) atomicMax(&box_hmax[b0], v);
+    } else if (b >= 0) {
+        atomicMax(&box_hmax[b], v);
+    }
+}
+
+__global__ void k_bin_count(const BoxDesc *__restrict__ box, int nbox, int64_t n,
+                            const float *__restrict__ pos, const float *__restrict__ h,
+                            int32_t *__restrict__ cellid, int32_t *__restrict__ count,
+                            uint32_t *__restrict__ cell_hmax, int *__restrict__ dflags)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const BoxDesc &B = box[box_of_particle(box, nbox, p)];
+    float x = wrap_coord(pos[3 * p + 0], B.L[0], 1.0f / B.L[0]);
+    float y = wrap_coord(pos[3 * p + 1], B.L[1], 1.0f / B.L[1]);
+    float z = wrap_coord(pos[3 * p + 2], B.L[2], 1.0f / B.L[2]);
+    int cx = cell_coord(x, B.inv_edge[0], B.g[0]);
+    int cy = cell_coord(y, B.inv_edge[1], B.g[1]);
+    int cz = cell_coord(z, B.inv_edge[2], B.g[2]);
+    int c = B.cell_off + (cx * B.g[1] + cy) * B.g[2] + cz;
+    cellid[p] = c;
+    atomicAdd(&count[c], 1);
+    float H = kGamma * h[p];
+    atomicMax(&cell_hmax[c], __float_as_uint(H));
+    float emin = fminf(B.edge[0], fminf(B.edge[1], B.edge[2]));
+    if (!(H <= emin) || !(H > 0.0f)) atomicOr(dflags, kErrGrid);
+}
+
+// Single workgroup: exclusive scan of count[0..ncell) into start[0..ncell],
+// counts reset to zero (they become scatter cursors), largest count into
+// dflags[1], overflow flagged.
+__global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restrict__ count,
+                                                int32_t *__restrict__ start,
+                                                int *__restrict__ dflags)
+{
+    __shared__ int32_t part[1024];
+    const int T = blockDim.x;
+    int64_t chunk = (ncell + T - 1) / T;
+    int64_t b = threadIdx.x * chunk;
+    int64_t e = b + chunk < ncell ? b + chunk : ncell;
+    int32_t sum = 0, mx = 0;
+    for (int64_t c = b; c < e; ++c) {
+        int32_t v = count[c];
+        sum += v;
+        mx = v > mx ? v : mx;
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan over the thread sums
+    for (int off = 1; off < T; off <<= 1) {
+        int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int32_t run = part[threadIdx.x] - sum;
+    for (int64_t c = b; c < e; ++c) {
+        int32_t v = count[c];
+        start[c] = run;
+        run += v;
+        count[c] = 0;
+    }
+    if (threadIdx.x == T - 1) start[ncell] = part[T - 1];
+    for (int off = 32; off > 0; off >>= 1) {
+        int32_t o = __shfl_xor(mx, off);
+        mx = mx > o ? mx : o;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&dflags[1], mx);
+        if (mx > PV_MAX_CELL) atomicOr(&dflags[0], kErrOverflow);
+    }
+}
+
+__global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n,
+                          const float *__restrict__ pos, const float *__restrict__ h,
+                          const float *__restrict__ mass, const int32_t *__restrict__ cellid,
+                          const int32_t *__restrict__ start, int32_t *__restrict__ cursor,
+                          float4 *__restrict__ stage, float2 *__restrict__ stage2)
+{
+    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const BoxDesc &B = box[box_of_particle(box, nbox, p)];
+    float x = wrap_coord(pos[3 * p + 0], B.L[0], 1.0f / B.L[0]);
+    float y = wrap_coord(pos[3 * p + 1], B.L[1], 1.0f / B.L[1]);
+    float z = wrap_coord(pos[3 * p + 2], B.L[2], 1.0f / B.L[2]);
+    int c = cellid[p];
+    int slot = start[c] + atomicAdd(&cursor[c], 1);
+    stage[slot] = make_float4(x, y, z, kGamma * h[p]);
+    stage2[slot] = make_float2(mass[p], __int_as_float((int)p));
+}
+
+// One workgroup per cell.
+__global__ void __launch_bounds__(kBlock) k_cell_finish(
+    const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
+    const int32_t *__restrict__ start, const float4 *__restrict__ stage,
+    const float2 *__restrict__ stage2, float4 *__restrict__ xyzm, float *__restrict__ Hout,
+    int32_t *__restrict__ orig)
+{
+    __shared__ uint64_t keys[PV_MAX_CELL];
+    const int c = blockIdx.x;
+    const int s0 = start[c];
+    const int cnt = start[c + 1] - s0;
+    if (cnt <= 0 || cnt > PV_MAX_CELL) return;
+    const BoxDesc &B = box[cell_box[c]];
+    int local = c - B.cell_off;
+    int cz = local % B.g[2];
+    int cy = (local / B.g[2]) % B.g[1];
+    int cx = local / (B.g[2] * B.g[1]);
+    float ox = (float)cx * B.edge[0], oy = (float)cy * B.edge[1], oz = (float)cz * B.edge[2];
+    int P2 = next_pow2(cnt);
+    for (int r = threadIdx.x; r < P2; r += blockDim.x) {
+        uint64_t k = ~0ull;
+        if (r < cnt) {
+            uint32_t o = (uint32_t)__float_as_int(stage2[s0 + r].y);
+            k = ((uint64_t)o << 32) | (uint32_t)r;
+        }
+        keys[r] = k;
+    }
+    __syncthreads();
+    bitonic_sort_segments(keys, P2, 1);
+    for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+        int slot = s0 + (int)(keys[r] & 0xffffffffu);
+        float4 a = stage[slot];
+        float2 b = stage2[slot];
+        xyzm[s0 + r] = make_float4(a.x - ox, a.y - oy, a.z - oz, b.x);
+        Hout[s0 + r] = a.w;
+        orig[s0 + r] = __float_as_int(b.y);
+    }
+}
+
+__global__ void k_cell_box(const BoxDesc *__restrict__ box, int nbox, int64_t ncell,
+                           int32_t *__restrict__ cell_box)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    int lo = 0, hi = nbox - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (box[mid].cell_off <= c) lo = mid; else hi = mid - 1;
+    }
+    cell_box[c] = lo;
+}
+
+__global__ void k_zero(uint32_t *__restrict__ p, int64_t words)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < words) p[i] = 0u;
+}
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_zero(hipStream_t st, void *p, int64_t words)
+{
+    if (words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3(blocks_for(words, 256)), dim3(256), 0, st, (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_box_hmax(hipStream_t st, const DevCells &c, int nbox, int64_t n,
+                           const float *h)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_box_hmax, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox, n,
+                       h, c.box_hmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin(hipStream_t st, const DevCells &c, int nbox, int64_t n, int64_t ncell,
+                      const float *pos, const float *h, const float *mass, int *dflags)
+{
+    hipLaunchKernelGGL(k_cell_box, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box, nbox,
+                       ncell, c.cell_box);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox,
+                           n, pos, h, c.cellid, c.cursor, c.cell_hmax, dflags);
+    }
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncell, c.cursor, c.cell_start, dflags);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox, n,
+                           pos, h, mass, c.cellid, c.cell_start, c.cursor, c.stage, c.stage2);
+        hipLaunchKernelGGL(k_cell_finish, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                           c.cell_box, c.cell_start, c.stage, c.stage2, c.xyzm, c.H, c.orig);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pvl

@@ -1,0 +1,474 @@
+// Host side of the C ABI declared in include/pvl.h: argument checks, grid
+// choice, memory of the cell structures, kernel launches on the context's
+// stream, error reporting.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "pvl_internal.h"
+
+using pvl::BoxDesc;
+using pvl::DevCells;
+
+struct pv_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    int *dflags = nullptr;                  // [0] sticky error bits, [1] max occupancy
+    unsigned long long *dcensus = nullptr;  // [0] pairs tested, [1] pairs in range
+    int census_on = 0;
+    int *hpinned = nullptr;                 // pinned read-back area (64 bytes)
+};
+
+struct pv_cells {
+    int nbox = 0;
+    int64_t n = 0;
+    int64_t ncell = 0;
+    std::vector<BoxDesc> hbox;
+    std::vector<BoxDesc> uploaded;  // what d.box currently holds
+    DevCells d;
+    int64_t cap_n = 0, cap_cell = 0, cap_box = 0;
+    bool sorted = false;
+};
+
+namespace {
+
+pv_status fail(pv_ctx *ctx, pv_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                               \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail((ctx), PV_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+template <class T>
+hipError_t dev_alloc(T **p, int64_t count)
+{
+    *p = nullptr;
+    if (count <= 0) count = 1;
+    return hipMalloc((void **)p, sizeof(T) * (size_t)count);
+}
+
+void free_dev(DevCells &d)
+{
+    void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cursor, d.cellid, d.stage,
+                    d.stage2, d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax};
+    for (void *p : ptrs)
+        if (p) (void)hipFree(p);
+    d = DevCells();
+}
+
+pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, int nbox)
+{
+    if (n <= c->cap_n && ncell <= c->cap_cell && nbox <= c->cap_box) return PV_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    free_dev(c->d);
+    c->uploaded.clear();
+    int64_t N = std::max<int64_t>(n, c->cap_n), C = std::max<int64_t>(ncell, c->cap_cell);
+    int64_t Bx = std::max<int64_t>(nbox, c->cap_box);
+    DevCells &d = c->d;
+    hipError_t e = hipSuccess;
+#define ALLOC(ptr, cnt) if (e == hipSuccess) e = dev_alloc(&ptr, cnt)
+    ALLOC(d.box, Bx);
+    ALLOC(d.box_hmax, Bx);
+    ALLOC(d.cell_box, C);
+    ALLOC(d.cell_start, C + 1);
+    ALLOC(d.cell_hmax, C);
+    ALLOC(d.cursor, C);
+    ALLOC(d.cellid, N);
+    ALLOC(d.stage, N);
+    ALLOC(d.stage2, N);
+    ALLOC(d.xyzm, N);
+    ALLOC(d.H, N);
+    ALLOC(d.orig, N);
+    ALLOC(d.sidx, 13 * N);
+    ALLOC(d.skey, 13 * N);
+    ALLOC(d.gcell, N);
+#undef ALLOC
+    if (e != hipSuccess) {
+        free_dev(c->d);
+        c->cap_n = c->cap_cell = c->cap_box = 0;
+        return fail(ctx, PV_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
+    c->cap_n = N;
+    c->cap_cell = C;
+    c->cap_box = Bx;
+    return PV_OK;
+}
+
+bool boxes_equal(const std::vector<BoxDesc> &a, const std::vector<BoxDesc> &b)
+{
+    return a.size() == b.size() && (a.empty() || memcmp(a.data(), b.data(), sizeof(BoxDesc) * a.size()) == 0);
+}
+
+pv_status upload_boxes(pv_ctx *ctx, pv_cells *c)
+{
+    if (boxes_equal(c->hbox, c->uploaded)) return PV_OK;
+    HIPCHK(ctx, hipMemcpyAsync(c->d.box, c->hbox.data(), sizeof(BoxDesc) * c->hbox.size(),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    c->uploaded = c->hbox;
+    return PV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pv_status pv_create(int device, void *hip_stream, pv_ctx **out)
+{
+    if (!out) return PV_EINVAL;
+    *out = nullptr;
+    if (device == -1) {
+        // argument-checking context: every entry point validates its
+        // arguments and then returns PV_ESTATE instead of touching a device
+        pv_ctx *ctx = new pv_ctx();
+        ctx->device = -1;
+        *out = ctx;
+        return PV_OK;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return PV_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return PV_EHIP;
+    pv_ctx *ctx = new pv_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipMalloc((void **)&ctx->dflags, 4 * sizeof(int)) != hipSuccess ||
+        hipMalloc((void **)&ctx->dcensus, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->hpinned, 64, hipHostMallocDefault) != hipSuccess) {
+        pv_destroy(ctx);
+        return PV_ENOMEM;
+    }
+    if (hipMemset(ctx->dflags, 0, 4 * sizeof(int)) != hipSuccess ||
+        hipMemset(ctx->dcensus, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        pv_destroy(ctx);
+        return PV_EHIP;
+    }
+    *out = ctx;
+    return PV_OK;
+}
+
+void pv_destroy(pv_ctx *ctx)
+{
+    if (!ctx) return;
+    if (ctx->device < 0) {
+        delete ctx;
+        return;
+    }
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    if (ctx->dflags) (void)hipFree(ctx->dflags);
+    if (ctx->dcensus) (void)hipFree(ctx->dcensus);
+    if (ctx->hpinned) (void)hipHostFree(ctx->hpinned);
+    delete ctx;
+}
+
+pv_status pv_set_stream(pv_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return PV_EINVAL;
+    ctx->stream = (hipStream_t)hip_stream;
+    return PV_OK;
+}
+
+const char *pv_last_error(const pv_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+pv_status pv_build_cells_batched(pv_ctx *ctx, int nbox, const int64_t *offsets,
+                                 const float *pos, const float *h, const float *mass,
+                                 const double *box, const int *grid, pv_cells **cells)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (nbox < 1) return fail(ctx, PV_EINVAL, "nbox < 1");
+    if (!offsets || !box) return fail(ctx, PV_EINVAL, "offsets or box is NULL");
+    if (offsets[0] != 0) return fail(ctx, PV_EINVAL, "offsets[0] != 0");
+    for (int b = 0; b < nbox; ++b)
+        if (offsets[b + 1] < offsets[b]) return fail(ctx, PV_EINVAL, "offsets decrease");
+    const int64_t n = offsets[nbox];
+    if (n > 0x7fffffffLL) return fail(ctx, PV_EINVAL, "more than 2^31-1 particles");
+    if (n > 0 && (!pos || !h || !mass)) return fail(ctx, PV_EINVAL, "NULL particle array");
+    for (int b = 0; b < 3 * nbox; ++b)
+        if (!(box[b] > 0.0) || !isfinite(box[b])) return fail(ctx, PV_EINVAL, "box edge <= 0");
+    bool autogrid = (grid == nullptr);
+    if (!autogrid) {
+        bool allzero = true;
+        for (int b = 0; b < 3 * nbox; ++b) allzero &= (grid[b] == 0);
+        autogrid = allzero;
+    }
+    if (!autogrid)
+        for (int b = 0; b < 3 * nbox; ++b)
+            if (grid[b] < 3 || grid[b] > PV_MAX_GRID)
+                return fail(ctx, PV_EGRID, "grid must have 3.." + std::to_string(PV_MAX_GRID) +
+                                               " cells per axis");
+
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    pv_cells *c = *cells;
+    bool fresh = (c == nullptr);
+    if (fresh) c = new pv_cells();
+    c->hbox.assign(nbox, BoxDesc());
+    for (int b = 0; b < nbox; ++b) {
+        BoxDesc &B = c->hbox[b];
+        for (int a = 0; a < 3; ++a) {
+            B.L[a] = (float)box[3 * b + a];
+            B.g[a] = 3;
+        }
+        B.part_off = (int)offsets[b];
+        B.n = (int)(offsets[b + 1] - offsets[b]);
+    }
+    // cell counts are needed to size memory; with an auto grid the largest
+    // cut-off of every box is read back first
+    std::vector<int> g(3 * nbox);
+    if (!autogrid) {
+        for (int b = 0; b < 3 * nbox; ++b) g[b] = grid[b];
+    }
+    auto ncell_of = [&](const std::vector<int> &gg) {
+        int64_t t = 0;
+        for (int b = 0; b < nbox; ++b) t += (int64_t)gg[3 * b] * gg[3 * b + 1] * gg[3 * b + 2];
+        return t;
+    };
+    pv_status st;
+    if (autogrid) {
+        st = ensure_capacity(ctx, c, n, std::max<int64_t>(c->cap_cell, 27 * nbox), nbox);
+        if (st != PV_OK) { if (fresh) { pv_free_cells(ctx, c); } return st; }
+        c->n = n;
+        if ((st = upload_boxes(ctx, c)) != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
+        hipError_t e = pvl::launch_zero(ctx->stream, c->d.box_hmax, nbox);
+        if (e == hipSuccess) e = pvl::launch_box_hmax(ctx->stream, c->d, nbox, n, h);
+        std::vector<uint32_t> hm(nbox);
+        if (e == hipSuccess) e = hipMemcpyAsync(hm.data(), c->d.box_hmax, sizeof(uint32_t) * nbox,
+                                                hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            if (fresh) pv_free_cells(ctx, c);
+            return fail(ctx, PV_EHIP, std::string("H_max read-back: ") + hipGetErrorString(e));
+        }
+        for (int b = 0; b < nbox; ++b) {
+            float Hm;
+            memcpy(&Hm, &hm[b], 4);
+            if (!(Hm >= 0.0f) || !isfinite(Hm)) {
+                if (fresh) pv_free_cells(ctx, c);
+                return fail(ctx, PV_EINVAL, "non-finite or negative h");
+            }
+            for (int a = 0; a < 3; ++a) {
+                double L = box[3 * b + a];
+                int64_t gg = Hm > 0.0f ? (int64_t)floor(L / ((double)Hm * (1.0 + 4e-6))) : PV_MAX_GRID;
+                if (gg > PV_MAX_GRID) gg = PV_MAX_GRID;
+                if (gg < 3) {
+                    if (fresh) pv_free_cells(ctx, c);
+                    return fail(ctx, PV_EGRID, "box " + std::to_string(b) +
+                                                   ": largest cut-off leaves fewer than 3 cells per axis");
+                }
+                g[3 * b + a] = (int)gg;
+            }
+        }
+    }
+    const int64_t ncell = ncell_of(g);
+    if (ncell > 0x7fffffffLL / 2) {
+        if (fresh) pv_free_cells(ctx, c);
+        return fail(ctx, PV_EGRID, "too many cells");
+    }
+    int coff = 0;
+    for (int b = 0; b < nbox; ++b) {
+        BoxDesc &B = c->hbox[b];
+        for (int a = 0; a < 3; ++a) {
+            B.g[a] = g[3 * b + a];
+            double L = box[3 * b + a];
+            B.edge[a] = (float)(L / B.g[a]);
+            B.inv_edge[a] = (float)(B.g[a] / L);
+        }
+        B.cell_off = coff;
+        coff += B.g[0] * B.g[1] * B.g[2];
+    }
+    st = ensure_capacity(ctx, c, n, ncell, nbox);
+    if (st != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
+    c->nbox = nbox;
+    c->n = n;
+    c->ncell = ncell;
+    c->sorted = false;
+    if ((st = upload_boxes(ctx, c)) != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
+    hipError_t e = pvl::launch_zero(ctx->stream, c->d.cursor, ncell);
+    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, c->d.cell_hmax, ncell);
+    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, ctx->dflags + 1, 1);
+    if (e == hipSuccess) e = pvl::launch_bin(ctx->stream, c->d, nbox, n, ncell, pos, h, mass, ctx->dflags);
+    if (e != hipSuccess) {
+        if (fresh) pv_free_cells(ctx, c);
+        return fail(ctx, PV_EHIP, std::string("binning launch: ") + hipGetErrorString(e));
+    }
+    if (autogrid) {
+        // the auto path synchronises anyway: report occupancy overflow now
+        e = hipMemcpyAsync(ctx->hpinned, ctx->dflags, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                           ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            if (fresh) pv_free_cells(ctx, c);
+            return fail(ctx, PV_EHIP, std::string("occupancy read-back: ") + hipGetErrorString(e));
+        }
+        if (ctx->hpinned[0] & pvl::kErrOverflow) {
+            // reported here, so cleared from the sticky flags
+            e = pvl::launch_zero(ctx->stream, ctx->dflags, 1);
+            if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+            *cells = c;
+            return fail(ctx, PV_EOVERFLOW, "a cell holds " + std::to_string(ctx->hpinned[1]) +
+                                               " particles (max " + std::to_string(PV_MAX_CELL) + ")");
+        }
+    }
+    *cells = c;
+    ctx->err.clear();
+    return PV_OK;
+}
+
+pv_status pv_build_cells(pv_ctx *ctx, int64_t n, const float *pos, const float *h,
+                         const float *mass, const double box[3], const int grid[3],
+                         pv_cells **cells)
+{
+    if (!ctx) return PV_EINVAL;
+    if (n < 0) return fail(ctx, PV_EINVAL, "n < 0");
+    int64_t off[2] = {0, n};
+    return pv_build_cells_batched(ctx, 1, off, pos, h, mass, box, grid, cells);
+}
+
+pv_status pv_sort_cells(pv_ctx *ctx, pv_cells *cells)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    HIPCHK(ctx, pvl::launch_sort13(ctx->stream, cells->d, cells->n, cells->ncell));
+    cells->sorted = true;
+    return PV_OK;
+}
+
+pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rho,
+                     float *wcount, float *drho_dh, int32_t *ncount)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (algo != PV_SORTED_PAIR && algo != PV_PLAIN_CELL) return fail(ctx, PV_EINVAL, "bad algo");
+    if (algo == PV_SORTED_PAIR && !cells->sorted)
+        return fail(ctx, PV_ESTATE, "pv_sort_cells must run before a sorted-pair density");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    if (ctx->census_on) HIPCHK(ctx, pvl::launch_zero(ctx->stream, ctx->dcensus, 4));
+    HIPCHK(ctx, pvl::launch_sweep(ctx->stream, cells->d, cells->n, cells->ncell, (int)algo, rho,
+                                  wcount, drho_dh, ncount, ctx->dflags,
+                                  ctx->census_on ? ctx->dcensus : nullptr));
+    return PV_OK;
+}
+
+pv_status pv_density_backward(pv_ctx *ctx, const pv_cells *cells, const float *grad_rho,
+                              float *grad_pos, float *grad_h)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (!grad_rho && cells->n > 0) return fail(ctx, PV_EINVAL, "grad_rho is NULL");
+    if (!cells->sorted) return fail(ctx, PV_ESTATE, "pv_sort_cells must run before the adjoint");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    HIPCHK(ctx, pvl::launch_backward(ctx->stream, cells->d, cells->n, cells->ncell, grad_rho,
+                                     grad_pos, grad_h, ctx->dflags));
+    return PV_OK;
+}
+
+pv_status pv_check(pv_ctx *ctx)
+{
+    if (!ctx) return PV_EINVAL;
+    if (ctx->device < 0) return PV_OK;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hpinned, ctx->dflags, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    int bits = ctx->hpinned[0];
+    if (bits) {
+        HIPCHK(ctx, pvl::launch_zero(ctx->stream, ctx->dflags, 1));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (bits & pvl::kErrOverflow)
+            return fail(ctx, PV_EOVERFLOW, "a cell held " + std::to_string(ctx->hpinned[1]) +
+                                               " particles (max " + std::to_string(PV_MAX_CELL) + ")");
+        return fail(ctx, PV_EGRID, "a cut-off exceeded the cell edge (grid too fine) or h <= 0");
+    }
+    return PV_OK;
+}
+
+pv_status pv_cells_info(pv_ctx *ctx, const pv_cells *cells, int grid[3], int64_t *ncell,
+                        int32_t *max_occupancy, float *hmax, int *nbox, int64_t *n)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (grid)
+        for (int a = 0; a < 3; ++a) grid[a] = cells->hbox.empty() ? 0 : cells->hbox[0].g[a];
+    if (ncell) *ncell = cells->ncell;
+    if (nbox) *nbox = cells->nbox;
+    if (n) *n = cells->n;
+    if (max_occupancy || hmax) {
+        HIPCHK(ctx, hipMemcpyAsync(ctx->hpinned, ctx->dflags, 2 * sizeof(int),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (max_occupancy) *max_occupancy = ctx->hpinned[1];
+        if (hmax) {
+            std::vector<uint32_t> v((size_t)std::max<int64_t>(cells->ncell, 1));
+            if (cells->ncell > 0)
+                HIPCHK(ctx, hipMemcpy(v.data(), cells->d.cell_hmax, sizeof(uint32_t) * cells->ncell,
+                                      hipMemcpyDeviceToHost));
+            uint32_t m = 0;
+            for (int64_t i = 0; i < cells->ncell; ++i) m = std::max(m, v[i]);
+            float f;
+            memcpy(&f, &m, 4);
+            *hmax = f;
+        }
+    }
+    return PV_OK;
+}
+
+pv_status pv_cells_export(pv_ctx *ctx, const pv_cells *cells, int32_t *cell_start,
+                          int32_t *order, uint16_t *sorted)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (cell_start)
+        HIPCHK(ctx, hipMemcpyAsync(cell_start, cells->d.cell_start, sizeof(int32_t) * (cells->ncell + 1),
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    if (order && cells->n > 0)
+        HIPCHK(ctx, hipMemcpyAsync(order, cells->d.orig, sizeof(int32_t) * cells->n,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    if (sorted && cells->n > 0) {
+        if (!cells->sorted) return fail(ctx, PV_ESTATE, "cells are not sorted");
+        HIPCHK(ctx, hipMemcpyAsync(sorted, cells->d.sidx, sizeof(uint16_t) * 13 * cells->n,
+                                   hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    return PV_OK;
+}
+
+pv_status pv_set_census(pv_ctx *ctx, int enable)
+{
+    if (!ctx) return PV_EINVAL;
+    ctx->census_on = enable ? 1 : 0;
+    return PV_OK;
+}
+
+pv_status pv_census(pv_ctx *ctx, int64_t counts[2])
+{
+    if (!ctx || !counts) return PV_EINVAL;
+    unsigned long long v[2];
+    HIPCHK(ctx, hipMemcpyAsync(v, ctx->dcensus, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    counts[0] = (int64_t)v[0];
+    counts[1] = (int64_t)v[1];
+    return PV_OK;
+}
+
+pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells)
+{
+    if (!cells) return PV_OK;
+    if (ctx && ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    else (void)hipDeviceSynchronize();
+    free_dev(cells->d);
+    delete cells;
+    return PV_OK;
+}
+
+}  // extern "C"

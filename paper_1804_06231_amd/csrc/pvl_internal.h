@@ -1,0 +1,104 @@
+// Internal declarations shared by the libpvl translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pvl.h"
+
+namespace pvl {
+
+// Cut-off over smoothing length of the cubic spline in 3D (H = GAMMA h).
+constexpr float kGamma = 1.825742f;
+constexpr float kPi = 3.14159265358979f;
+// Threads per workgroup of the per-cell kernels.
+constexpr int kBlock = 256;
+// Device error bits.
+constexpr int kErrOverflow = 1;
+constexpr int kErrGrid = 2;
+
+// One periodic box of a (possibly batched) cell structure, as the kernels see it.
+struct BoxDesc {
+    float L[3];         // box edge per axis
+    float edge[3];      // cell edge L / g (fp32)
+    float inv_edge[3];  // g / L
+    int g[3];           // cells per axis
+    int cell_off;       // first global cell of this box
+    int part_off;       // first particle of this box (input and cell order)
+    int n;              // particles in the box
+    int pad;
+};
+
+// The 13 canonical cell offsets: those d in {-1,0,1}^3 \ 0 whose first
+// non-zero component is positive.  A neighbour at offset d uses axis s with
+// d_s = +d or d_s = -d.
+__host__ __device__ inline void dir_offset(int s, int d[3])
+{
+    // s = 0..8: x = +1, (y, z) in {-1,0,1}^2; s = 9..11: x = 0, y = +1, z in {-1,0,1};
+    // s = 12: (0, 0, 1)
+    if (s < 9) { d[0] = 1; d[1] = s / 3 - 1; d[2] = s % 3 - 1; }
+    else if (s < 12) { d[0] = 0; d[1] = 1; d[2] = s - 10; }
+    else { d[0] = 0; d[1] = 0; d[2] = 1; }
+}
+
+// Map an offset d != 0 to (axis s, sign): d = sign * d_s.
+__host__ __device__ inline int dir_canon(int dx, int dy, int dz, int *sign)
+{
+    int sx = dx, sy = dy, sz = dz;
+    int sg = 1;
+    if (dx < 0 || (dx == 0 && (dy < 0 || (dy == 0 && dz < 0)))) {
+        sx = -dx; sy = -dy; sz = -dz; sg = -1;
+    }
+    *sign = sg;
+    if (sx == 1) return (sy + 1) * 3 + (sz + 1);
+    if (sy == 1) return 10 + sz;
+    return 12;
+}
+
+// Unit axis of direction s: d_s / |d_s|.
+__host__ __device__ inline void dir_axis(int s, float e[3])
+{
+    int d[3];
+    dir_offset(s, d);
+    int nz = (d[0] != 0) + (d[1] != 0) + (d[2] != 0);
+    float inv = nz == 1 ? 1.0f : (nz == 2 ? 0.70710678118654752f : 0.57735026918962576f);
+    e[0] = d[0] * inv; e[1] = d[1] * inv; e[2] = d[2] * inv;
+}
+
+// Device-side buffers of one cell structure.
+struct DevCells {
+    BoxDesc *box = nullptr;       // nbox
+    int32_t *cell_box = nullptr;  // ncell: owning box
+    int32_t *cell_start = nullptr;// ncell + 1: first slot (global, cell order)
+    uint32_t *cell_hmax = nullptr;// ncell: max cut-off in the cell (fp32 bits)
+    int32_t *cursor = nullptr;    // ncell: scatter cursors / counts
+    int32_t *cellid = nullptr;    // n: global cell of each input particle
+    float4 *stage = nullptr;      // n: (x, y, z, H) wrapped, in scatter order
+    float2 *stage2 = nullptr;     // n: (m, original index as bits)
+    float4 *xyzm = nullptr;       // n: cell-relative position and mass
+    float *H = nullptr;           // n: cut-off radius
+    int32_t *orig = nullptr;      // n: original index
+    uint16_t *sidx = nullptr;     // 13 x n: in-cell rank lists, ascending key
+    float *skey = nullptr;        // 13 x n: the keys in that order
+    float *gcell = nullptr;       // n: upstream gradient in cell order (adjoint)
+    uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
+};
+
+// Launch wrappers (each lives next to its kernels).
+hipError_t launch_box_hmax(hipStream_t st, const DevCells &c, int nbox, int64_t n,
+                           const float *h);
+hipError_t launch_bin(hipStream_t st, const DevCells &c, int nbox, int64_t n, int64_t ncell,
+                      const float *pos, const float *h, const float *mass, int *dflags);
+hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell);
+hipError_t launch_zero(hipStream_t st, void *p, int64_t words);
+hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
+                        float *rho, float *wcount, float *drho_dh, int32_t *ncount,
+                        const int *dflags, unsigned long long *census);
+hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                           const float *grad_rho, float *grad_pos, float *grad_h,
+                           const int *dflags);
+
+}  // namespace pvl

@@ -1,0 +1,316 @@
+"""ctypes binding of libpvl.so (include/pvl.h).
+
+Argument marshalling only: every step of the density loop runs in the HIP
+library.  PyTorch provides device memory and the stream; tensors must be
+contiguous fp32 (int32 for counts) on the context's GPU.  If the library is
+not built, loading fails with an error -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpvl.so")
+
+PV_OK, PV_EINVAL, PV_ENOMEM, PV_EHIP, PV_EGRID, PV_EOVERFLOW, PV_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PV_SORTED_PAIR, PV_PLAIN_CELL = 0, 1
+PV_MAX_CELL = 4096
+PV_MAX_GRID = 1024
+ALGOS = {"sorted": PV_SORTED_PAIR, "plain": PV_PLAIN_CELL}
+
+# every symbol the header declares (checked by the CPU tests)
+EXPORTS = (
+    "pv_create", "pv_destroy", "pv_set_stream", "pv_last_error", "pv_build_cells",
+    "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
+    "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
+    "pv_free_cells",
+)
+
+_STATUS = {
+    PV_EINVAL: "PV_EINVAL", PV_ENOMEM: "PV_ENOMEM", PV_EHIP: "PV_EHIP",
+    PV_EGRID: "PV_EGRID", PV_EOVERFLOW: "PV_EOVERFLOW", PV_ESTATE: "PV_ESTATE",
+}
+
+
+class PVError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpvl.so and declare its signatures.  Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libpvl.so not found at {path}: build it with "
+                           "`python -m paper_1804_06231_amd.build`")
+    lib = C.CDLL(path)
+    P, i32, i64 = C.c_void_p, C.c_int, C.c_int64
+    sig = {
+        "pv_create": ([i32, P, P], i32),
+        "pv_destroy": ([P], None),
+        "pv_set_stream": ([P, P], i32),
+        "pv_last_error": ([P], C.c_char_p),
+        "pv_build_cells": ([P, i64, P, P, P, P, P, P], i32),
+        "pv_build_cells_batched": ([P, i32, P, P, P, P, P, P, P], i32),
+        "pv_sort_cells": ([P, P], i32),
+        "pv_density": ([P, P, i32, P, P, P, P], i32),
+        "pv_density_backward": ([P, P, P, P, P], i32),
+        "pv_check": ([P], i32),
+        "pv_cells_info": ([P, P, P, P, P, P, P, P], i32),
+        "pv_cells_export": ([P, P, P, P, P], i32),
+        "pv_set_census": ([P, i32], i32),
+        "pv_census": ([P, P], i32),
+        "pv_free_cells": ([P, P], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, n, cols, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32")
+    shape = (n, cols) if cols else (n,)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Cells:
+    """A pv_cells handle (library-owned device memory)."""
+
+    def __init__(self, ctx: "Context", handle, n: int, nbox: int):
+        self.ctx = ctx
+        self.handle = handle
+        self.n = n
+        self.nbox = nbox
+        self.sorted = False
+
+    def info(self):
+        g = (C.c_int * 3)()
+        nc = C.c_int64()
+        occ = C.c_int32()
+        hm = C.c_float()
+        nb = C.c_int()
+        n = C.c_int64()
+        self.ctx._call("pv_cells_info", self.handle, g, C.byref(nc), C.byref(occ), C.byref(hm),
+                       C.byref(nb), C.byref(n))
+        return dict(grid=tuple(g), ncell=nc.value, max_occupancy=occ.value, hmax=hm.value,
+                    nbox=nb.value, n=n.value)
+
+    def export(self):
+        """(cell_start, order, sorted) device tensors describing the layout."""
+        info = self.info()
+        dev = self.ctx.device
+        cs = torch.empty(info["ncell"] + 1, dtype=torch.int32, device=dev)
+        order = torch.empty(self.n, dtype=torch.int32, device=dev)
+        srt = torch.empty((13, self.n), dtype=torch.int16, device=dev) if self.sorted else None
+        self.ctx._sync_stream()
+        self.ctx._call("pv_cells_export", self.handle, _ptr(cs), _ptr(order), _ptr(srt))
+        return cs, order, srt
+
+    def free(self):
+        if self.handle is not None and self.ctx.handle is not None:
+            load_library().pv_free_cells(self.ctx.handle, self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A pv_ctx bound to one GPU; calls are issued on torch's current stream."""
+
+    def __init__(self, device: Optional[int] = None):
+        lib = load_library()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device)
+        h = C.c_void_p()
+        st = lib.pv_create(device, C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream),
+                           C.byref(h))
+        if st != PV_OK:
+            raise PVError(st, f"pv_create(device={device}) failed")
+        self.handle = h
+
+    # -- plumbing --------------------------------------------------------
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        load_library().pv_set_stream(self.handle, C.c_void_p(s))
+
+    def _call(self, name, *args):
+        st = getattr(load_library(), name)(self.handle, *args)
+        if st != PV_OK:
+            msg = load_library().pv_last_error(self.handle)
+            raise PVError(st, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            load_library().pv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points ----------------------------------------------------
+    def build_cells(self, pos, h, mass, box=(1.0, 1.0, 1.0), grid=None,
+                    cells: Optional[Cells] = None) -> Cells:
+        n = int(pos.shape[0])
+        _dev_f32(pos, n, 3, "pos", self.device)
+        _dev_f32(h, n, 0, "h", self.device)
+        _dev_f32(mass, n, 0, "mass", self.device)
+        return self.build_cells_batched([0, n], pos, h, mass, [box], None if grid is None else [grid],
+                                        cells)
+
+    def build_cells_batched(self, offsets: Sequence[int], pos, h, mass, boxes, grids=None,
+                            cells: Optional[Cells] = None) -> Cells:
+        nbox = len(offsets) - 1
+        n = int(offsets[-1])
+        _dev_f32(pos, n, 3, "pos", self.device)
+        _dev_f32(h, n, 0, "h", self.device)
+        _dev_f32(mass, n, 0, "mass", self.device)
+        off = (C.c_int64 * (nbox + 1))(*[int(x) for x in offsets])
+        bx = []
+        for b in boxes:
+            bx.extend([float(b)] * 3 if isinstance(b, (int, float)) else [float(x) for x in b])
+        if len(bx) != 3 * nbox:
+            raise ValueError("boxes must give 3 edges per box")
+        barr = (C.c_double * (3 * nbox))(*bx)
+        garr = None
+        if grids is not None:
+            gl = []
+            for g in grids:
+                gl.extend([int(g)] * 3 if isinstance(g, (int,)) else [int(x) for x in g])
+            if len(gl) != 3 * nbox:
+                raise ValueError("grids must give 3 counts per box")
+            garr = (C.c_int * (3 * nbox))(*gl)
+        handle = C.c_void_p(cells.handle.value if cells is not None else None)
+        self._sync_stream()
+        self._call("pv_build_cells_batched", nbox, off, _ptr(pos), _ptr(h), _ptr(mass), barr,
+                   garr, C.byref(handle))
+        if cells is not None:
+            cells.handle = handle
+            cells.n = n
+            cells.nbox = nbox
+            cells.sorted = False
+            return cells
+        return Cells(self, handle, n, nbox)
+
+    def sort_cells(self, cells: Cells) -> None:
+        self._sync_stream()
+        self._call("pv_sort_cells", cells.handle)
+        cells.sorted = True
+
+    def density(self, cells: Cells, algo: str = "sorted", out=None):
+        """(rho, wcount, drho_dh, ncount) in original particle order."""
+        n = cells.n
+        if out is None:
+            rho = torch.empty(n, dtype=torch.float32, device=self.device)
+            wc = torch.empty_like(rho)
+            dh = torch.empty_like(rho)
+            nc = torch.empty(n, dtype=torch.int32, device=self.device)
+        else:
+            rho, wc, dh, nc = out
+        self._sync_stream()
+        self._call("pv_density", cells.handle, ALGOS[algo], _ptr(rho), _ptr(wc), _ptr(dh), _ptr(nc))
+        return rho, wc, dh, nc
+
+    def density_backward(self, cells: Cells, grad_rho, out=None):
+        n = cells.n
+        _dev_f32(grad_rho, n, 0, "grad_rho", self.device)
+        if out is None:
+            gp = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+            gh = torch.empty(n, dtype=torch.float32, device=self.device)
+        else:
+            gp, gh = out
+        self._sync_stream()
+        self._call("pv_density_backward", cells.handle, _ptr(grad_rho), _ptr(gp), _ptr(gh))
+        return gp, gh
+
+    def check(self) -> None:
+        self._sync_stream()
+        self._call("pv_check")
+
+    def set_census(self, on: bool) -> None:
+        self._call("pv_set_census", 1 if on else 0)
+
+    def census(self):
+        v = (C.c_int64 * 2)()
+        self._sync_stream()
+        self._call("pv_census", v)
+        return int(v[0]), int(v[1])
+
+
+_contexts = {}
+
+
+def context(device: Optional[int] = None) -> Context:
+    """Process-wide context for a device (created on first use)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    if device not in _contexts:
+        _contexts[device] = Context(device)
+    return _contexts[device]
+
+
+# -- high-level, differentiable ------------------------------------------------
+class _DensityFn(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, pos, h, mass, box, grid, algo):
+        ctx = context(pos.device.index)
+        cells = ctx.build_cells(pos.detach(), h.detach(), mass.detach(), box, grid)
+        if algo == "sorted" or pos.requires_grad or h.requires_grad:
+            ctx.sort_cells(cells)
+        rho, wc, dh, nc = ctx.density(cells, algo)
+        fctx.cells = cells
+        fctx.mark_non_differentiable(wc, dh, nc)
+        return rho, wc, dh, nc
+
+    @staticmethod
+    def backward(fctx, g_rho, g_wc, g_dh, g_nc):
+        cells = fctx.cells
+        ctx = cells.ctx
+        if g_rho is None:
+            return None, None, None, None, None, None
+        gp, gh = ctx.density_backward(cells, g_rho.contiguous().float())
+        need_p, need_h = fctx.needs_input_grad[0], fctx.needs_input_grad[1]
+        return (gp if need_p else None), (gh if need_h else None), None, None, None, None
+
+
+def density(pos, mass, h, box=(1.0, 1.0, 1.0), algo: str = "sorted", grid=None):
+    """SPH density of every particle: (rho, wcount, drho_dh, ncount).
+
+    Differentiable in pos and h through rho (the adjoint runs in the library);
+    wcount, drho_dh and ncount carry no gradient."""
+    if algo not in ALGOS:
+        raise ValueError(f"algo must be one of {sorted(ALGOS)}")
+    return _DensityFn.apply(pos, h, mass, tuple(box) if not isinstance(box, (int, float)) else (box,) * 3,
+                            grid, algo)
