@@ -33,8 +33,8 @@ __device__ __forceinline__ void grad_pair(float dx, float dy, float dz, float mj
     float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     float Hk2 = Hk * Hk, Hj2 = Hj * Hj;
     if ((r2 < Hk2 || r2 < Hj2) && r2 > 0.0f) {
-        float r = sqrtf(r2);
-        float invr = 1.0f / r;
+        float invr = __builtin_amdgcn_rsqf(r2);   // v_rsq_f32, 1 ulp
+        float r = r2 * invr;
         float coef = 0.0f;
         if (r2 < Hk2) {
             float u = r * invHk;
@@ -46,7 +46,7 @@ __device__ __forceinline__ void grad_pair(float dx, float dy, float dz, float mj
             a.dh = fmaf(mj, fmaf(u, dw, 3.0f * w), a.dh);
         }
         if (r2 < Hj2) {
-            float invHj = 1.0f / Hj;
+            float invHj = __builtin_amdgcn_rcpf(Hj);  // v_rcp_f32, 1 ulp
             float u = r * invHj;
             float v = 1.0f - u;
             float dw = u < 0.5f ? u * fmaf(18.0f, u, -12.0f) : -6.0f * v * v;

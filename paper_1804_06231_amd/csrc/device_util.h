@@ -81,4 +81,40 @@ __device__ __forceinline__ int next_pow2(int v)
     return p;
 }
 
+struct CellGeom {
+    int cx, cy, cz;
+    float ox, oy, oz;
+};
+
+__device__ __forceinline__ CellGeom cell_geom(const BoxDesc &B, int c)
+{
+    CellGeom g;
+    int local = c - B.cell_off;
+    g.cz = local % B.g[2];
+    g.cy = (local / B.g[2]) % B.g[1];
+    g.cx = local / (B.g[2] * B.g[1]);
+    g.ox = (float)g.cx * B.edge[0];
+    g.oy = (float)g.cy * B.edge[1];
+    g.oz = (float)g.cz * B.edge[2];
+    return g;
+}
+
+// Neighbour cell at offset (dx, dy, dz) with periodic wrap; returns its global
+// index and the shift that maps its cell-relative positions into the frame of
+// the receiver cell: shift = origin_b (+- L when wrapped) - origin_a, formed so
+// that every operation is exact in fp32.
+__device__ __forceinline__ int neighbour(const BoxDesc &B, const CellGeom &a, int dx, int dy,
+                                         int dz, float &sx, float &sy, float &sz)
+{
+    int bx = a.cx + dx, by = a.cy + dy, bz = a.cz + dz;
+    float wx = 0.0f, wy = 0.0f, wz = 0.0f;
+    if (bx < 0) { bx += B.g[0]; wx = -B.L[0]; } else if (bx >= B.g[0]) { bx -= B.g[0]; wx = B.L[0]; }
+    if (by < 0) { by += B.g[1]; wy = -B.L[1]; } else if (by >= B.g[1]) { by -= B.g[1]; wy = B.L[1]; }
+    if (bz < 0) { bz += B.g[2]; wz = -B.L[2]; } else if (bz >= B.g[2]) { bz -= B.g[2]; wz = B.L[2]; }
+    sx = ((float)bx * B.edge[0] - a.ox) + wx;
+    sy = ((float)by * B.edge[1] - a.oy) + wy;
+    sz = ((float)bz * B.edge[2] - a.oz) + wz;
+    return B.cell_off + (bx * B.g[1] + by) * B.g[2] + bz;
+}
+
 }  // namespace pvl

@@ -19,6 +19,8 @@ constexpr int kBlock = 256;
 // Device error bits.
 constexpr int kErrOverflow = 1;
 constexpr int kErrGrid = 2;
+// Largest cell the tiled sweep handles in one workgroup (larger: scalar sweep).
+constexpr int kTiledMaxCell = 512;
 
 // One periodic box of a (possibly batched) cell structure, as the kernels see it.
 struct BoxDesc {
@@ -97,6 +99,9 @@ hipError_t launch_zero(hipStream_t st, void *p, int64_t words);
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,
                         const int *dflags, unsigned long long *census);
+hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                              float *rho, float *wcount, float *drho_dh, int32_t *ncount,
+                              const int *dflags);
 hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                            const float *grad_rho, float *grad_pos, float *grad_h,
                            const int *dflags);

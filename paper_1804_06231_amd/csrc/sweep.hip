@@ -30,7 +30,7 @@ __device__ __forceinline__ void density_pair(float dx, float dy, float dz, float
 {
     float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     if (r2 < H2) {
-        float u = sqrtf(r2) * invH;
+        float u = __builtin_amdgcn_sqrtf(r2) * invH;   // v_sqrt_f32, 1 ulp
         float u2 = u * u;
         float v = 1.0f - u;
         float v2 = v * v;
@@ -60,42 +60,6 @@ __device__ __forceinline__ void write_density(const DensityAcc &a, float H, floa
     if (wcount) wcount[o] = norm * (a.wc + 1.0f);
     if (drho_dh) drho_dh[o] = -norm * (kGamma * invH) * (a.dh + 3.0f * mi);  // 1/h = gamma/H
     if (ncount) ncount[o] = a.cnt;
-}
-
-struct CellGeom {
-    int cx, cy, cz;
-    float ox, oy, oz;
-};
-
-__device__ __forceinline__ CellGeom cell_geom(const BoxDesc &B, int c)
-{
-    CellGeom g;
-    int local = c - B.cell_off;
-    g.cz = local % B.g[2];
-    g.cy = (local / B.g[2]) % B.g[1];
-    g.cx = local / (B.g[2] * B.g[1]);
-    g.ox = (float)g.cx * B.edge[0];
-    g.oy = (float)g.cy * B.edge[1];
-    g.oz = (float)g.cz * B.edge[2];
-    return g;
-}
-
-// Neighbour cell at offset (dx, dy, dz) with periodic wrap; returns its global
-// index and the shift that maps its cell-relative positions into the frame of
-// the receiver cell: shift = origin_b (+- L when wrapped) - origin_a, formed so
-// that every operation is exact in fp32.
-__device__ __forceinline__ int neighbour(const BoxDesc &B, const CellGeom &a, int dx, int dy,
-                                         int dz, float &sx, float &sy, float &sz)
-{
-    int bx = a.cx + dx, by = a.cy + dy, bz = a.cz + dz;
-    float wx = 0.0f, wy = 0.0f, wz = 0.0f;
-    if (bx < 0) { bx += B.g[0]; wx = -B.L[0]; } else if (bx >= B.g[0]) { bx -= B.g[0]; wx = B.L[0]; }
-    if (by < 0) { by += B.g[1]; wy = -B.L[1]; } else if (by >= B.g[1]) { by -= B.g[1]; wy = B.L[1]; }
-    if (bz < 0) { bz += B.g[2]; wz = -B.L[2]; } else if (bz >= B.g[2]) { bz -= B.g[2]; wz = B.L[2]; }
-    sx = ((float)bx * B.edge[0] - a.ox) + wx;
-    sy = ((float)by * B.edge[1] - a.oy) + wy;
-    sz = ((float)bz * B.edge[2] - a.oz) + wz;
-    return B.cell_off + (bx * B.g[1] + by) * B.g[2] + bz;
 }
 
 // Frames for the difference x_j - x_i of a receiver i in cell a and a source j
@@ -190,13 +154,13 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
     const float *__restrict__ Hc, const int32_t *__restrict__ orig,
     const uint16_t *__restrict__ sidx, const float *__restrict__ skey, int64_t n, float *rho,
     float *wcount, float *drho_dh, int32_t *ncount, const int *__restrict__ dflags,
-    unsigned long long *census)
+    unsigned long long *census, int only_above)
 {
     if (dflags[0]) return;
     const int a = blockIdx.x;
     const int sa = start[a];
     const int na = start[a + 1] - sa;
-    if (na <= 0) return;
+    if (na <= 0 || na <= only_above) return;
     const BoxDesc &B = box[cell_box[a]];
     const CellGeom ga = cell_geom(B, a);
     // pruning slack covering fp32 rounding of keys and shifts (>> the error)
@@ -268,10 +232,18 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
         hipLaunchKernelGGL(k_sweep_plain, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                            c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, rho, wcount, drho_dh,
                            ncount, dflags, census);
-    } else {
+    } else if (census) {
+        // the census counts the candidates of the exact per-receiver bounds
         hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                            c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n, rho,
-                           wcount, drho_dh, ncount, dflags, census);
+                           wcount, drho_dh, ncount, dflags, census, 0);
+    } else {
+        hipError_t e = launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags);
+        if (e != hipSuccess) return e;
+        // cells too large for the tiled workgroup
+        hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                           c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n, rho,
+                           wcount, drho_dh, ncount, dflags, census, kTiledMaxCell);
     }
     return hipGetLastError();
 }
