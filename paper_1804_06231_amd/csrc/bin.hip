@@ -39,8 +39,8 @@ __global__ void k_box_hmax(const BoxDesc *__restrict__ box, int nbox, int64_t n,
 
 __global__ void k_bin_count(const BoxDesc *__restrict__ box, int nbox, int64_t n,
                             const float *__restrict__ pos, const float *__restrict__ h,
-                            int32_t *__restrict__ cellid, int32_t *__restrict__ count,
-                            uint32_t *__restrict__ cell_hmax, int *__restrict__ dflags)
+                            int32_t *__restrict__ cellid, int32_t *__restrict__ slot,
+                            int32_t *__restrict__ count, int *__restrict__ dflags)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -53,16 +53,16 @@ __global__ void k_bin_count(const BoxDesc *__restrict__ box, int nbox, int64_t n
     int cz = cell_coord(z, B.inv_edge[2], B.g[2]);
     int c = B.cell_off + (cx * B.g[1] + cy) * B.g[2] + cz;
     cellid[p] = c;
-    atomicAdd(&count[c], 1);
+    // arrival order within the cell; made deterministic later by the
+    // per-cell sort on the original index
+    slot[p] = atomicAdd(&count[c], 1);
     float H = kGamma * h[p];
-    atomicMax(&cell_hmax[c], __float_as_uint(H));
     float emin = fminf(B.edge[0], fminf(B.edge[1], B.edge[2]));
     if (!(H <= emin) || !(H > 0.0f)) atomicOr(dflags, kErrGrid);
 }
 
 // Single workgroup: exclusive scan of count[0..ncell) into start[0..ncell],
-// counts reset to zero (they become scatter cursors), largest count into
-// dflags[1], overflow flagged.
+// largest count into dflags[1], overflow flagged.
 __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restrict__ count,
                                                 int32_t *__restrict__ start,
                                                 int *__restrict__ dflags)
@@ -92,7 +92,6 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restric
         int32_t v = count[c];
         start[c] = run;
         run += v;
-        count[c] = 0;
     }
     if (threadIdx.x == T - 1) start[ncell] = part[T - 1];
     for (int off = 32; off > 0; off >>= 1) {
@@ -108,7 +107,7 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restric
 __global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n,
                           const float *__restrict__ pos, const float *__restrict__ h,
                           const float *__restrict__ mass, const int32_t *__restrict__ cellid,
-                          const int32_t *__restrict__ start, int32_t *__restrict__ cursor,
+                          const int32_t *__restrict__ slot, const int32_t *__restrict__ start,
                           float4 *__restrict__ stage, float2 *__restrict__ stage2)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -117,10 +116,9 @@ __global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n,
     float x = wrap_coord(pos[3 * p + 0], B.L[0], 1.0f / B.L[0]);
     float y = wrap_coord(pos[3 * p + 1], B.L[1], 1.0f / B.L[1]);
     float z = wrap_coord(pos[3 * p + 2], B.L[2], 1.0f / B.L[2]);
-    int c = cellid[p];
-    int slot = start[c] + atomicAdd(&cursor[c], 1);
-    stage[slot] = make_float4(x, y, z, kGamma * h[p]);
-    stage2[slot] = make_float2(mass[p], __int_as_float((int)p));
+    int q = start[cellid[p]] + slot[p];
+    stage[q] = make_float4(x, y, z, kGamma * h[p]);
+    stage2[q] = make_float2(mass[p], __int_as_float((int)p));
 }
 
 // One workgroup per cell.
@@ -128,13 +126,17 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     const float2 *__restrict__ stage2, float4 *__restrict__ xyzm, float *__restrict__ Hout,
-    int32_t *__restrict__ orig)
+    int32_t *__restrict__ orig, uint32_t *__restrict__ cell_hmax)
 {
     __shared__ uint64_t keys[PV_MAX_CELL];
+    __shared__ uint32_t hred[kBlock / 64];
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
-    if (cnt <= 0 || cnt > PV_MAX_CELL) return;
+    if (cnt <= 0 || cnt > PV_MAX_CELL) {
+        if (threadIdx.x == 0) cell_hmax[c] = 0u;
+        return;
+    }
     const BoxDesc &B = box[cell_box[c]];
     int local = c - B.cell_off;
     int cz = local % B.g[2];
@@ -152,6 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
     }
     __syncthreads();
     bitonic_sort_segments(keys, P2, 1);
+    uint32_t hm = 0u;
     for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
         int slot = s0 + (int)(keys[r] & 0xffffffffu);
         float4 a = stage[slot];
@@ -159,6 +162,16 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
         xyzm[s0 + r] = make_float4(a.x - ox, a.y - oy, a.z - oz, b.x);
         Hout[s0 + r] = a.w;
         orig[s0 + r] = __float_as_int(b.y);
+        hm = max(hm, __float_as_uint(a.w));
+    }
+    // largest cut-off of the cell (positive floats order as their bits)
+    for (int off = 32; off > 0; off >>= 1) hm = max(hm, (uint32_t)__shfl_xor((int)hm, off));
+    if ((threadIdx.x & 63) == 0) hred[threadIdx.x >> 6] = hm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = 0u;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, hred[w]);
+        cell_hmax[c] = m;
     }
 }
 
@@ -206,15 +219,16 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, int nbox, int64_t n, in
                        ncell, c.cell_box);
     if (n > 0) {
         hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox,
-                           n, pos, h, c.cellid, c.cursor, c.cell_hmax, dflags);
+                           n, pos, h, c.cellid, c.slot, c.cursor, dflags);
     }
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncell, c.cursor, c.cell_start, dflags);
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox, n,
-                           pos, h, mass, c.cellid, c.cell_start, c.cursor, c.stage, c.stage2);
-        hipLaunchKernelGGL(k_cell_finish, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                           c.cell_box, c.cell_start, c.stage, c.stage2, c.xyzm, c.H, c.orig);
+                           pos, h, mass, c.cellid, c.slot, c.cell_start, c.stage, c.stage2);
     }
+    hipLaunchKernelGGL(k_cell_finish, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                       c.cell_box, c.cell_start, c.stage, c.stage2, c.xyzm, c.H, c.orig,
+                       c.cell_hmax);
     return hipGetLastError();
 }
 

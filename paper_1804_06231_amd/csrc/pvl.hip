@@ -59,7 +59,7 @@ hipError_t dev_alloc(T **p, int64_t count)
 
 void free_dev(DevCells &d)
 {
-    void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cursor, d.cellid, d.stage,
+    void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cursor, d.cellid, d.slot, d.stage,
                     d.stage2, d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -84,6 +84,7 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.cell_hmax, C);
     ALLOC(d.cursor, C);
     ALLOC(d.cellid, N);
+    ALLOC(d.slot, N);
     ALLOC(d.stage, N);
     ALLOC(d.stage2, N);
     ALLOC(d.xyzm, N);
@@ -296,7 +297,6 @@ pv_status pv_build_cells_batched(pv_ctx *ctx, int nbox, const int64_t *offsets,
     c->sorted = false;
     if ((st = upload_boxes(ctx, c)) != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
     hipError_t e = pvl::launch_zero(ctx->stream, c->d.cursor, ncell);
-    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, c->d.cell_hmax, ncell);
     if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, ctx->dflags + 1, 1);
     if (e == hipSuccess) e = pvl::launch_bin(ctx->stream, c->d, nbox, n, ncell, pos, h, mass, ctx->dflags);
     if (e != hipSuccess) {

@@ -78,6 +78,7 @@ struct DevCells {
     uint32_t *cell_hmax = nullptr;// ncell: max cut-off in the cell (fp32 bits)
     int32_t *cursor = nullptr;    // ncell: scatter cursors / counts
     int32_t *cellid = nullptr;    // n: global cell of each input particle
+    int32_t *slot = nullptr;      // n: arrival rank of the particle within its cell
     float4 *stage = nullptr;      // n: (x, y, z, H) wrapped, in scatter order
     float2 *stage2 = nullptr;     // n: (m, original index as bits)
     float4 *xyzm = nullptr;       // n: cell-relative position and mass
