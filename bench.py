@@ -47,6 +47,9 @@ def _args():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="also run one device copy of this many MiB (a reference kernel "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
@@ -85,6 +88,12 @@ def main():
     h = torch.from_numpy(s.h).to(dev)
     m = torch.from_numpy(s.m).to(dev)
     ctx = pvl.Context(0)
+    if a.copy_probe_mb:
+        src = torch.ones(a.copy_probe_mb * (1 << 20) // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # grid: the workload's own, else the finest legal one (found once, then the
     # cell structure is rebuilt in place every step with that grid)

@@ -163,6 +163,25 @@ pv_status pv_cells_export(pv_ctx *ctx, const pv_cells *cells, int32_t *cell_star
 pv_status pv_set_census(pv_ctx *ctx, int enable);
 pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
 
+/* Tuning parameters of the sweep kernels (all results are identical up to
+ * floating-point summation order; only speed changes).  Values persist on
+ * the context.  The autotuner picks them per workload.
+ *   PV_PARAM_REACH_ORDER  1: order each direction's receivers by the reach of
+ *                         their cut-off past the shared face before blocking
+ *                         them into rows of 16 (tighter loop bounds, costs a
+ *                         sort per cell); 0: use the key order.  Default 0.
+ *   PV_PARAM_TASK_SORT    1: run row tasks longest first so the rows of a wave
+ *                         finish together; 0: natural order.  Default 1.
+ *   PV_PARAM_TILED_MAX    cells with more particles than this use the scalar
+ *                         sweep (0..512).  Default 512. */
+typedef enum {
+    PV_PARAM_REACH_ORDER = 1,
+    PV_PARAM_TASK_SORT = 2,
+    PV_PARAM_TILED_MAX = 3
+} pv_param;
+pv_status pv_set_param(pv_ctx *ctx, pv_param param, int value);
+pv_status pv_get_param(pv_ctx *ctx, pv_param param, int *value);
+
 /* Release a cell structure.  NULL is accepted. */
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells);
 

@@ -21,6 +21,7 @@ struct pv_ctx {
     unsigned long long *dcensus = nullptr;  // [0] pairs tested, [1] pairs in range
     int census_on = 0;
     int *hpinned = nullptr;                 // pinned read-back area (64 bytes)
+    pvl::SweepTuning tune;
 };
 
 struct pv_cells {
@@ -358,7 +359,7 @@ pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rh
     if (ctx->census_on) HIPCHK(ctx, pvl::launch_zero(ctx->stream, ctx->dcensus, 4));
     HIPCHK(ctx, pvl::launch_sweep(ctx->stream, cells->d, cells->n, cells->ncell, (int)algo, rho,
                                   wcount, drho_dh, ncount, ctx->dflags,
-                                  ctx->census_on ? ctx->dcensus : nullptr));
+                                  ctx->census_on ? ctx->dcensus : nullptr, ctx->tune));
     return PV_OK;
 }
 
@@ -459,6 +460,32 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2])
     counts[0] = (int64_t)v[0];
     counts[1] = (int64_t)v[1];
     return PV_OK;
+}
+
+pv_status pv_set_param(pv_ctx *ctx, pv_param param, int value)
+{
+    if (!ctx) return PV_EINVAL;
+    switch (param) {
+    case PV_PARAM_REACH_ORDER: ctx->tune.reach_order = value ? 1 : 0; return PV_OK;
+    case PV_PARAM_TASK_SORT: ctx->tune.task_sort = value ? 1 : 0; return PV_OK;
+    case PV_PARAM_TILED_MAX:
+        if (value < 0 || value > pvl::kTiledMaxCell)
+            return fail(ctx, PV_EINVAL, "tiled_max must be 0.." + std::to_string(pvl::kTiledMaxCell));
+        ctx->tune.tiled_max = value;
+        return PV_OK;
+    }
+    return fail(ctx, PV_EINVAL, "unknown parameter");
+}
+
+pv_status pv_get_param(pv_ctx *ctx, pv_param param, int *value)
+{
+    if (!ctx || !value) return PV_EINVAL;
+    switch (param) {
+    case PV_PARAM_REACH_ORDER: *value = ctx->tune.reach_order; return PV_OK;
+    case PV_PARAM_TASK_SORT: *value = ctx->tune.task_sort; return PV_OK;
+    case PV_PARAM_TILED_MAX: *value = ctx->tune.tiled_max; return PV_OK;
+    }
+    return fail(ctx, PV_EINVAL, "unknown parameter");
 }
 
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells)

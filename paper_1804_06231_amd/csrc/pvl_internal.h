@@ -97,12 +97,19 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, int nbox, int64_t n, in
                       const float *pos, const float *h, const float *mass, int *dflags);
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell);
 hipError_t launch_zero(hipStream_t st, void *p, int64_t words);
+// Sweep tuning (see pv_param).
+struct SweepTuning {
+    int reach_order = 0;
+    int task_sort = 1;
+    int tiled_max = kTiledMaxCell;
+};
+
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                        const int *dflags, unsigned long long *census);
+                        const int *dflags, unsigned long long *census, const SweepTuning &tune);
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                              const int *dflags);
+                              const int *dflags, const SweepTuning &tune, bool plain);
 hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                            const float *grad_rho, float *grad_pos, float *grad_h,
                            const int *dflags);

@@ -107,13 +107,13 @@ __global__ void __launch_bounds__(kBlock) k_sweep_plain(
     const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
     const float *__restrict__ Hc, const int32_t *__restrict__ orig, float *rho, float *wcount,
     float *drho_dh, int32_t *ncount, const int *__restrict__ dflags,
-    unsigned long long *census)
+    unsigned long long *census, int only_above)
 {
     if (dflags[0]) return;
     const int a = blockIdx.x;
     const int sa = start[a];
     const int na = start[a + 1] - sa;
-    if (na <= 0) return;
+    if (na <= 0 || na <= only_above) return;
     const BoxDesc &B = box[cell_box[a]];
     const CellGeom ga = cell_geom(B, a);
     for (int i0 = 0; i0 < na; i0 += blockDim.x) {
@@ -225,25 +225,34 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
 
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                        const int *dflags, unsigned long long *census)
+                        const int *dflags, unsigned long long *census,
+                        const SweepTuning &tune)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
-    if (algo == PV_PLAIN_CELL) {
+    if (algo == PV_PLAIN_CELL && census) {
         hipLaunchKernelGGL(k_sweep_plain, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                            c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, rho, wcount, drho_dh,
-                           ncount, dflags, census);
+                           ncount, dflags, census, 0);
+    } else if (algo == PV_PLAIN_CELL) {
+        hipError_t e = launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags,
+                                          tune, true);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sweep_plain, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                           c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, rho, wcount, drho_dh,
+                           ncount, dflags, census, tune.tiled_max);
     } else if (census) {
         // the census counts the candidates of the exact per-receiver bounds
         hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                            c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n, rho,
                            wcount, drho_dh, ncount, dflags, census, 0);
     } else {
-        hipError_t e = launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags);
+        hipError_t e = launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags,
+                                          tune, false);
         if (e != hipSuccess) return e;
         // cells too large for the tiled workgroup
         hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                            c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n, rho,
-                           wcount, drho_dh, ncount, dflags, census, kTiledMaxCell);
+                           wcount, drho_dh, ncount, dflags, census, tune.tiled_max);
     }
     return hipGetLastError();
 }

@@ -15,12 +15,18 @@
 //     fetched once per 16 pair tests;
 //   * a row's task is (neighbour direction, block of 16 receivers); its number
 //     of source tiles is the paper's bound taken for the block: the sources up
-//     to the largest key + cut-off of its receivers;
+//     to the largest key + cut-off of its receivers.  Receivers are ordered by
+//     that reach (key + H toward a neighbour ahead on the axis, key - H toward
+//     one behind) rather than by key, so the 16 bounds of a block are close;
+//   * tasks run longest first, four to a wave, so the rows of a wave finish
+//     together;
 //   * receivers past first_a (none of their candidates can be in range, judged
 //     with the cell's largest cut-off) get no task.
 //
-// The receiver's own cell is swept in cell order with the same tiles (the
-// paper does not treat the self interaction).  Each wave accumulates its
+// The receiver's own cell (which the paper does not treat) uses the same
+// tiles on the cell's sorted list along x: a block of 16 receivers only meets
+// the source tiles whose keys lie within the block's key range widened by its
+// largest cut-off on both sides.  Each wave accumulates its
 // rows in registers and adds them, once per task, into its own LDS array;
 // the four arrays are summed in a fixed order at the end, so the result does
 // not depend on timing.  One workgroup (4 waves) per cell of at most
@@ -29,7 +35,13 @@
 
 namespace pvl {
 
-constexpr int kTiledMaxTasks = 27 * (kTiledMaxCell / 16);
+// Per size class MAXC (largest cell handled by one workgroup): task slots and
+// receivers (over all 26 directions) that can be ordered by reach in LDS.
+template <int MAXC> struct TiledLimits {
+    static constexpr int tasks = 27 * (MAXC / 16);
+    static constexpr int recv = 6 * MAXC;
+    static_assert(recv * 10 <= 4 * MAXC * 16, "set-up arrays alias the accumulators");
+};
 
 template <int K>
 __device__ __forceinline__ float ror16(float v)
@@ -71,11 +83,14 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH, Ti
     }
 
 // Task word: bits 0-8 source tiles, 9-14 receiver block, 15-19 direction
-// (0..25 neighbour, 26 = own cell).
-__device__ __forceinline__ uint32_t pack_task(int dir, int blk, int nt)
+// (0..25 neighbour, 26 = own cell), 20-28 first source tile.
+__device__ __forceinline__ uint32_t pack_task(int dir, int blk, int nt, int t0)
 {
-    return (uint32_t)nt | ((uint32_t)blk << 9) | ((uint32_t)dir << 15);
+    return (uint32_t)nt | ((uint32_t)blk << 9) | ((uint32_t)dir << 15) | ((uint32_t)t0 << 20);
 }
+
+// Axis of the own-cell sort: d = (1, 0, 0).
+constexpr int kSelfAxis = 4;
 
 __device__ __forceinline__ int nb_offset(int dir, int &dx, int &dy, int &dz)
 {
@@ -86,32 +101,44 @@ __device__ __forceinline__ int nb_offset(int dir, int &dx, int &dy, int &dz)
     return o;
 }
 
+// PLAIN = true gives the plain cell-list comparator on the same tiles: every
+// receiver of the cell meets every particle of the 27 cells, in cell order,
+// with no sorted lists and no pruning (Listing 1).
+template <int MAXC, bool PLAIN>
 __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
     const float *__restrict__ Hc, const uint32_t *__restrict__ cell_hmax,
     const int32_t *__restrict__ orig, const uint16_t *__restrict__ sidx,
     const float *__restrict__ skey, int64_t n, float *rho, float *wcount, float *drho_dh,
-    int32_t *ncount, const int *__restrict__ dflags)
+    int32_t *ncount, const int *__restrict__ dflags, int min_na, int max_na, int reach_order,
+    int task_sort)
 {
-    __shared__ float4 acc_lds[4][kTiledMaxCell];
+    constexpr int kTiledMaxRecv = TiledLimits<MAXC>::recv;
+    constexpr int kTiledMaxTasks = TiledLimits<MAXC>::tasks;
+    // per-wave accumulators; during set-up the same bytes hold the receiver
+    // reach values and indices being sorted
+    __shared__ float4 acc_lds[4][MAXC];
+    __shared__ uint16_t rlist[kTiledMaxRecv];
     __shared__ uint32_t tasks[kTiledMaxTasks];
+    __shared__ uint16_t torder[kTiledMaxTasks];
     __shared__ int n_act[27];
     __shared__ int task_off[28];
+    __shared__ int recv_off[27];
+    float *rv = reinterpret_cast<float *>(&acc_lds[0][0]);               // reach, key order
+    float *rvs = rv + kTiledMaxRecv;                                     // reach, sorted
+    uint16_t *ria = reinterpret_cast<uint16_t *>(rvs + kTiledMaxRecv);   // receiver, key order
 
     if (dflags[0]) return;
     const int a = blockIdx.x;
     const int sa = start[a];
     const int na = start[a + 1] - sa;
-    if (na <= 0 || na > kTiledMaxCell) return;
+    if (na <= min_na || na > max_na) return;
     const BoxDesc &B = box[cell_box[a]];
     const CellGeom ga = cell_geom(B, a);
     const float slack = 1.52587890625e-5f * (B.edge[0] + B.edge[1] + B.edge[2]);
     const float hmax_a = __uint_as_float(cell_hmax[a]);
     const int tid = threadIdx.x;
-
-    for (int t = tid; t < 4 * kTiledMaxCell; t += blockDim.x)
-        (&acc_lds[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
 
     // receivers of each direction that can have a candidate (first_a)
     if (tid < 26) {
@@ -121,7 +148,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
         int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
         int sb = start[b], nb = start[b + 1] - sb;
         int act = 0;
-        if (nb > 0) {
+        if (PLAIN) {
+            act = nb > 0 ? na : 0;
+        } else if (nb > 0) {
             int sign;
             int s = dir_canon(dx, dy, dz, &sign);
             float e[3];
@@ -148,24 +177,91 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
     if (tid == 26) n_act[26] = na;
     __syncthreads();
     if (tid == 0) {
-        int off = 0;
+        int off = 0, roff = 0;
         for (int d = 0; d < 27; ++d) {
             task_off[d] = off;
             off += (n_act[d] + 15) >> 4;
+            if (d < 26) {
+                recv_off[d] = roff;
+                roff += n_act[d];
+            }
         }
         task_off[27] = off;
+        // reach ordering needs room for every active receiver
+        recv_off[26] = (!PLAIN && reach_order && roff <= kTiledMaxRecv) ? roff : -1;
     }
     __syncthreads();
     const int ntask = task_off[27];
+    const bool by_reach = recv_off[26] >= 0;
+    const int nrecv = by_reach ? recv_off[26] : 0;
+
+    // Order each direction's active receivers by how far past the shared face
+    // their cut-off reaches (key + H toward a neighbour ahead, key - H toward
+    // one behind), so a block of 16 has nearly equal loop bounds.
+    if (by_reach) {
+        for (int q = tid; q < nrecv; q += blockDim.x) {
+            int dir = 0;
+            while (dir < 25 && recv_off[dir + 1] <= q) ++dir;
+            int r = q - recv_off[dir];
+            int dx, dy, dz, sign;
+            nb_offset(dir, dx, dy, dz);
+            int s = dir_canon(dx, dy, dz, &sign);
+            int qs = sign > 0 ? na - 1 - r : r;
+            int ia = sidx[(size_t)s * n + sa + qs];
+            float k = skey[(size_t)s * n + sa + qs];
+            float H = Hc[sa + ia];
+            rv[q] = sign > 0 ? -(k + H) : (k - H);
+            ria[q] = (uint16_t)ia;
+        }
+        __syncthreads();
+        for (int q = tid; q < nrecv; q += blockDim.x) {
+            int dir = 0;
+            while (dir < 25 && recv_off[dir + 1] <= q) ++dir;
+            int o = recv_off[dir], r = q - o, m = n_act[dir];
+            float v = rv[q];
+            int rank = 0;
+            for (int k = 0; k < m; ++k) {
+                float w = rv[o + k];
+                rank += (w < v) || (w == v && k < r);
+            }
+            rlist[o + rank] = ria[q];
+            rvs[o + rank] = v;
+        }
+        __syncthreads();
+    }
 
     // source tiles of every task: the paper's bound for the block of receivers
     for (int t = tid; t < ntask; t += blockDim.x) {
         int dir = 0;
         while (task_off[dir + 1] <= t) ++dir;
         int blk = t - task_off[dir];
-        int nt;
-        if (dir == 26) {
-            nt = (na + 15) >> 4;
+        int nt, t0 = 0;
+        if (PLAIN) {
+            int nb = na;
+            if (dir < 26) {
+                int dx, dy, dz;
+                nb_offset(dir, dx, dy, dz);
+                float sx, sy, sz;
+                int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
+                nb = start[b + 1] - start[b];
+            }
+            nt = (nb + 15) >> 4;
+        } else if (dir == 26) {
+            // two-sided window on the x-sorted list: |key_j - key_i| < H_i
+            const float *ka = skey + (size_t)kSelfAxis * n + sa;
+            const uint16_t *ia = sidx + (size_t)kSelfAxis * n + sa;
+            int r0 = blk * 16, r1 = min(r0 + 16, na);
+            float hb = 0.0f;
+            for (int r = r0; r < r1; ++r) hb = fmaxf(hb, Hc[sa + ia[r]]);
+            float lo_k = ka[r0] - hb - slack, hi_k = ka[r1 - 1] + hb + slack;
+            int lo = 0, hi = na;
+            while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] <= lo_k) lo = m + 1; else hi = m; }
+            int j0 = lo;
+            lo = 0; hi = na;
+            while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] < hi_k) lo = m + 1; else hi = m; }
+            int j1 = lo;
+            t0 = j0 >> 4;
+            nt = ((j1 + 15) >> 4) - t0;
         } else {
             int dx, dy, dz;
             nb_offset(dir, dx, dy, dz);
@@ -181,20 +277,28 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
             const uint16_t *ia = sidx + (size_t)s * n + sa;
             const float *kb = skey + (size_t)s * n + sb;
             int r0 = blk * 16, r1 = min(r0 + 16, n_act[dir]);
-            int nsrc;
-            if (sign > 0) {
-                float T = -INFINITY;
+            // block reach: the largest key + H (ahead) or smallest key - H (behind)
+            float T;
+            if (by_reach) {
+                float v = rvs[recv_off[dir] + r0];
+                T = sign > 0 ? -v : v;
+            } else if (sign > 0) {
+                T = -INFINITY;
                 for (int r = r0; r < r1; ++r) {
                     int q = na - 1 - r;
                     T = fmaxf(T, ka[q] + Hc[sa + ia[q]]);
                 }
+            } else {
+                T = INFINITY;
+                for (int r = r0; r < r1; ++r) T = fminf(T, ka[r] - Hc[sa + ia[r]]);
+            }
+            int nsrc;
+            if (sign > 0) {
                 T = (T - se) + slack;
                 int lo = 0, hi = nb;
                 while (lo < hi) { int m = (lo + hi) >> 1; if (kb[m] < T) lo = m + 1; else hi = m; }
                 nsrc = lo;
             } else {
-                float T = INFINITY;
-                for (int r = r0; r < r1; ++r) T = fminf(T, ka[r] - Hc[sa + ia[r]]);
                 T = (T - se) - slack;
                 int lo = 0, hi = nb;
                 while (lo < hi) { int m = (lo + hi) >> 1; if (kb[m] <= T) lo = m + 1; else hi = m; }
@@ -202,8 +306,24 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
             }
             nt = (nsrc + 15) >> 4;
         }
-        tasks[t] = pack_task(dir, blk, nt);
+        tasks[t] = pack_task(dir, blk, nt, t0);
     }
+    __syncthreads();
+    // longest tasks first, so the four rows of a wave carry similar loads
+    for (int t = tid; t < ntask; t += blockDim.x) {
+        int rank = t;
+        if (task_sort) {
+            int nt = (int)(tasks[t] & 511u);
+            rank = 0;
+            for (int q = 0; q < ntask; ++q) {
+                int nq = (int)(tasks[q] & 511u);
+                rank += (nq > nt) || (nq == nt && q < t);
+            }
+        }
+        torder[rank] = (uint16_t)t;
+    }
+    for (int t = tid; t < 4 * MAXC; t += blockDim.x)
+        (&acc_lds[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 
     // tasks in groups of 4 (one per row); group g runs on wave g % 4
@@ -214,12 +334,13 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
     for (int g = wave; g * 4 < ntask; g += 4) {
         const int t = g * 4 + row;
         const bool row_valid = t < ntask;
-        uint32_t tw = row_valid ? tasks[t] : 0u;
+        uint32_t tw = row_valid ? tasks[torder[t]] : 0u;
         int nt = row_valid ? (int)(tw & 511u) : 0;
         int blk = (int)((tw >> 9) & 63u);
-        int dir = (int)(tw >> 15);
+        int dir = (int)((tw >> 15) & 31u);
+        const int t0 = (int)(tw >> 20);
         // receiver of this lane and the source list of its row
-        int dx = 0, dy = 0, dz = 0, sb = sa, nb = na, sign = 1, s = 0;
+        int dx = 0, dy = 0, dz = 0, sb = sa, nb = na, sign = 1, s = kSelfAxis;
         float shx = 0.f, shy = 0.f, shz = 0.f;
         if (dir < 26) {
             nb_offset(dir, dx, dy, dz);
@@ -232,7 +353,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
         const bool recv_ok = row_valid && r < n_act[dir];
         int ia = 0;
         if (recv_ok) {
-            if (dir == 26) ia = r;
+            if (PLAIN) ia = r;
+            else if (dir == 26) ia = sidx[(size_t)s * n + sa + r];
+            else if (by_reach) ia = rlist[recv_off[dir] + r];
             else if (sign > 0) ia = sidx[(size_t)s * n + sa + (na - 1 - r)];
             else ia = sidx[(size_t)s * n + sa + r];
         }
@@ -247,24 +370,25 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
         const float ux = dx < 0 ? shx : 0.0f;
         const float uy = dy < 0 ? shy : 0.0f;
         const float uz = dz < 0 ? shz : 0.0f;
-        const uint16_t *lb = sidx + (size_t)s * n + sb;
+        const uint16_t *lb = PLAIN ? nullptr : sidx + (size_t)s * n + sb;
 
         int ntmax = nt;
         ntmax = max(ntmax, __shfl_xor(ntmax, 16));
         ntmax = max(ntmax, __shfl_xor(ntmax, 32));
         TileAcc acc = {0.f, 0.f, 0.f, 0.f};
-        for (int tile = 0; tile < ntmax; ++tile) {
+        for (int it = 0; it < ntmax; ++it) {
+            const int tile = t0 + it;
             const int j = tile * 16 + l16;
             float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-            if (tile < nt && j < nb) {
-                int p = dir == 26 ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
+            if (it < nt && j < nb) {
+                int p = PLAIN ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
                 q = xyzm[sb + p];
                 q.x += ux;
                 q.y += uy;
                 q.z += uz;
             }
             const float sx = q.x, sy = q.y, sz = q.z, sm = q.w;
-            if (tile < nt) {
+            if (it < nt) {
                 if (!(dir == 26 && tile == blk)) {
                     float dx0 = sx - tx, dy0 = sy - ty, dz0 = sz - tz;
                     float r2 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
@@ -306,12 +430,34 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
 
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                              const int *dflags)
+                              const int *dflags, const SweepTuning &tune, bool plain)
 {
+    if (plain) {
+        int tmax = tune.tiled_max < 0 ? 0 : (tune.tiled_max > kTiledMaxCell ? kTiledMaxCell : tune.tiled_max);
+        hipLaunchKernelGGL((k_sweep_tiled<256, true>), dim3((unsigned)ncell), dim3(kBlock), 0, st,
+                           c.box, c.cell_box, c.cell_start, c.xyzm, c.H, c.cell_hmax, c.orig,
+                           c.sidx, c.skey, n, rho, wcount, drho_dh, ncount, dflags, 0,
+                           tmax < 256 ? tmax : 256, 0, tune.task_sort);
+        if (tmax > 256)
+            hipLaunchKernelGGL((k_sweep_tiled<kTiledMaxCell, true>), dim3((unsigned)ncell),
+                               dim3(kBlock), 0, st, c.box, c.cell_box, c.cell_start, c.xyzm, c.H,
+                               c.cell_hmax, c.orig, c.sidx, c.skey, n, rho, wcount, drho_dh,
+                               ncount, dflags, 256, tmax, 0, tune.task_sort);
+        return hipGetLastError();
+    }
     if (ncell == 0 || n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sweep_tiled, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+    int tmax = tune.tiled_max < 0 ? 0 : (tune.tiled_max > kTiledMaxCell ? kTiledMaxCell : tune.tiled_max);
+    // two size classes: the common small cells run with half the LDS, hence
+    // more workgroups per compute unit
+    hipLaunchKernelGGL((k_sweep_tiled<256, false>), dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                        c.cell_box, c.cell_start, c.xyzm, c.H, c.cell_hmax, c.orig, c.sidx, c.skey,
-                       n, rho, wcount, drho_dh, ncount, dflags);
+                       n, rho, wcount, drho_dh, ncount, dflags, 0, tmax < 256 ? tmax : 256,
+                       tune.reach_order, tune.task_sort);
+    if (tmax > 256)
+        hipLaunchKernelGGL((k_sweep_tiled<kTiledMaxCell, false>), dim3((unsigned)ncell), dim3(kBlock), 0, st,
+                           c.box, c.cell_box, c.cell_start, c.xyzm, c.H, c.cell_hmax, c.orig,
+                           c.sidx, c.skey, n, rho, wcount, drho_dh, ncount, dflags, 256, tmax,
+                           tune.reach_order, tune.task_sort);
     return hipGetLastError();
 }
 

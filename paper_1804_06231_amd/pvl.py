@@ -27,8 +27,9 @@ EXPORTS = (
     "pv_create", "pv_destroy", "pv_set_stream", "pv_last_error", "pv_build_cells",
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
-    "pv_free_cells",
+    "pv_free_cells", "pv_set_param", "pv_get_param",
 )
+PARAMS = {"reach_order": 1, "task_sort": 2, "tiled_max": 3}
 
 _STATUS = {
     PV_EINVAL: "PV_EINVAL", PV_ENOMEM: "PV_ENOMEM", PV_EHIP: "PV_EHIP",
@@ -71,6 +72,8 @@ def load_library(path: str = LIB_PATH):
         "pv_set_census": ([P, i32], i32),
         "pv_census": ([P, P], i32),
         "pv_free_cells": ([P, P], i32),
+        "pv_set_param": ([P, i32, i32], i32),
+        "pv_get_param": ([P, i32, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -258,6 +261,15 @@ class Context:
     def check(self) -> None:
         self._sync_stream()
         self._call("pv_check")
+
+    def set_param(self, name: str, value: int) -> None:
+        """Sweep tuning parameter (see pv_param in include/pvl.h)."""
+        self._call("pv_set_param", PARAMS[name], int(value))
+
+    def get_param(self, name: str) -> int:
+        v = C.c_int()
+        self._call("pv_get_param", PARAMS[name], C.byref(v))
+        return v.value
 
     def set_census(self, on: bool) -> None:
         self._call("pv_set_census", 1 if on else 0)
