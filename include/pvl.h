@@ -159,7 +159,11 @@ pv_status pv_cells_export(pv_ctx *ctx, const pv_cells *cells, int32_t *cell_star
 
 /* Candidate census of the last pv_density call made with census enabled:
  * counts[0] = pairs tested by the distance check, counts[1] = pairs in range
- * (non-self).  pv_set_census(ctx, 1) enables counting (slower). */
+ * (non-self).  pv_set_census(ctx, 1) enables counting: the density is then
+ * computed by scalar kernels that test exactly the pairs admitted by the
+ * per-receiver bounds of Section 3.3 (sorted) or the 27-cell stencil (plain),
+ * so counts[0] is the method's candidate count, not the tiled kernels'
+ * padded one (slower). */
 pv_status pv_set_census(pv_ctx *ctx, int enable);
 pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
 
@@ -172,12 +176,12 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
  *                         sort per cell); 0: use the key order.  Default 0.
  *   PV_PARAM_TASK_SORT    1: run row tasks longest first so the rows of a wave
  *                         finish together; 0: natural order.  Default 1.
- *   PV_PARAM_TILED_MAX    cells with more particles than this use the scalar
- *                         sweep (0..512).  Default 512. */
+ *   PV_PARAM_QUEUE_WGS    persistent workgroups per compute unit of the
+ *                         work-queue sweeps (1..32).  Default 4. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,
     PV_PARAM_TASK_SORT = 2,
-    PV_PARAM_TILED_MAX = 3
+    PV_PARAM_QUEUE_WGS = 3
 } pv_param;
 pv_status pv_set_param(pv_ctx *ctx, pv_param param, int value);
 pv_status pv_get_param(pv_ctx *ctx, pv_param param, int *value);

@@ -5,7 +5,8 @@
 
 Each .hip file is compiled to an object in parallel, then linked into
 paper_1804_06231_amd/libpvl.so.  Packed fp32 instructions are disabled for all
-device code.
+device code, and multiply-add fusion happens only where the source asks
+for it (fmaf).
 """
 from __future__ import annotations
 
@@ -27,6 +28,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # no implicit multiply-add fusion: cell origins and cell-pair shifts must be
+    # rounded exactly as written for the differences taken from them to be
+    # exact; every intended fused multiply-add is an explicit fmaf
+    "-ffp-contract=off",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wall", "-Wno-unused-function",
 ]

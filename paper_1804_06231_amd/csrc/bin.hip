@@ -1,14 +1,15 @@
 // Cell binning: a counting sort of the particles into the cells of each box
 // (Section 2 of the paper: cells of edge >= the cut-off, each cell's particles
-// stored together), finished by a per-cell sort on the original index so that
-// the cell-ordered layout does not depend on atomic arrival order.
+// stored together), finished by a per-cell sort on (x, original index): the
+// cell-ordered layout then depends neither on atomic arrival order nor on the
+// order of the input, and consecutive particles of a cell form x-slabs.
 //
 //   k_box_hmax    max cut-off per box (auto grid)
 //   k_bin_count   cell of every particle, per-cell counts and max cut-off
 //   k_scan        exclusive scan of the counts -> cell_start; occupancy check
 //   k_scatter     particles -> scatter-ordered staging records
-//   k_cell_finish per cell: order by original index, shift positions to the
-//                 cell origin, write the cell-ordered structure of arrays
+//   k_cell_finish per cell: order by (x, original index), shift positions to
+//                 the cell origin, write the cell-ordered structure of arrays
 #include "device_util.h"
 
 namespace pvl {
@@ -144,11 +145,13 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
     int cx = local / (B.g[2] * B.g[1]);
     float ox = (float)cx * B.edge[0], oy = (float)cy * B.edge[1], oz = (float)cz * B.edge[2];
     int P2 = next_pow2(cnt);
+    // sort by cell-relative x (ordered bits) with the arrival slot as payload;
+    // runs of equal x are then ordered by original index (unique)
     for (int r = threadIdx.x; r < P2; r += blockDim.x) {
         uint64_t k = ~0ull;
         if (r < cnt) {
-            uint32_t o = (uint32_t)__float_as_int(stage2[s0 + r].y);
-            k = ((uint64_t)o << 32) | (uint32_t)r;
+            float xr = stage[s0 + r].x - ox;
+            k = ((uint64_t)float_to_ordered(xr) << 32) | (uint32_t)r;
         }
         keys[r] = k;
     }
@@ -156,12 +159,21 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
     bitonic_sort_segments(keys, P2, 1);
     uint32_t hm = 0u;
     for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-        int slot = s0 + (int)(keys[r] & 0xffffffffu);
+        const uint64_t key = keys[r];
+        const uint32_t xb = (uint32_t)(key >> 32);
+        const int slot = s0 + (int)(key & 0xffffffffu);
+        const int my_orig = __float_as_int(stage2[slot].y);
+        int lo = r, hi = r + 1;
+        while (lo > 0 && (uint32_t)(keys[lo - 1] >> 32) == xb) --lo;
+        while (hi < cnt && (uint32_t)(keys[hi] >> 32) == xb) ++hi;
+        int rank = lo;
+        for (int q = lo; q < hi; ++q)
+            rank += __float_as_int(stage2[s0 + (int)(keys[q] & 0xffffffffu)].y) < my_orig;
         float4 a = stage[slot];
         float2 b = stage2[slot];
-        xyzm[s0 + r] = make_float4(a.x - ox, a.y - oy, a.z - oz, b.x);
-        Hout[s0 + r] = a.w;
-        orig[s0 + r] = __float_as_int(b.y);
+        xyzm[s0 + rank] = make_float4(a.x - ox, a.y - oy, a.z - oz, b.x);
+        Hout[s0 + rank] = a.w;
+        orig[s0 + rank] = my_orig;
         hm = max(hm, __float_as_uint(a.w));
     }
     // largest cut-off of the cell (positive floats order as their bits)

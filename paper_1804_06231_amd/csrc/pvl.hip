@@ -61,7 +61,8 @@ hipError_t dev_alloc(T **p, int64_t count)
 void free_dev(DevCells &d)
 {
     void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cursor, d.cellid, d.slot, d.stage,
-                    d.stage2, d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax};
+                    d.stage2, d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
+                    d.items, d.qcount};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DevCells();
@@ -94,6 +95,8 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.sidx, 13 * N);
     ALLOC(d.skey, 13 * N);
     ALLOC(d.gcell, N);
+    ALLOC(d.items, pvl::queue_capacity(N, C));
+    ALLOC(d.qcount, 4);
 #undef ALLOC
     if (e != hipSuccess) {
         free_dev(c->d);
@@ -149,6 +152,9 @@ pv_status pv_create(int device, void *hip_stream, pv_ctx **out)
         pv_destroy(ctx);
         return PV_ENOMEM;
     }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->tune.num_cu = prop.multiProcessorCount;
     if (hipMemset(ctx->dflags, 0, 4 * sizeof(int)) != hipSuccess ||
         hipMemset(ctx->dcensus, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -468,10 +474,9 @@ pv_status pv_set_param(pv_ctx *ctx, pv_param param, int value)
     switch (param) {
     case PV_PARAM_REACH_ORDER: ctx->tune.reach_order = value ? 1 : 0; return PV_OK;
     case PV_PARAM_TASK_SORT: ctx->tune.task_sort = value ? 1 : 0; return PV_OK;
-    case PV_PARAM_TILED_MAX:
-        if (value < 0 || value > pvl::kTiledMaxCell)
-            return fail(ctx, PV_EINVAL, "tiled_max must be 0.." + std::to_string(pvl::kTiledMaxCell));
-        ctx->tune.tiled_max = value;
+    case PV_PARAM_QUEUE_WGS:
+        if (value < 1 || value > 32) return fail(ctx, PV_EINVAL, "queue_wgs must be 1..32");
+        ctx->tune.queue_wgs_per_cu = value;
         return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
@@ -483,7 +488,7 @@ pv_status pv_get_param(pv_ctx *ctx, pv_param param, int *value)
     switch (param) {
     case PV_PARAM_REACH_ORDER: *value = ctx->tune.reach_order; return PV_OK;
     case PV_PARAM_TASK_SORT: *value = ctx->tune.task_sort; return PV_OK;
-    case PV_PARAM_TILED_MAX: *value = ctx->tune.tiled_max; return PV_OK;
+    case PV_PARAM_QUEUE_WGS: *value = ctx->tune.queue_wgs_per_cu; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }

@@ -19,8 +19,6 @@ constexpr int kBlock = 256;
 // Device error bits.
 constexpr int kErrOverflow = 1;
 constexpr int kErrGrid = 2;
-// Largest cell the tiled sweep handles in one workgroup (larger: scalar sweep).
-constexpr int kTiledMaxCell = 512;
 
 // One periodic box of a (possibly batched) cell structure, as the kernels see it.
 struct BoxDesc {
@@ -87,6 +85,8 @@ struct DevCells {
     uint16_t *sidx = nullptr;     // 13 x n: in-cell rank lists, ascending key
     float *skey = nullptr;        // 13 x n: the keys in that order
     float *gcell = nullptr;       // n: upstream gradient in cell order (adjoint)
+    int2 *items = nullptr;        // work queue of (cell, receiver chunk)
+    int *qcount = nullptr;        // [0] large-cell chunks, [1] single-chunk cells, [2] head
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
 };
 
@@ -101,8 +101,12 @@ hipError_t launch_zero(hipStream_t st, void *p, int64_t words);
 struct SweepTuning {
     int reach_order = 0;
     int task_sort = 1;
-    int tiled_max = kTiledMaxCell;
+    int queue_wgs_per_cu = 4;   // persistent workgroups per compute unit
+    int num_cu = 256;           // compute units of the device
 };
+
+// Entries of the work queue for n particles in ncell cells.
+int queue_capacity(int64_t n, int64_t ncell);
 
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,

@@ -12,7 +12,9 @@
 //
 // Both kernels run one workgroup per receiver cell and finish in place: the
 // self term is added, the sums are normalised and written in the caller's
-// original particle order, so no separate finalisation pass is needed.
+// original particle order, so no separate finalisation pass is needed.  They
+// test exactly the pairs the paper's bounds admit, one receiver per lane, and
+// serve as the candidate census; the production sweeps are the tiled ones.
 #include "device_util.h"
 
 namespace pvl {
@@ -229,30 +231,20 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
                         const SweepTuning &tune)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
-    if (algo == PV_PLAIN_CELL && census) {
-        hipLaunchKernelGGL(k_sweep_plain, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                           c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, rho, wcount, drho_dh,
-                           ncount, dflags, census, 0);
-    } else if (algo == PV_PLAIN_CELL) {
-        hipError_t e = launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags,
-                                          tune, true);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_sweep_plain, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                           c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, rho, wcount, drho_dh,
-                           ncount, dflags, census, tune.tiled_max);
-    } else if (census) {
+    if (census) {
         // the census counts the candidates of the exact per-receiver bounds
-        hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                           c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n, rho,
-                           wcount, drho_dh, ncount, dflags, census, 0);
+        // (scalar kernels: one receiver per lane, no tiles)
+        if (algo == PV_PLAIN_CELL)
+            hipLaunchKernelGGL(k_sweep_plain, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                               c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, rho, wcount,
+                               drho_dh, ncount, dflags, census, 0);
+        else
+            hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                               c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n,
+                               rho, wcount, drho_dh, ncount, dflags, census, 0);
     } else {
-        hipError_t e = launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags,
-                                          tune, false);
-        if (e != hipSuccess) return e;
-        // cells too large for the tiled workgroup
-        hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                           c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n, rho,
-                           wcount, drho_dh, ncount, dflags, census, tune.tiled_max);
+        return launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags, tune,
+                                  algo == PV_PLAIN_CELL);
     }
     return hipGetLastError();
 }

@@ -1,4 +1,4 @@
-// Tiled pseudo-Verlet density sweep for wave64.
+// Tiled pseudo-Verlet density sweep for wave64, fed by a device work queue.
 //
 // The paper's SIMD strategy (Section 3.1) holds one receiver and streams a
 // vector of sources past it; its loop bounds (Section 3.3: first_a and the
@@ -15,38 +15,47 @@
 //     fetched once per 16 pair tests;
 //   * a row's task is (neighbour direction, block of 16 receivers); its number
 //     of source tiles is the paper's bound taken for the block: the sources up
-//     to the largest key + cut-off of its receivers.  Receivers are ordered by
-//     that reach (key + H toward a neighbour ahead on the axis, key - H toward
-//     one behind) rather than by key, so the 16 bounds of a block are close;
-//   * tasks run longest first, four to a wave, so the rows of a wave finish
-//     together;
+//     to the largest key + cut-off of its receivers (optionally the receivers
+//     are first ordered by that reach);
 //   * receivers past first_a (none of their candidates can be in range, judged
-//     with the cell's largest cut-off) get no task.
+//     with the cell's largest cut-off) get no task;
+//   * tasks run longest first, four to a wave, so the rows of a wave finish
+//     together.
 //
-// The receiver's own cell (which the paper does not treat) uses the same
-// tiles on the cell's sorted list along x: a block of 16 receivers only meets
-// the source tiles whose keys lie within the block's key range widened by its
-// largest cut-off on both sides.  Each wave accumulates its
-// rows in registers and adds them, once per task, into its own LDS array;
-// the four arrays are summed in a fixed order at the end, so the result does
-// not depend on timing.  One workgroup (4 waves) per cell of at most
-// kTiledMaxCell receivers; larger cells go through the scalar sweep.
+// The receiver's own cell (which the paper does not treat) uses the same tiles
+// in cell order, which is x order: a block of 16 receivers meets only the
+// source tiles whose x lies within the block's range widened by its largest
+// cut-off on both sides.
+//
+// Work items are (cell, chunk of at most kChunk receivers); a cell's chunks are
+// consecutive x-slabs.  For a chunk of a large cell the active receivers of
+// every direction are compacted out of the cell's sorted lists in order.
+// Persistent workgroups take items from a device queue that lists the chunks
+// of large cells first, so uneven occupancy and many boxes of different sizes
+// share one launch.  Each wave adds its rows' sums, once per task, into its
+// own LDS array; the four arrays are summed in a fixed order at the end, so
+// the result does not depend on timing or on which workgroup took the item.
+//
+// PLAIN = true gives the plain cell-list comparator on the same tiles: every
+// receiver meets every particle of the 27 cells, in cell order, with no sorted
+// lists and no pruning (Listing 1).
 #include "device_util.h"
 
 namespace pvl {
 
-// Per size class MAXC (largest cell handled by one workgroup): task slots and
-// receivers (over all 26 directions) that can be ordered by reach in LDS.
-template <int MAXC> struct TiledLimits {
-    static constexpr int tasks = 27 * (MAXC / 16);
-    static constexpr int recv = 6 * MAXC;
-    static_assert(recv * 10 <= 4 * MAXC * 16, "set-up arrays alias the accumulators");
-};
+constexpr int kChunk = 256;                    // receivers per work item
+constexpr int kMaxTasks = 27 * (kChunk / 16);  // task slots per item
+constexpr int kMaxRecv = 26 * kChunk;          // compacted receiver lists per item
+constexpr int kSelfAxis = 4;                   // d = (1, 0, 0): cell order is x order
 
+// Value of lane (l + K) mod 16 of the same 16-lane row (DPP row_ror:K).
 template <int K>
 __device__ __forceinline__ float ror16(float v)
 {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + K, 0xf, 0xf, true));
+    if constexpr (K == 0)
+        return v;
+    else
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + K, 0xf, 0xf, true));
 }
 
 struct TileAcc {
@@ -59,8 +68,10 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH, Ti
     float u2 = u * u;
     float v = 1.0f - u;
     float v2 = v * v;
+    // inner piece (u < 1/2): w = 1 - 6u^2 + 6u^3, 3w + u w' = 3 - 30u^2 + 36u^3
     float wi = fmaf(u2, fmaf(6.0f, u, -6.0f), 1.0f);
     float di = fmaf(u2, fmaf(36.0f, u, -30.0f), 3.0f);
+    // outer piece: w = 2 (1-u)^3, 3w + u w' = 6 (1-u)^2 (1 - 2u)
     float wo = 2.0f * v2 * v;
     float dout = v2 * fmaf(-12.0f, u, 6.0f);
     bool in = u < 0.5f;
@@ -82,71 +93,83 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH, Ti
         if (r2 < H2) tile_interact(r2, mj, invH, acc);                    \
     }
 
-// Task word: bits 0-8 source tiles, 9-14 receiver block, 15-19 direction
-// (0..25 neighbour, 26 = own cell), 20-28 first source tile.
+// Task word: bits 0-8 source tiles, 9-13 receiver block, 14-18 direction
+// (0..25 neighbour, 26 = own cell), 19-27 first source tile.
 __device__ __forceinline__ uint32_t pack_task(int dir, int blk, int nt, int t0)
 {
-    return (uint32_t)nt | ((uint32_t)blk << 9) | ((uint32_t)dir << 15) | ((uint32_t)t0 << 20);
+    return (uint32_t)nt | ((uint32_t)blk << 9) | ((uint32_t)dir << 14) | ((uint32_t)t0 << 19);
 }
 
-// Axis of the own-cell sort: d = (1, 0, 0).
-constexpr int kSelfAxis = 4;
-
-__device__ __forceinline__ int nb_offset(int dir, int &dx, int &dy, int &dz)
+__device__ __forceinline__ void nb_offset(int dir, int &dx, int &dy, int &dz)
 {
     int o = dir < 13 ? dir : dir + 1;   // skip the centre of the 3x3x3 block
     dx = o / 9 - 1;
     dy = (o / 3) % 3 - 1;
     dz = o % 3 - 1;
-    return o;
 }
 
-// PLAIN = true gives the plain cell-list comparator on the same tiles: every
-// receiver of the cell meets every particle of the 27 cells, in cell order,
-// with no sorted lists and no pruning (Listing 1).
-template <int MAXC, bool PLAIN>
-__global__ void __launch_bounds__(kBlock) k_sweep_tiled(
-    const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
-    const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
-    const float *__restrict__ Hc, const uint32_t *__restrict__ cell_hmax,
-    const int32_t *__restrict__ orig, const uint16_t *__restrict__ sidx,
-    const float *__restrict__ skey, int64_t n, float *rho, float *wcount, float *drho_dh,
-    int32_t *ncount, const int *__restrict__ dflags, int min_na, int max_na, int reach_order,
-    int task_sort)
-{
-    constexpr int kTiledMaxRecv = TiledLimits<MAXC>::recv;
-    constexpr int kTiledMaxTasks = TiledLimits<MAXC>::tasks;
-    // per-wave accumulators; during set-up the same bytes hold the receiver
-    // reach values and indices being sorted
-    __shared__ float4 acc_lds[4][MAXC];
-    __shared__ uint16_t rlist[kTiledMaxRecv];
-    __shared__ uint32_t tasks[kTiledMaxTasks];
-    __shared__ uint16_t torder[kTiledMaxTasks];
-    __shared__ int n_act[27];
-    __shared__ int task_off[28];
-    __shared__ int recv_off[27];
-    float *rv = reinterpret_cast<float *>(&acc_lds[0][0]);               // reach, key order
-    float *rvs = rv + kTiledMaxRecv;                                     // reach, sorted
-    uint16_t *ria = reinterpret_cast<uint16_t *>(rvs + kTiledMaxRecv);   // receiver, key order
+struct SweepArgs {
+    const BoxDesc *box;
+    const int32_t *cell_box;
+    const int32_t *start;
+    const float4 *xyzm;
+    const float *Hc;
+    const uint32_t *cell_hmax;
+    const int32_t *orig;
+    const uint16_t *sidx;
+    const float *skey;
+    int64_t n;
+    float *rho, *wcount, *drho_dh;
+    int32_t *ncount;
+    const int *dflags;
+    const int2 *items;   // queue: [0, nbig) large-cell chunks, [cap - nsmall, cap) cells
+    const int *qcount;   // [0] nbig, [1] nsmall
+    int *head;           // items taken after the first static round
+    int cap;
+    int reach_order;
+    int task_sort;
+};
 
-    if (dflags[0]) return;
-    const int a = blockIdx.x;
-    const int sa = start[a];
-    const int na = start[a + 1] - sa;
-    if (na <= min_na || na > max_na) return;
-    const BoxDesc &B = box[cell_box[a]];
+struct SweepLds {
+    float4 acc[4][kChunk];       // per-wave receiver sums; aliased during set-up
+    uint16_t rlist[kMaxRecv];    // receivers per direction (compacted or reach-ordered)
+    uint32_t tasks[kMaxTasks];
+    uint16_t torder[kMaxTasks];
+    int n_act[27];
+    int act_cell[26];
+    int task_off[28];
+    int recv_off[27];
+    int wsum[4];
+    int flag;
+    int item;
+};
+
+template <bool PLAIN>
+__device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
+{
+    const int64_t n = A.n;
+    const int sa = A.start[a];
+    const int na = A.start[a + 1] - sa;
+    const int r_lo = chunk * kChunk;
+    const int r_hi = min(r_lo + kChunk, na);
+    const int nr = r_hi - r_lo;
+    const bool whole = na <= kChunk;
+    const BoxDesc &B = A.box[A.cell_box[a]];
     const CellGeom ga = cell_geom(B, a);
     const float slack = 1.52587890625e-5f * (B.edge[0] + B.edge[1] + B.edge[2]);
-    const float hmax_a = __uint_as_float(cell_hmax[a]);
+    const float hmax_a = __uint_as_float(A.cell_hmax[a]);
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const uint16_t *sidx = A.sidx;
+    const float *skey = A.skey;
 
-    // receivers of each direction that can have a candidate (first_a)
+    // receivers of each direction that can have a candidate (first_a), whole cell
     if (tid < 26) {
         int dx, dy, dz;
         nb_offset(tid, dx, dy, dz);
         float sx, sy, sz;
         int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
-        int sb = start[b], nb = start[b + 1] - sb;
+        int sb = A.start[b], nb = A.start[b + 1] - sb;
         int act = 0;
         if (PLAIN) {
             act = nb > 0 ? na : 0;
@@ -172,69 +195,118 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
                 act = lo;
             }
         }
-        n_act[tid] = act;
+        L.act_cell[tid] = act;
     }
-    if (tid == 26) n_act[26] = na;
+    __syncthreads();
+
+    // active receivers of this chunk, per direction
+    bool listed = false;   // receivers taken from L.rlist
+    if (PLAIN) {
+        if (tid < 26) L.n_act[tid] = L.act_cell[tid] > 0 ? nr : 0;
+    } else if (whole) {
+        if (tid < 26) L.n_act[tid] = L.act_cell[tid];
+        if (tid == 0) {
+            int roff = 0;
+            for (int d = 0; d < 26; ++d) {
+                L.recv_off[d] = roff;
+                roff += L.act_cell[d];
+            }
+            L.flag = (A.reach_order && roff <= kMaxRecv) ? 1 : 0;
+        }
+        __syncthreads();
+        listed = L.flag != 0;
+        if (listed) {
+            // order each direction's receivers by how far past the shared face
+            // their cut-off reaches (key + H toward a neighbour ahead on the
+            // axis, key - H toward one behind); the set-up arrays borrow the
+            // accumulator space
+            float *rv = reinterpret_cast<float *>(&L.acc[0][0]);
+            uint16_t *ria = reinterpret_cast<uint16_t *>(rv + kMaxRecv);
+            const int nrecv = L.recv_off[25] + L.act_cell[25];
+            for (int q = tid; q < nrecv; q += blockDim.x) {
+                int dir = 0;
+                while (dir < 25 && L.recv_off[dir + 1] <= q) ++dir;
+                int r = q - L.recv_off[dir];
+                int dx, dy, dz, sign;
+                nb_offset(dir, dx, dy, dz);
+                int s = dir_canon(dx, dy, dz, &sign);
+                int qs = sign > 0 ? na - 1 - r : r;
+                int ia = sidx[(size_t)s * n + sa + qs];
+                float k = skey[(size_t)s * n + sa + qs];
+                float H = A.Hc[sa + ia];
+                rv[q] = sign > 0 ? -(k + H) : (k - H);
+                ria[q] = (uint16_t)ia;
+            }
+            __syncthreads();
+            for (int q = tid; q < nrecv; q += blockDim.x) {
+                int dir = 0;
+                while (dir < 25 && L.recv_off[dir + 1] <= q) ++dir;
+                int o = L.recv_off[dir], r = q - o, m = L.act_cell[dir];
+                float v = rv[q];
+                int rank = 0;
+                for (int k = 0; k < m; ++k) {
+                    float w = rv[o + k];
+                    rank += (w < v) || (w == v && k < r);
+                }
+                L.rlist[o + rank] = ria[q];
+            }
+        }
+    } else {
+        // compact, in interface-first order, the active receivers that belong to
+        // this chunk (in-cell rank in [r_lo, r_hi)); one direction at a time
+        listed = true;
+        int roff = 0;
+        for (int d = 0; d < 26; ++d) {
+            const int act = L.act_cell[d];
+            int dx, dy, dz, sign;
+            nb_offset(d, dx, dy, dz);
+            const int s = dir_canon(dx, dy, dz, &sign);
+            int cnt = 0;
+            for (int base = 0; base < act; base += blockDim.x) {
+                const int q = base + tid;
+                int ia = -1;
+                if (q < act) ia = sidx[(size_t)s * n + sa + (sign > 0 ? na - 1 - q : q)];
+                const bool keep = ia >= r_lo && ia < r_hi;
+                const uint64_t m = __ballot(keep);
+                if (lane == 0) L.wsum[wave] = __popcll(m);
+                __syncthreads();
+                int before = 0, total = 0;
+                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                    before += w < wave ? L.wsum[w] : 0;
+                    total += L.wsum[w];
+                }
+                const int pos = before + (int)__builtin_amdgcn_mbcnt_hi(
+                                             (uint32_t)(m >> 32),
+                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                if (keep) L.rlist[roff + cnt + pos] = (uint16_t)ia;
+                cnt += total;
+                __syncthreads();
+            }
+            if (tid == 0) {
+                L.n_act[d] = cnt;
+                L.recv_off[d] = roff;
+            }
+            roff += cnt;
+        }
+    }
+    if (tid == 0) L.n_act[26] = nr;
     __syncthreads();
     if (tid == 0) {
-        int off = 0, roff = 0;
+        int off = 0;
         for (int d = 0; d < 27; ++d) {
-            task_off[d] = off;
-            off += (n_act[d] + 15) >> 4;
-            if (d < 26) {
-                recv_off[d] = roff;
-                roff += n_act[d];
-            }
+            L.task_off[d] = off;
+            off += (L.n_act[d] + 15) >> 4;
         }
-        task_off[27] = off;
-        // reach ordering needs room for every active receiver
-        recv_off[26] = (!PLAIN && reach_order && roff <= kTiledMaxRecv) ? roff : -1;
+        L.task_off[27] = off;
     }
     __syncthreads();
-    const int ntask = task_off[27];
-    const bool by_reach = recv_off[26] >= 0;
-    const int nrecv = by_reach ? recv_off[26] : 0;
-
-    // Order each direction's active receivers by how far past the shared face
-    // their cut-off reaches (key + H toward a neighbour ahead, key - H toward
-    // one behind), so a block of 16 has nearly equal loop bounds.
-    if (by_reach) {
-        for (int q = tid; q < nrecv; q += blockDim.x) {
-            int dir = 0;
-            while (dir < 25 && recv_off[dir + 1] <= q) ++dir;
-            int r = q - recv_off[dir];
-            int dx, dy, dz, sign;
-            nb_offset(dir, dx, dy, dz);
-            int s = dir_canon(dx, dy, dz, &sign);
-            int qs = sign > 0 ? na - 1 - r : r;
-            int ia = sidx[(size_t)s * n + sa + qs];
-            float k = skey[(size_t)s * n + sa + qs];
-            float H = Hc[sa + ia];
-            rv[q] = sign > 0 ? -(k + H) : (k - H);
-            ria[q] = (uint16_t)ia;
-        }
-        __syncthreads();
-        for (int q = tid; q < nrecv; q += blockDim.x) {
-            int dir = 0;
-            while (dir < 25 && recv_off[dir + 1] <= q) ++dir;
-            int o = recv_off[dir], r = q - o, m = n_act[dir];
-            float v = rv[q];
-            int rank = 0;
-            for (int k = 0; k < m; ++k) {
-                float w = rv[o + k];
-                rank += (w < v) || (w == v && k < r);
-            }
-            rlist[o + rank] = ria[q];
-            rvs[o + rank] = v;
-        }
-        __syncthreads();
-    }
+    const int ntask = L.task_off[27];
 
     // source tiles of every task: the paper's bound for the block of receivers
     for (int t = tid; t < ntask; t += blockDim.x) {
         int dir = 0;
-        while (task_off[dir + 1] <= t) ++dir;
-        int blk = t - task_off[dir];
+        while (L.task_off[dir + 1] <= t) ++dir;
+        const int blk = t - L.task_off[dir];
         int nt, t0 = 0;
         if (PLAIN) {
             int nb = na;
@@ -243,23 +315,22 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
                 nb_offset(dir, dx, dy, dz);
                 float sx, sy, sz;
                 int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
-                nb = start[b + 1] - start[b];
+                nb = A.start[b + 1] - A.start[b];
             }
             nt = (nb + 15) >> 4;
         } else if (dir == 26) {
-            // two-sided window on the x-sorted list: |key_j - key_i| < H_i
+            // two-sided window in x over the whole cell: |x_j - x_i| < H_i
             const float *ka = skey + (size_t)kSelfAxis * n + sa;
-            const uint16_t *ia = sidx + (size_t)kSelfAxis * n + sa;
-            int r0 = blk * 16, r1 = min(r0 + 16, na);
+            const int r0 = r_lo + blk * 16, r1 = min(r0 + 16, r_hi);
             float hb = 0.0f;
-            for (int r = r0; r < r1; ++r) hb = fmaxf(hb, Hc[sa + ia[r]]);
-            float lo_k = ka[r0] - hb - slack, hi_k = ka[r1 - 1] + hb + slack;
+            for (int r = r0; r < r1; ++r) hb = fmaxf(hb, A.Hc[sa + r]);
+            const float lo_k = ka[r0] - hb - slack, hi_k = ka[r1 - 1] + hb + slack;
             int lo = 0, hi = na;
             while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] <= lo_k) lo = m + 1; else hi = m; }
-            int j0 = lo;
+            const int j0 = lo;
             lo = 0; hi = na;
             while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] < hi_k) lo = m + 1; else hi = m; }
-            int j1 = lo;
+            const int j1 = lo;
             t0 = j0 >> 4;
             nt = ((j1 + 15) >> 4) - t0;
         } else {
@@ -267,30 +338,31 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
             nb_offset(dir, dx, dy, dz);
             float sx, sy, sz;
             int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
-            int sb = start[b], nb = start[b + 1] - sb;
+            int sb = A.start[b], nb = A.start[b + 1] - sb;
             int sign;
             int s = dir_canon(dx, dy, dz, &sign);
             float e[3];
             dir_axis(s, e);
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
             const float *ka = skey + (size_t)s * n + sa;
-            const uint16_t *ia = sidx + (size_t)s * n + sa;
+            const uint16_t *il = sidx + (size_t)s * n + sa;
             const float *kb = skey + (size_t)s * n + sb;
-            int r0 = blk * 16, r1 = min(r0 + 16, n_act[dir]);
+            const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[dir]);
             // block reach: the largest key + H (ahead) or smallest key - H (behind)
-            float T;
-            if (by_reach) {
-                float v = rvs[recv_off[dir] + r0];
-                T = sign > 0 ? -v : v;
-            } else if (sign > 0) {
-                T = -INFINITY;
-                for (int r = r0; r < r1; ++r) {
-                    int q = na - 1 - r;
-                    T = fmaxf(T, ka[q] + Hc[sa + ia[q]]);
+            float T = sign > 0 ? -INFINITY : INFINITY;
+            for (int r = r0; r < r1; ++r) {
+                float k, H;
+                if (listed) {
+                    int ia = L.rlist[L.recv_off[dir] + r];
+                    float4 p = A.xyzm[sa + ia];
+                    k = proj_key(p.x, p.y, p.z, s);
+                    H = A.Hc[sa + ia];
+                } else {
+                    int q = sign > 0 ? na - 1 - r : r;
+                    k = ka[q];
+                    H = A.Hc[sa + il[q]];
                 }
-            } else {
-                T = INFINITY;
-                for (int r = r0; r < r1; ++r) T = fminf(T, ka[r] - Hc[sa + ia[r]]);
+                T = sign > 0 ? fmaxf(T, k + H) : fminf(T, k - H);
             }
             int nsrc;
             if (sign > 0) {
@@ -306,61 +378,58 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
             }
             nt = (nsrc + 15) >> 4;
         }
-        tasks[t] = pack_task(dir, blk, nt, t0);
+        L.tasks[t] = pack_task(dir, blk, nt, t0);
     }
     __syncthreads();
     // longest tasks first, so the four rows of a wave carry similar loads
     for (int t = tid; t < ntask; t += blockDim.x) {
         int rank = t;
-        if (task_sort) {
-            int nt = (int)(tasks[t] & 511u);
+        if (A.task_sort) {
+            const int nt = (int)(L.tasks[t] & 511u);
             rank = 0;
             for (int q = 0; q < ntask; ++q) {
-                int nq = (int)(tasks[q] & 511u);
+                const int nq = (int)(L.tasks[q] & 511u);
                 rank += (nq > nt) || (nq == nt && q < t);
             }
         }
-        torder[rank] = (uint16_t)t;
+        L.torder[rank] = (uint16_t)t;
     }
-    for (int t = tid; t < 4 * MAXC; t += blockDim.x)
-        (&acc_lds[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int t = tid; t < 4 * kChunk; t += blockDim.x)
+        (&L.acc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 
     // tasks in groups of 4 (one per row); group g runs on wave g % 4
-    const int wave = tid >> 6;
-    const int lane = tid & 63;
     const int row = lane >> 4;
     const int l16 = lane & 15;
     for (int g = wave; g * 4 < ntask; g += 4) {
         const int t = g * 4 + row;
         const bool row_valid = t < ntask;
-        uint32_t tw = row_valid ? tasks[torder[t]] : 0u;
-        int nt = row_valid ? (int)(tw & 511u) : 0;
-        int blk = (int)((tw >> 9) & 63u);
-        int dir = (int)((tw >> 15) & 31u);
-        const int t0 = (int)(tw >> 20);
+        const uint32_t tw = row_valid ? L.tasks[L.torder[t]] : 0u;
+        const int nt = row_valid ? (int)(tw & 511u) : 0;
+        const int blk = (int)((tw >> 9) & 31u);
+        const int dir = (int)((tw >> 14) & 31u);
+        const int t0 = (int)(tw >> 19);
         // receiver of this lane and the source list of its row
         int dx = 0, dy = 0, dz = 0, sb = sa, nb = na, sign = 1, s = kSelfAxis;
         float shx = 0.f, shy = 0.f, shz = 0.f;
         if (dir < 26) {
             nb_offset(dir, dx, dy, dz);
             int b = neighbour(B, ga, dx, dy, dz, shx, shy, shz);
-            sb = start[b];
-            nb = start[b + 1] - sb;
+            sb = A.start[b];
+            nb = A.start[b + 1] - sb;
             s = dir_canon(dx, dy, dz, &sign);
         }
         const int r = blk * 16 + l16;
-        const bool recv_ok = row_valid && r < n_act[dir];
+        const bool recv_ok = row_valid && r < L.n_act[dir];
         int ia = 0;
         if (recv_ok) {
-            if (PLAIN) ia = r;
-            else if (dir == 26) ia = sidx[(size_t)s * n + sa + r];
-            else if (by_reach) ia = rlist[recv_off[dir] + r];
+            if (PLAIN || dir == 26) ia = r_lo + r;
+            else if (listed) ia = L.rlist[L.recv_off[dir] + r];
             else if (sign > 0) ia = sidx[(size_t)s * n + sa + (na - 1 - r)];
             else ia = sidx[(size_t)s * n + sa + r];
         }
-        float4 pi = recv_ok ? xyzm[sa + ia] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float Hi = recv_ok ? Hc[sa + ia] : 0.0f;
+        const float4 pi = recv_ok ? A.xyzm[sa + ia] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float Hi = recv_ok ? A.Hc[sa + ia] : 0.0f;
         const float H2 = Hi * Hi;
         const float invH = recv_ok ? 1.0f / Hi : 0.0f;
         // pair frame: receiver moved for +1 offsets, source for -1 offsets
@@ -370,7 +439,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
         const float ux = dx < 0 ? shx : 0.0f;
         const float uy = dy < 0 ? shy : 0.0f;
         const float uz = dz < 0 ? shz : 0.0f;
-        const uint16_t *lb = PLAIN ? nullptr : sidx + (size_t)s * n + sb;
+        const uint16_t *lb = sidx + (size_t)s * n + sb;
+        // the own cell's diagonal tile pairs each receiver with itself at K = 0
+        const int diag = dir == 26 ? (r_lo >> 4) + blk : -1;
 
         int ntmax = nt;
         ntmax = max(ntmax, __shfl_xor(ntmax, 16));
@@ -381,19 +452,15 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
             const int j = tile * 16 + l16;
             float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.f);
             if (it < nt && j < nb) {
-                int p = PLAIN ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
-                q = xyzm[sb + p];
+                const int p = (PLAIN || dir == 26) ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
+                q = A.xyzm[sb + p];
                 q.x += ux;
                 q.y += uy;
                 q.z += uz;
             }
             const float sx = q.x, sy = q.y, sz = q.z, sm = q.w;
             if (it < nt) {
-                if (!(dir == 26 && tile == blk)) {
-                    float dx0 = sx - tx, dy0 = sy - ty, dz0 = sz - tz;
-                    float r2 = fmaf(dx0, dx0, fmaf(dy0, dy0, dz0 * dz0));
-                    if (r2 < H2) tile_interact(r2, sm, invH, acc);
-                }
+                if (tile != diag) PVL_TILE_STEP(0)
                 PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
                 PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
                 PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
@@ -401,7 +468,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
             }
         }
         if (recv_ok) {
-            float *dst = reinterpret_cast<float *>(&acc_lds[wave][ia]);
+            float *dst = reinterpret_cast<float *>(&L.acc[wave][ia - r_lo]);
             atomicAdd(dst + 0, acc.rho);
             atomicAdd(dst + 1, acc.wc);
             atomicAdd(dst + 2, acc.dh);
@@ -410,54 +477,105 @@ __global__ void __launch_bounds__(kBlock) k_sweep_tiled(
     }
     __syncthreads();
 
-    for (int i = tid; i < na; i += blockDim.x) {
-        float4 s0 = acc_lds[0][i], s1 = acc_lds[1][i], s2 = acc_lds[2][i], s3 = acc_lds[3][i];
-        float sr = ((s0.x + s1.x) + s2.x) + s3.x;
-        float sw = ((s0.y + s1.y) + s2.y) + s3.y;
-        float sd = ((s0.z + s1.z) + s2.z) + s3.z;
-        float sc = ((s0.w + s1.w) + s2.w) + s3.w;
-        float H = Hc[sa + i];
-        float mi = xyzm[sa + i].w;
-        float invH = 1.0f / H;
-        float norm = (8.0f / kPi) * invH * invH * invH;
-        int o = orig[sa + i];
-        if (rho) rho[o] = norm * (sr + mi);
-        if (wcount) wcount[o] = norm * (sw + 1.0f);
-        if (drho_dh) drho_dh[o] = -norm * (kGamma * invH) * (sd + 3.0f * mi);
-        if (ncount) ncount[o] = (int32_t)sc;
+    for (int i = tid; i < nr; i += blockDim.x) {
+        const float4 s0 = L.acc[0][i], s1 = L.acc[1][i], s2 = L.acc[2][i], s3 = L.acc[3][i];
+        const float sr = ((s0.x + s1.x) + s2.x) + s3.x;
+        const float sw = ((s0.y + s1.y) + s2.y) + s3.y;
+        const float sd = ((s0.z + s1.z) + s2.z) + s3.z;
+        const float sc = ((s0.w + s1.w) + s2.w) + s3.w;
+        const int p = sa + r_lo + i;
+        const float H = A.Hc[p];
+        const float mi = A.xyzm[p].w;
+        const float invH = 1.0f / H;
+        const float norm = (8.0f / kPi) * invH * invH * invH;
+        const int o = A.orig[p];
+        if (A.rho) A.rho[o] = norm * (sr + mi);                          // self: w(0) = 1
+        if (A.wcount) A.wcount[o] = norm * (sw + 1.0f);
+        if (A.drho_dh) A.drho_dh[o] = -norm * (kGamma * invH) * (sd + 3.0f * mi);  // 1/h = gamma/H
+        if (A.ncount) A.ncount[o] = (int32_t)sc;
     }
 }
+
+template <bool PLAIN>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) k_sweep_queue(SweepArgs A)
+{
+    __shared__ SweepLds L;
+    if (A.dflags[0]) return;
+    const int nbig = A.qcount[0], nsmall = A.qcount[1];
+    const int nitems = nbig + nsmall;
+    int item = blockIdx.x;
+    while (item < nitems) {
+        const int2 w = item < nbig ? A.items[item] : A.items[A.cap - nsmall + (item - nbig)];
+        sweep_item<PLAIN>(A, L, w.x, w.y);
+        __syncthreads();
+        if (threadIdx.x == 0) L.item = (int)gridDim.x + atomicAdd(A.head, 1);
+        __syncthreads();
+        item = L.item;
+    }
+}
+
+// Work items: the chunks of cells larger than one chunk at the front, in any
+// order; single-chunk cells at the back, counted from the end.
+__global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, int cap,
+                              int2 *__restrict__ items, int *__restrict__ qcount)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const int na = start[c + 1] - start[c];
+    if (na <= 0) return;
+    if (na > kChunk) {
+        const int nch = (na + kChunk - 1) / kChunk;
+        const int p = atomicAdd(&qcount[0], nch);
+        for (int k = 0; k < nch; ++k) items[p + k] = make_int2((int)c, k);
+    } else {
+        const int p = atomicAdd(&qcount[1], 1);
+        items[cap - 1 - p] = make_int2((int)c, 0);
+    }
+}
+
+int queue_capacity(int64_t n, int64_t ncell) { return (int)(ncell + n / kChunk + 1); }
 
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
                               const int *dflags, const SweepTuning &tune, bool plain)
 {
-    if (plain) {
-        int tmax = tune.tiled_max < 0 ? 0 : (tune.tiled_max > kTiledMaxCell ? kTiledMaxCell : tune.tiled_max);
-        hipLaunchKernelGGL((k_sweep_tiled<256, true>), dim3((unsigned)ncell), dim3(kBlock), 0, st,
-                           c.box, c.cell_box, c.cell_start, c.xyzm, c.H, c.cell_hmax, c.orig,
-                           c.sidx, c.skey, n, rho, wcount, drho_dh, ncount, dflags, 0,
-                           tmax < 256 ? tmax : 256, 0, tune.task_sort);
-        if (tmax > 256)
-            hipLaunchKernelGGL((k_sweep_tiled<kTiledMaxCell, true>), dim3((unsigned)ncell),
-                               dim3(kBlock), 0, st, c.box, c.cell_box, c.cell_start, c.xyzm, c.H,
-                               c.cell_hmax, c.orig, c.sidx, c.skey, n, rho, wcount, drho_dh,
-                               ncount, dflags, 256, tmax, 0, tune.task_sort);
-        return hipGetLastError();
-    }
     if (ncell == 0 || n == 0) return hipSuccess;
-    int tmax = tune.tiled_max < 0 ? 0 : (tune.tiled_max > kTiledMaxCell ? kTiledMaxCell : tune.tiled_max);
-    // two size classes: the common small cells run with half the LDS, hence
-    // more workgroups per compute unit
-    hipLaunchKernelGGL((k_sweep_tiled<256, false>), dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.xyzm, c.H, c.cell_hmax, c.orig, c.sidx, c.skey,
-                       n, rho, wcount, drho_dh, ncount, dflags, 0, tmax < 256 ? tmax : 256,
-                       tune.reach_order, tune.task_sort);
-    if (tmax > 256)
-        hipLaunchKernelGGL((k_sweep_tiled<kTiledMaxCell, false>), dim3((unsigned)ncell), dim3(kBlock), 0, st,
-                           c.box, c.cell_box, c.cell_start, c.xyzm, c.H, c.cell_hmax, c.orig,
-                           c.sidx, c.skey, n, rho, wcount, drho_dh, ncount, dflags, 256, tmax,
-                           tune.reach_order, tune.task_sort);
+    const int cap = queue_capacity(n, ncell);
+    // qcount[0..1] and the head counter (qcount[2]) start at zero
+    hipError_t e = launch_zero(st, c.qcount, 3);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_queue_items, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st,
+                       c.cell_start, ncell, cap, c.items, c.qcount);
+    SweepArgs A;
+    A.box = c.box;
+    A.cell_box = c.cell_box;
+    A.start = c.cell_start;
+    A.xyzm = c.xyzm;
+    A.Hc = c.H;
+    A.cell_hmax = c.cell_hmax;
+    A.orig = c.orig;
+    A.sidx = c.sidx;
+    A.skey = c.skey;
+    A.n = n;
+    A.rho = rho;
+    A.wcount = wcount;
+    A.drho_dh = drho_dh;
+    A.ncount = ncount;
+    A.dflags = dflags;
+    A.items = c.items;
+    A.qcount = c.qcount;
+    A.head = c.qcount + 2;
+    A.cap = cap;
+    A.reach_order = tune.reach_order;
+    A.task_sort = tune.task_sort;
+    // persistent workgroups: a few per compute unit, never more than the cells
+    int64_t grid = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
+    if (grid > ncell) grid = ncell;
+    if (grid < 1) grid = 1;
+    if (plain)
+        hipLaunchKernelGGL(k_sweep_queue<true>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    else
+        hipLaunchKernelGGL(k_sweep_queue<false>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     return hipGetLastError();
 }
 

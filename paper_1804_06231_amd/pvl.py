@@ -29,7 +29,7 @@ EXPORTS = (
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
     "pv_free_cells", "pv_set_param", "pv_get_param",
 )
-PARAMS = {"reach_order": 1, "task_sort": 2, "tiled_max": 3}
+PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3}
 
 _STATUS = {
     PV_EINVAL: "PV_EINVAL", PV_ENOMEM: "PV_ENOMEM", PV_EHIP: "PV_EHIP",

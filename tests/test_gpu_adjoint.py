@@ -90,26 +90,36 @@ def test_autograd_matches_abi(ctx):
 
 def test_adjoint_against_finite_differences(ctx):
     """fp32 GPU gradient of L = sum (rho - t)^2 against fp64 central
-    differences of the oracle's L on sampled particles and coordinates."""
+    differences of the oracle's L on sampled particles and coordinates; the
+    allowance adds what rounding the upstream gradient to fp32 changes."""
     s = adjoint_set(20000, 8)
     o = oracle_for(s)
     from oracle import Oracle
     t = Oracle(s.extra["pos_target"], s.h, s.m, s.box).density()["rho"]
     rho = o.density()["rho"]
-    G = 2 * (rho - t)
-    gp, gh = _gpu_grad(ctx, s, G.astype(np.float32))
+    G64 = 2 * (rho - t)
+    G32 = G64.astype(np.float32)
+    gp, gh = _gpu_grad(ctx, s, G32)
     rng = np.random.Generator(np.random.PCG64(10))
-    ks = rng.choice(s.n, 200, replace=False)
-    ks = np.repeat(ks, 4)
-    comps = np.tile(np.arange(4), ks.size // 4)
-    H = 1.825742 * s.h[ks].astype(np.float64)
-    eps = np.where(comps < 3, 1e-4 * H, 1e-4 * s.h[ks])
-    fd = o.fd_loss(t, ks, comps, eps)
-    ref = o.grad(G, np.unique(ks))
-    pos_of = {k: i for i, k in enumerate(np.unique(ks))}
-    scale = np.array([ref["gx_abs"][pos_of[k], c] if c < 3 else ref["gh_abs"][pos_of[k]]
-                      for k, c in zip(ks, comps)])
-    gpu = np.where(comps < 3, gp[ks, np.minimum(comps, 2)], gh[ks])
-    # G is fp32 on the GPU: allow its rounding on top of the 1e-5
-    err = np.abs(gpu - fd) / scale
-    assert np.max(err) < 2e-5, f"max FD err {np.max(err)}"
+    ks = np.sort(rng.choice(s.n, 200, replace=False))
+    kk = np.repeat(ks, 4)
+    comps = np.tile(np.arange(4), ks.size)
+    row = np.repeat(np.arange(ks.size), 4)
+    H = 1.825742 * s.h[kk].astype(np.float64)
+    eps = np.where(comps < 3, 1e-4 * H, 1e-4 * s.h[kk])
+    # Richardson-extrapolated central differences; |fd(e) - fd(e/2)| bounds the
+    # truncation left (the loss is quadratic, so where rho ~ t its curvature
+    # term dominates the small gradient)
+    fd1 = o.fd_loss(t, kk, comps, eps)
+    fd2 = o.fd_loss(t, kk, comps, eps / 2)
+    fd = (4.0 * fd2 - fd1) / 3.0
+    trunc = 0.1 * np.abs(fd1 - fd2)
+    r32 = o.grad(G32.astype(np.float64), ks)
+    r64 = o.grad(G64, ks)
+    pick = lambda r: np.where(comps < 3, r["gx"][row, np.minimum(comps, 2)], r["gh"][row])
+    scale = np.where(comps < 3, r64["gx_abs"][row, np.minimum(comps, 2)], r64["gh_abs"][row])
+    gpu = np.where(comps < 3, gp[kk, np.minimum(comps, 2)], gh[kk])
+    _check(gp, gh, r32, ks, label="fd-set")
+    allow = 1e-5 * scale + np.abs(pick(r64) - pick(r32)) + trunc
+    err = np.abs(gpu - fd) / allow
+    assert np.max(err) < 1.0, f"max FD err / allowance {np.max(err)}"
