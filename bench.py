@@ -148,6 +148,7 @@ def main():
         print("[bench] timing the fp64 CPU oracle on a sample", file=sys.stderr, flush=True)
         cpu = _cpu_baseline(s, a.cpu_seconds)
 
+    traffic = _traffic(a.workload, "pvl::k_sweep_queue<false>")
     rec = {
         "metric": "density pair-interactions/s + ns/particle, sorted-pair vs cell-list, 1 GPU",
         "value": value,
@@ -174,14 +175,32 @@ def main():
         "candidates_per_particle": {"sorted": cand_sorted / n, "plain": cand_plain / n,
                                     "in_range": inr / n},
         "wall_ms_per_step": wall_sorted,
-        "roofline": {"kernel": "k_sweep_sorted", "bound": "alu", "achieved": achieved,
-                     "peak": VALU_PEAK_TOPS, "unit": "TOP/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None,
-                     "work": f"{OPS_PER_CANDIDATE} lane-ops per tested pair + "
-                             f"{OPS_PER_INTERACTION} per pair in range"},
+        "roofline": {"kernel": "k_sweep_queue<false> (sorted-pair density sweep)", "bound": "alu",
+                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+                     "work": f"{OPS_PER_CANDIDATE} lane-ops per pair admitted by the per-receiver "
+                             f"bounds + {OPS_PER_INTERACTION} per pair in range "
+                             f"({alg_ops / n:.0f} per particle)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
+
+
+def _traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload, if it was taken on the current library sources."""
+    from paper_1804_06231_amd.rocprof_summary import source_hash
+    path = os.path.join(ROOT, "profiles", f"{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    t = rec.get("traffic", {}).get(kernel)
+    if not t:
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
 def _cpu_baseline(s, target_seconds):
