@@ -105,11 +105,12 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restric
     }
 }
 
+// Staging record of one particle: 32 bytes, written with one aligned store pair.
 __global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n,
                           const float *__restrict__ pos, const float *__restrict__ h,
                           const float *__restrict__ mass, const int32_t *__restrict__ cellid,
                           const int32_t *__restrict__ slot, const int32_t *__restrict__ start,
-                          float4 *__restrict__ stage, float2 *__restrict__ stage2)
+                          float4 *__restrict__ stage)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
@@ -117,19 +118,28 @@ __global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n,
     float x = wrap_coord(pos[3 * p + 0], B.L[0], 1.0f / B.L[0]);
     float y = wrap_coord(pos[3 * p + 1], B.L[1], 1.0f / B.L[1]);
     float z = wrap_coord(pos[3 * p + 2], B.L[2], 1.0f / B.L[2]);
-    int q = start[cellid[p]] + slot[p];
-    stage[q] = make_float4(x, y, z, kGamma * h[p]);
-    stage2[q] = make_float2(mass[p], __int_as_float((int)p));
+    int64_t q = start[cellid[p]] + slot[p];
+    stage[2 * q] = make_float4(x, y, z, kGamma * h[p]);
+    stage[2 * q + 1] = make_float4(mass[p], __int_as_float((int)p), 0.f, 0.f);
 }
 
-// One workgroup per cell.
+// One workgroup per cell: order the cell's particles by (cell-relative x,
+// original index) with a bucket sort in LDS (buckets are equal x ranges of
+// the cell; the exact rank inside a bucket compares bucket mates), shift the
+// positions to the cell origin, write the cell-ordered arrays and the cell's
+// largest cut-off.
+constexpr int kFinishMaxBuckets = 1024;
+
 __global__ void __launch_bounds__(kBlock) k_cell_finish(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
-    const float2 *__restrict__ stage2, float4 *__restrict__ xyzm, float *__restrict__ Hout,
-    int32_t *__restrict__ orig, uint32_t *__restrict__ cell_hmax)
+    float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
+    uint32_t *__restrict__ cell_hmax)
 {
-    __shared__ uint64_t keys[PV_MAX_CELL];
+    __shared__ float key[PV_MAX_CELL];
+    __shared__ uint16_t slot[PV_MAX_CELL];
+    __shared__ uint16_t border[PV_MAX_CELL];
+    __shared__ uint32_t hist[kFinishMaxBuckets];
     __shared__ uint32_t hred[kBlock / 64];
     const int c = blockIdx.x;
     const int s0 = start[c];
@@ -139,39 +149,72 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
         return;
     }
     const BoxDesc &B = box[cell_box[c]];
-    int local = c - B.cell_off;
-    int cz = local % B.g[2];
-    int cy = (local / B.g[2]) % B.g[1];
-    int cx = local / (B.g[2] * B.g[1]);
-    float ox = (float)cx * B.edge[0], oy = (float)cy * B.edge[1], oz = (float)cz * B.edge[2];
-    int P2 = next_pow2(cnt);
-    // sort by cell-relative x (ordered bits) with the arrival slot as payload;
-    // runs of equal x are then ordered by original index (unique)
-    for (int r = threadIdx.x; r < P2; r += blockDim.x) {
-        uint64_t k = ~0ull;
-        if (r < cnt) {
-            float xr = stage[s0 + r].x - ox;
-            k = ((uint64_t)float_to_ordered(xr) << 32) | (uint32_t)r;
-        }
-        keys[r] = k;
+    const int local = c - B.cell_off;
+    const int cz = local % B.g[2];
+    const int cy = (local / B.g[2]) % B.g[1];
+    const int cx = local / (B.g[2] * B.g[1]);
+    const float ox = (float)cx * B.edge[0], oy = (float)cy * B.edge[1], oz = (float)cz * B.edge[2];
+    int NB = cnt <= 256 ? 128 : next_pow2(cnt) >> 2;
+    NB = NB > kFinishMaxBuckets ? kFinishMaxBuckets : NB;
+    const float scale = (float)NB / B.edge[0];
+    auto bucket = [&](float xr) {
+        int b = (int)(xr * scale);
+        return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
+    };
+    for (int b = threadIdx.x; b < NB; b += blockDim.x) hist[b] = 0u;
+    __syncthreads();
+    for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+        const float xr = stage[2 * (int64_t)(s0 + r)].x - ox;
+        key[r] = xr;
+        slot[r] = (uint16_t)atomicAdd(&hist[bucket(xr)], 1u);
     }
     __syncthreads();
-    bitonic_sort_segments(keys, P2, 1);
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        const int per = (NB + 63) >> 6;
+        uint32_t loc = 0;
+        for (int k = 0; k < per; ++k) {
+            const int q = lane * per + k;
+            if (q < NB) loc += hist[q];
+        }
+        uint32_t inc = loc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+            if (lane >= off) inc += o;
+        }
+        uint32_t run = inc - loc;
+        for (int k = 0; k < per; ++k) {
+            const int q = lane * per + k;
+            if (q < NB) {
+                const uint32_t v = hist[q];
+                hist[q] = run;
+                run += v;
+            }
+        }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < cnt; r += blockDim.x)
+        border[hist[bucket(key[r])] + slot[r]] = (uint16_t)r;
+    __syncthreads();
     uint32_t hm = 0u;
     for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-        const uint64_t key = keys[r];
-        const uint32_t xb = (uint32_t)(key >> 32);
-        const int slot = s0 + (int)(key & 0xffffffffu);
-        const int my_orig = __float_as_int(stage2[slot].y);
-        int lo = r, hi = r + 1;
-        while (lo > 0 && (uint32_t)(keys[lo - 1] >> 32) == xb) --lo;
-        while (hi < cnt && (uint32_t)(keys[hi] >> 32) == xb) ++hi;
-        int rank = lo;
-        for (int q = lo; q < hi; ++q)
-            rank += __float_as_int(stage2[s0 + (int)(keys[q] & 0xffffffffu)].y) < my_orig;
-        float4 a = stage[slot];
-        float2 b = stage2[slot];
-        xyzm[s0 + rank] = make_float4(a.x - ox, a.y - oy, a.z - oz, b.x);
+        const float k = key[r];
+        const int b = bucket(k);
+        const int q0 = (int)hist[b];
+        const int q1 = b + 1 < NB ? (int)hist[b + 1] : cnt;
+        const float4 a = stage[2 * (int64_t)(s0 + r)];
+        const float4 m = stage[2 * (int64_t)(s0 + r) + 1];
+        const int my_orig = __float_as_int(m.y);
+        int rank = q0;
+        for (int q = q0; q < q1; ++q) {
+            const int r2 = border[q];
+            const float k2 = key[r2];
+            bool before = k2 < k;
+            if (k2 == k && r2 != r)
+                before = __float_as_int(stage[2 * (int64_t)(s0 + r2) + 1].y) < my_orig;
+            rank += before;
+        }
+        xyzm[s0 + rank] = make_float4(k, a.y - oy, a.z - oz, m.x);
         Hout[s0 + rank] = a.w;
         orig[s0 + rank] = my_orig;
         hm = max(hm, __float_as_uint(a.w));
@@ -181,9 +224,9 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
     if ((threadIdx.x & 63) == 0) hred[threadIdx.x >> 6] = hm;
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t m = 0u;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, hred[w]);
-        cell_hmax[c] = m;
+        uint32_t mx = 0u;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = max(mx, hred[w]);
+        cell_hmax[c] = mx;
     }
 }
 
@@ -236,11 +279,10 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, int nbox, int64_t n, in
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncell, c.cursor, c.cell_start, dflags);
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox, n,
-                           pos, h, mass, c.cellid, c.slot, c.cell_start, c.stage, c.stage2);
+                           pos, h, mass, c.cellid, c.slot, c.cell_start, c.stage);
     }
     hipLaunchKernelGGL(k_cell_finish, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.stage, c.stage2, c.xyzm, c.H, c.orig,
-                       c.cell_hmax);
+                       c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax);
     return hipGetLastError();
 }
 

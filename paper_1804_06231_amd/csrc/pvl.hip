@@ -61,7 +61,7 @@ hipError_t dev_alloc(T **p, int64_t count)
 void free_dev(DevCells &d)
 {
     void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cursor, d.cellid, d.slot, d.stage,
-                    d.stage2, d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
+                    d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
                     d.items, d.qcount};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
@@ -87,8 +87,7 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.cursor, C);
     ALLOC(d.cellid, N);
     ALLOC(d.slot, N);
-    ALLOC(d.stage, N);
-    ALLOC(d.stage2, N);
+    ALLOC(d.stage, 2 * N);
     ALLOC(d.xyzm, N);
     ALLOC(d.H, N);
     ALLOC(d.orig, N);

@@ -77,8 +77,7 @@ struct DevCells {
     int32_t *cursor = nullptr;    // ncell: scatter cursors / counts
     int32_t *cellid = nullptr;    // n: global cell of each input particle
     int32_t *slot = nullptr;      // n: arrival rank of the particle within its cell
-    float4 *stage = nullptr;      // n: (x, y, z, H) wrapped, in scatter order
-    float2 *stage2 = nullptr;     // n: (m, original index as bits)
+    float4 *stage = nullptr;      // 2n: per particle (x, y, z, H) wrapped, (m, index bits, -, -)
     float4 *xyzm = nullptr;       // n: cell-relative position and mass
     float *H = nullptr;           // n: cut-off radius
     int32_t *orig = nullptr;      // n: original index

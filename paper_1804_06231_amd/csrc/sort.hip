@@ -10,18 +10,30 @@
 // bucket's start plus the number of bucket mates with a smaller (key, in-cell
 // rank) pair.  Equal keys keep in-cell order, so the result is deterministic,
 // and the work is linear in the occupancy unless a bucket is crowded.
+//
+// Each thread reads the positions of its particles once and computes their
+// keys for every axis of the pass; ranks are resolved in LDS and the sorted
+// lists are written out in order, so the global stores are coalesced.
 // Output per axis: the in-cell ranks (uint16) in key order and the keys (fp32).
 #include "device_util.h"
 
 namespace pvl {
 
-constexpr int kSortLdsBytes = 48 * 1024;
+constexpr int kSortLdsBytes = 40 * 1024;
 
 __device__ __forceinline__ int sort_buckets(int cnt)
 {
     if (cnt <= 256) return 128;
     int p = next_pow2(cnt);
     return cnt <= 1024 ? p >> 1 : p >> 2;
+}
+
+// Bucket of key k on an axis whose cell projection starts at kmin: the range
+// split into NB equal parts (scale = NB / range).
+__device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int NB)
+{
+    const int b = (int)((k - kmin) * scale);
+    return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
 }
 
 __global__ void __launch_bounds__(kBlock) k_sort13(const BoxDesc *__restrict__ box,
@@ -32,38 +44,133 @@ __global__ void __launch_bounds__(kBlock) k_sort13(const BoxDesc *__restrict__ b
                                                     float *__restrict__ skey)
 {
     __shared__ __align__(16) unsigned char lds[kSortLdsBytes];
+    __shared__ float ax_kmin[13], ax_scale[13];
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
     if (cnt <= 0 || cnt > PV_MAX_CELL) return;
     const BoxDesc &B = box[cell_box[c]];
-    const int NB = sort_buckets(cnt);
-    const int per_axis = NB * 4 + cnt * 8 + ((cnt * 2 + 15) & ~15);
+    const int NB = sort_buckets(cnt);   // 128 whenever cnt <= kBlock
+    // per axis: histogram (NB u32), keys (cnt f32), the arrival-slot list (later
+    // reused for the final order) and the bucket-order list (cnt u16 each),
+    // rows rounded to 16 bytes
+    const int keyw = ((cnt * 4 + 15) & ~15) / 4;     // floats per key row
+    const int u16w = ((cnt * 2 + 15) & ~15) / 2;     // u16 per list row
+    const int per_axis = NB * 4 + keyw * 4 + 2 * u16w * 2;
     int G = kSortLdsBytes / per_axis;
     G = G > 13 ? 13 : (G < 1 ? 1 : G);
+    if (threadIdx.x < 13) {
+        float e[3];
+        dir_axis(threadIdx.x, e);
+        const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
+                           fminf(e[2], 0.f) * B.edge[2];
+        const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
+                           fmaxf(e[2], 0.f) * B.edge[2];
+        ax_kmin[threadIdx.x] = kmin;
+        ax_scale[threadIdx.x] = (float)NB / (kmax - kmin);
+    }
+    __syncthreads();
+
+    if (cnt <= kBlock) {
+        // one particle per thread, all 13 axes at once with the axis loops
+        // unrolled so that their LDS traffic overlaps
+        uint32_t *hist = reinterpret_cast<uint32_t *>(lds);                    // [13][128]
+        float *key = reinterpret_cast<float *>(lds + 13 * 128 * 4);           // [13][256]
+        uint16_t *border = reinterpret_cast<uint16_t *>(key + 13 * kBlock);   // [13][256]
+        uint16_t *forder = border + 13 * kBlock;                              // [13][256]
+        const int r = threadIdx.x;
+        const bool on = r < cnt;
+        for (int t = threadIdx.x; t < 13 * 128; t += blockDim.x) hist[t] = 0u;
+        __syncthreads();
+        float k[13];
+        int b[13];
+        uint32_t sl[13];
+        float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int g = 0; g < 13; ++g) {
+            k[g] = proj_key(p.x, p.y, p.z, g);
+            b[g] = key_bucket(k[g], ax_kmin[g], ax_scale[g], 128);
+        }
+        if (on) {
+#pragma unroll
+            for (int g = 0; g < 13; ++g) {
+                key[g * kBlock + r] = k[g];
+                sl[g] = atomicAdd(&hist[g * 128 + b[g]], 1u);
+            }
+        }
+        __syncthreads();
+        {
+            // exclusive scans: 13 axes of 128 buckets, two buckets per lane
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            for (int g = wave; g < 13; g += (int)(blockDim.x >> 6)) {
+                uint32_t *hh = hist + g * 128;
+                const uint32_t v0 = hh[2 * lane], v1 = hh[2 * lane + 1];
+                const uint32_t loc = v0 + v1;
+                uint32_t inc = loc;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+                    if (lane >= off) inc += o;
+                }
+                const uint32_t ex = inc - loc;
+                hh[2 * lane] = ex;
+                hh[2 * lane + 1] = ex + v0;
+            }
+        }
+        __syncthreads();
+        int q0[13];
+        if (on) {
+#pragma unroll
+            for (int g = 0; g < 13; ++g) {
+                q0[g] = (int)hist[g * 128 + b[g]];
+                border[g * kBlock + q0[g] + (int)sl[g]] = (uint16_t)r;
+            }
+        }
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int g = 0; g < 13; ++g) {
+                const int q1 = b[g] + 1 < 128 ? (int)hist[g * 128 + b[g] + 1] : cnt;
+                int rank = q0[g];
+                for (int q = q0[g]; q < q1; ++q) {
+                    const int r2 = border[g * kBlock + q];
+                    const float k2 = key[g * kBlock + r2];
+                    rank += (k2 < k[g]) || (k2 == k[g] && r2 < r);
+                }
+                forder[g * kBlock + rank] = (uint16_t)r;
+            }
+        }
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int g = 0; g < 13; ++g) {
+                const int rr = forder[g * kBlock + r];
+                const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + r);
+                sidx[o] = (uint16_t)rr;
+                skey[o] = key[g * kBlock + rr];
+            }
+        }
+        return;
+    }
 
     for (int sf = 0; sf < 13; sf += G) {
         const int ng = 13 - sf < G ? 13 - sf : G;
-        uint32_t *hist = reinterpret_cast<uint32_t *>(lds);                          // [ng][NB]
-        uint64_t *key = reinterpret_cast<uint64_t *>(lds + (size_t)ng * NB * 4);     // [ng][cnt]
-        uint16_t *order = reinterpret_cast<uint16_t *>(lds + (size_t)ng * NB * 4 + (size_t)ng * cnt * 8);
+        uint32_t *hist = reinterpret_cast<uint32_t *>(lds);                     // [ng][NB]
+        float *key = reinterpret_cast<float *>(lds + (size_t)ng * NB * 4);      // [ng][keyw]
+        uint16_t *slot = reinterpret_cast<uint16_t *>(key + (size_t)ng * keyw); // [ng][u16w]
+        uint16_t *border = slot + (size_t)ng * u16w;                            // bucket order
+        uint16_t *forder = slot;                                                // final order
         for (int t = threadIdx.x; t < ng * NB; t += blockDim.x) hist[t] = 0u;
         __syncthreads();
-        // keys, buckets, histogram
-        for (int t = threadIdx.x; t < ng * cnt; t += blockDim.x) {
-            int g = t / cnt, r = t - g * cnt, s = sf + g;
-            float4 p = xyzm[s0 + r];
-            float k = proj_key(p.x, p.y, p.z, s);
-            float e[3];
-            dir_axis(s, e);
-            float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
-                         fminf(e[2], 0.f) * B.edge[2];
-            float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
-                         fmaxf(e[2], 0.f) * B.edge[2];
-            int b = (int)((k - kmin) * ((float)NB / (kmax - kmin)));
-            b = b < 0 ? 0 : (b >= NB ? NB - 1 : b);
-            atomicAdd(&hist[g * NB + b], 1u);
-            key[t] = ((uint64_t)float_to_ordered(k) << 32) | ((uint32_t)b << 16) | (uint32_t)r;
+        // keys of every axis in the pass from one position read per particle;
+        // the histogram atomic gives each key its arrival slot in its bucket
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+            const float4 p = xyzm[s0 + r];
+            for (int g = 0; g < ng; ++g) {
+                const float k = proj_key(p.x, p.y, p.z, sf + g);
+                const int b = key_bucket(k, ax_kmin[sf + g], ax_scale[sf + g], NB);
+                key[g * keyw + r] = k;
+                slot[g * u16w + r] = (uint16_t)atomicAdd(&hist[g * NB + b], 1u);
+            }
         }
         __syncthreads();
         // exclusive scan of every axis' histogram (one wave per axis)
@@ -74,19 +181,19 @@ __global__ void __launch_bounds__(kBlock) k_sort13(const BoxDesc *__restrict__ b
                 uint32_t *hh = hist + g * NB;
                 uint32_t loc = 0;
                 for (int k = 0; k < per; ++k) {
-                    int q = lane * per + k;
+                    const int q = lane * per + k;
                     if (q < NB) loc += hh[q];
                 }
                 uint32_t inc = loc;
                 for (int off = 1; off < 64; off <<= 1) {
-                    uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+                    const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
                     if (lane >= off) inc += o;
                 }
                 uint32_t run = inc - loc;
                 for (int k = 0; k < per; ++k) {
-                    int q = lane * per + k;
+                    const int q = lane * per + k;
                     if (q < NB) {
-                        uint32_t v = hh[q];
+                        const uint32_t v = hh[q];
                         hh[q] = run;
                         run += v;
                     }
@@ -94,26 +201,44 @@ __global__ void __launch_bounds__(kBlock) k_sort13(const BoxDesc *__restrict__ b
             }
         }
         __syncthreads();
-        // list every bucket's members; afterwards hist[b] is the end of bucket b
-        for (int t = threadIdx.x; t < ng * cnt; t += blockDim.x) {
-            int g = t / cnt;
-            int b = (int)((key[t] >> 16) & 0xffffu);
-            uint32_t q = atomicAdd(&hist[g * NB + b], 1u);
-            order[g * cnt + q] = (uint16_t)(t - g * cnt);
+        // bucket start + arrival slot: the list of every bucket's members
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+            for (int g = 0; g < ng; ++g) {
+                const int b = key_bucket(key[g * keyw + r], ax_kmin[sf + g], ax_scale[sf + g], NB);
+                border[g * u16w + (int)hist[g * NB + b] + slot[g * u16w + r]] = (uint16_t)r;
+            }
         }
         __syncthreads();
-        // rank = bucket start + bucket mates ordered before this key
-        for (int t = threadIdx.x; t < ng * cnt; t += blockDim.x) {
-            int g = t / cnt;
-            uint64_t mine = key[t];
-            int b = (int)((mine >> 16) & 0xffffu);
-            int q1 = (int)hist[g * NB + b];
-            int q0 = b > 0 ? (int)hist[g * NB + b - 1] : 0;
-            int rank = q0;
-            for (int q = q0; q < q1; ++q) rank += key[g * cnt + order[g * cnt + q]] < mine;
-            size_t o = (size_t)(sf + g) * (size_t)n + (size_t)(s0 + rank);
-            sidx[o] = (uint16_t)(mine & 0xffffu);
-            skey[o] = ordered_to_float((uint32_t)(mine >> 32));
+        // exact rank: bucket start + bucket mates with a smaller (key, rank);
+        // the members of bucket b sit at [hist[b], hist[b+1])
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+            for (int g = 0; g < ng; ++g) {
+                const float *kk = key + g * keyw;
+                const uint16_t *bo = border + g * u16w;
+                const float k = kk[r];
+                const int b = key_bucket(k, ax_kmin[sf + g], ax_scale[sf + g], NB);
+                const int q0 = (int)hist[g * NB + b];
+                const int q1 = b + 1 < NB ? (int)hist[g * NB + b + 1] : cnt;
+                int rank = q0;
+                for (int q = q0; q < q1; ++q) {
+                    const int r2 = bo[q];
+                    const float k2 = kk[r2];
+                    rank += (k2 < k) || (k2 == k && r2 < r);
+                }
+                forder[g * u16w + rank] = (uint16_t)r;
+            }
+        }
+        __syncthreads();
+        // coalesced output of the sorted lists
+        for (int g = 0; g < ng; ++g) {
+            const float *kk = key + g * keyw;
+            const uint16_t *fo = forder + g * u16w;
+            const size_t o = (size_t)(sf + g) * (size_t)n + (size_t)s0;
+            for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+                const int r = fo[q];
+                sidx[o + q] = (uint16_t)r;
+                skey[o + q] = kk[r];
+            }
         }
         __syncthreads();
     }
