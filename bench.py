@@ -136,6 +136,12 @@ def main():
     ms_sort, _ = _time_loop(lambda: ctx.sort_cells(cells), a.steps, 1, torch)
     ms_sweep, _ = _time_loop(lambda: ctx.density(cells, "sorted", out_s), a.steps, 1, torch)
     ms_sweep_plain, _ = _time_loop(lambda: ctx.density(cells, "plain", out_p), a.steps, 1, torch)
+    # adjoint sweep for a seeded upstream gradient (dL/drho)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    g_rho = torch.randn(s.n, generator=gen, device=dev)
+    out_g = (torch.empty((s.n, 3), device=dev), torch.empty(s.n, device=dev))
+    ms_adj, _ = _time_loop(lambda: ctx.density_backward(cells, g_rho, out_g), a.steps, 1, torch)
     ctx.check()
 
     n = s.n
@@ -148,7 +154,7 @@ def main():
         print("[bench] timing the fp64 CPU oracle on a sample", file=sys.stderr, flush=True)
         cpu = _cpu_baseline(s, a.cpu_seconds)
 
-    traffic = _traffic(a.workload, "pvl::k_sweep_queue<false>")
+    traffic = _traffic(a.workload, "pvl::k_sweep_queue<0>")
     rec = {
         "metric": "density pair-interactions/s + ns/particle, sorted-pair vs cell-list, 1 GPU",
         "value": value,
@@ -171,11 +177,12 @@ def main():
                             "ns_per_particle": ms_plain * 1e6 / n,
                             "sweep_ms": ms_sweep_plain},
         "speedup_sorted_vs_plain": ms_plain / ms_sorted,
-        "stages_ms": {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep},
+        "stages_ms": {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep,
+                      "adjoint_sweep": ms_adj},
         "candidates_per_particle": {"sorted": cand_sorted / n, "plain": cand_plain / n,
                                     "in_range": inr / n},
         "wall_ms_per_step": wall_sorted,
-        "roofline": {"kernel": "k_sweep_queue<false> (sorted-pair density sweep)", "bound": "alu",
+        "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
                      "work": f"{OPS_PER_CANDIDATE} lane-ops per pair admitted by the per-receiver "

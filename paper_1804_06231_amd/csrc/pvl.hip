@@ -377,7 +377,7 @@ pv_status pv_density_backward(pv_ctx *ctx, const pv_cells *cells, const float *g
     if (!cells->sorted) return fail(ctx, PV_ESTATE, "pv_sort_cells must run before the adjoint");
     if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
     HIPCHK(ctx, pvl::launch_backward(ctx->stream, cells->d, cells->n, cells->ncell, grad_rho,
-                                     grad_pos, grad_h, ctx->dflags));
+                                     grad_pos, grad_h, ctx->dflags, ctx->tune));
     return PV_OK;
 }
 

@@ -113,8 +113,11 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
                               const int *dflags, const SweepTuning &tune, bool plain);
+hipError_t launch_backward_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                                 float *grad_pos, float *grad_h, const int *dflags,
+                                 const SweepTuning &tune);
 hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                            const float *grad_rho, float *grad_pos, float *grad_h,
-                           const int *dflags);
+                           const int *dflags, const SweepTuning &tune);
 
 }  // namespace pvl

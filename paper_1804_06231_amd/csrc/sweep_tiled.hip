@@ -36,12 +36,25 @@
 // own LDS array; the four arrays are summed in a fixed order at the end, so
 // the result does not depend on timing or on which workgroup took the item.
 //
-// PLAIN = true gives the plain cell-list comparator on the same tiles: every
-// receiver meets every particle of the 27 cells, in cell order, with no sorted
-// lists and no pruning (Listing 1).
+// Three sweeps share this code (the MODE template argument):
+//   * kModeSorted: the density with the pruned bounds above;
+//   * kModePlain: the plain cell-list comparator on the same tiles: every
+//     receiver meets every particle of the 27 cells, in cell order, with no
+//     sorted lists and no pruning (Listing 1);
+//   * kModeAdjoint: the gradient of a loss through rho.  A receiver k gathers
+//       dL/dx_k = sum_j [G_k m_j W_r(r, H_k) + G_j m_k W_r(r, H_j)] (x_k - x_j) / r
+//       dL/dh_k = G_k drho_dh_k
+//     (G = dL/drho, W_r = dW/dr), so every output has one writer.  A pair
+//     counts when r < max(H_k, H_j): the bounds use max(H_k, largest cut-off
+//     of the source cell) in place of H_k, which keeps every pair that the
+//     source's own cut-off decides.
 #include "device_util.h"
 
 namespace pvl {
+
+constexpr int kModeSorted = 0;
+constexpr int kModePlain = 1;
+constexpr int kModeAdjoint = 2;
 
 constexpr int kChunk = 256;                    // receivers per work item
 constexpr int kMaxTasks = 27 * (kChunk / 16);  // task slots per item
@@ -60,6 +73,11 @@ __device__ __forceinline__ float ror16(float v)
 
 struct TileAcc {
     float rho, wc, dh, cnt;
+};
+
+struct GradAcc {
+    float gx, gy, gz;   // dL/dx_k
+    float dh;           // sum over r < H_k of m_j (3 w + u w')
 };
 
 __device__ __forceinline__ void tile_interact(float r2, float mj, float invH, TileAcc &a)
@@ -82,6 +100,46 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH, Ti
     a.dh = fmaf(mj, d3, a.dh);
     a.cnt += 1.0f;
 }
+
+// Both terms of the adjoint for a source j within max(H_k, H_j) of receiver
+// k (d = x_j - x_k, r2 = |d|^2 > 0).  Receiver constants: H_k^2, 1/H_k,
+// ck = G_k 8 / (pi H_k^4), m_k; source: m_j, 1/H_j, cj = G_j 8 / (pi H_j^4),
+// H_j^2.  Accumulates dL/dx_k and sum m_j (3 w + u w') over r < H_k.
+__device__ __forceinline__ void grad_interact(float dx, float dy, float dz, float r2, float mj,
+                                              float invHj, float cj, float Hj2, float Hk2,
+                                              float invHk, float ck, float mk, GradAcc &a)
+{
+    float invr = __builtin_amdgcn_rsqf(r2);   // v_rsq_f32, 1 ulp
+    float r = r2 * invr;
+    float uk = r * invHk, vk = 1.0f - uk;
+    float uj = r * invHj, vj = 1.0f - uj;
+    // w' = -12u + 18u^2 (u < 1/2), -6 (1-u)^2 (u >= 1/2); w as in the forward
+    float dwk = uk < 0.5f ? uk * fmaf(18.0f, uk, -12.0f) : -6.0f * vk * vk;
+    float wk = uk < 0.5f ? fmaf(uk * uk, fmaf(6.0f, uk, -6.0f), 1.0f) : 2.0f * vk * vk * vk;
+    float dwj = uj < 0.5f ? uj * fmaf(18.0f, uj, -12.0f) : -6.0f * vj * vj;
+    bool ink = r2 < Hk2, inj = r2 < Hj2;
+    float coef = (ink ? ck * mj * dwk : 0.0f) + (inj ? cj * mk * dwj : 0.0f);
+    a.dh += ink ? mj * fmaf(uk, dwk, 3.0f * wk) : 0.0f;
+    // (x_k - x_j) / r = -d / r
+    float c = -coef * invr;
+    a.gx = fmaf(c, dx, a.gx);
+    a.gy = fmaf(c, dy, a.gy);
+    a.gz = fmaf(c, dz, a.gz);
+}
+
+#define PVL_GRAD_STEP(K)                                                  \
+    {                                                                     \
+        float dx = ror16<K>(sx) - tx;                                     \
+        float dy = ror16<K>(sy) - ty;                                     \
+        float dz = ror16<K>(sz) - tz;                                     \
+        float mj = ror16<K>(sm);                                          \
+        float hj2 = ror16<K>(sh2);                                        \
+        float ij = ror16<K>(sinv);                                        \
+        float cj = ror16<K>(sc);                                          \
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                   \
+        if ((r2 < H2 || r2 < hj2) && r2 > 0.0f)                          \
+            grad_interact(dx, dy, dz, r2, mj, ij, cj, hj2, H2, invH, ck, mi, acc); \
+    }
 
 #define PVL_TILE_STEP(K)                                                  \
     {                                                                     \
@@ -121,6 +179,8 @@ struct SweepArgs {
     int64_t n;
     float *rho, *wcount, *drho_dh;
     int32_t *ncount;
+    const float *gcell;          // adjoint: upstream gradient in cell order
+    float *grad_pos, *grad_h;    // adjoint outputs (input order)
     const int *dflags;
     const int2 *items;   // queue: [0, nbig) large-cell chunks, [cap - nsmall, cap) cells
     const int *qcount;   // [0] nbig, [1] nsmall
@@ -144,9 +204,11 @@ struct SweepLds {
     int item;
 };
 
-template <bool PLAIN>
+template <int MODE>
 __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
 {
+    constexpr bool PLAIN = MODE == kModePlain;
+    constexpr bool ADJ = MODE == kModeAdjoint;
     const int64_t n = A.n;
     const int sa = A.start[a];
     const int na = A.start[a + 1] - sa;
@@ -181,15 +243,17 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
             const float *ka = skey + (size_t)s * n + sa;
             const float *kb = skey + (size_t)s * n + sb;
+            // the adjoint also keeps pairs decided by the source's cut-off
+            const float reach = ADJ ? fmaxf(hmax_a, __uint_as_float(A.cell_hmax[b])) : hmax_a;
             if (sign > 0) {
-                // receivers with key_i + Hmax_a > key_b[0] + se
-                float thr = (kb[0] + se) - hmax_a - slack;
+                // receivers with key_i + reach > key_b[0] + se
+                float thr = (kb[0] + se) - reach - slack;
                 int lo = 0, hi = na;
                 while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] <= thr) lo = m + 1; else hi = m; }
                 act = na - lo;
             } else {
-                // receivers with key_i - Hmax_a < key_b[nb-1] + se
-                float thr = (kb[nb - 1] + se) + hmax_a + slack;
+                // receivers with key_i - reach < key_b[nb-1] + se
+                float thr = (kb[nb - 1] + se) + reach + slack;
                 int lo = 0, hi = na;
                 while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] < thr) lo = m + 1; else hi = m; }
                 act = lo;
@@ -211,7 +275,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
                 L.recv_off[d] = roff;
                 roff += L.act_cell[d];
             }
-            L.flag = (A.reach_order && roff <= kMaxRecv) ? 1 : 0;
+            L.flag = (!ADJ && A.reach_order && roff <= kMaxRecv) ? 1 : 0;
         }
         __syncthreads();
         listed = L.flag != 0;
@@ -322,8 +386,10 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             // two-sided window in x over the whole cell: |x_j - x_i| < H_i
             const float *ka = skey + (size_t)kSelfAxis * n + sa;
             const int r0 = r_lo + blk * 16, r1 = min(r0 + 16, r_hi);
-            float hb = 0.0f;
-            for (int r = r0; r < r1; ++r) hb = fmaxf(hb, A.Hc[sa + r]);
+            // the adjoint's pairs reach max(H_i, H_j) <= the cell's largest cut-off
+            float hb = ADJ ? hmax_a : 0.0f;
+            if (!ADJ)
+                for (int r = r0; r < r1; ++r) hb = fmaxf(hb, A.Hc[sa + r]);
             const float lo_k = ka[r0] - hb - slack, hi_k = ka[r1 - 1] + hb + slack;
             int lo = 0, hi = na;
             while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] <= lo_k) lo = m + 1; else hi = m; }
@@ -348,6 +414,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             const uint16_t *il = sidx + (size_t)s * n + sa;
             const float *kb = skey + (size_t)s * n + sb;
             const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[dir]);
+            const float hmax_b = __uint_as_float(A.cell_hmax[b]);
             // block reach: the largest key + H (ahead) or smallest key - H (behind)
             float T = sign > 0 ? -INFINITY : INFINITY;
             for (int r = r0; r < r1; ++r) {
@@ -362,6 +429,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
                     k = ka[q];
                     H = A.Hc[sa + il[q]];
                 }
+                if (ADJ) H = fmaxf(H, hmax_b);
                 T = sign > 0 ? fmaxf(T, k + H) : fminf(T, k - H);
             }
             int nsrc;
@@ -446,33 +514,74 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
         int ntmax = nt;
         ntmax = max(ntmax, __shfl_xor(ntmax, 16));
         ntmax = max(ntmax, __shfl_xor(ntmax, 32));
-        TileAcc acc = {0.f, 0.f, 0.f, 0.f};
-        for (int it = 0; it < ntmax; ++it) {
-            const int tile = t0 + it;
-            const int j = tile * 16 + l16;
-            float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-            if (it < nt && j < nb) {
-                const int p = (PLAIN || dir == 26) ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
-                q = A.xyzm[sb + p];
-                q.x += ux;
-                q.y += uy;
-                q.z += uz;
+        float4 res;
+        if constexpr (ADJ) {
+            // receiver constants; a lane without a receiver sits far away so
+            // that no source is within its own or the source's cut-off
+            const float far = recv_ok ? 0.0f : 1e30f;
+            const float tfx = tx + far, tfy = ty + far, tfz = tz + far;
+            const float Gi = recv_ok ? A.gcell[sa + ia] : 0.0f;
+            const float ck = Gi * ((8.0f / kPi) * (invH * invH) * (invH * invH));
+            const float mi = pi.w;
+            GradAcc acc = {0.f, 0.f, 0.f, 0.f};
+            for (int it = 0; it < ntmax; ++it) {
+                const int tile = t0 + it;
+                const int j = tile * 16 + l16;
+                float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+                float hj = 0.0f, gj = 0.0f;
+                if (it < nt && j < nb) {
+                    const int p = dir == 26 ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
+                    q = A.xyzm[sb + p];
+                    q.x += ux;
+                    q.y += uy;
+                    q.z += uz;
+                    hj = A.Hc[sb + p];
+                    gj = A.gcell[sb + p];
+                }
+                const float sx = q.x, sy = q.y, sz = q.z, sm = q.w;
+                const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
+                const float sh2 = hj * hj;
+                const float sc = gj * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
+                if (it < nt) {
+                    const float tx = tfx, ty = tfy, tz = tfz;
+                    if (tile != diag) PVL_GRAD_STEP(0)
+                    PVL_GRAD_STEP(1) PVL_GRAD_STEP(2) PVL_GRAD_STEP(3) PVL_GRAD_STEP(4)
+                    PVL_GRAD_STEP(5) PVL_GRAD_STEP(6) PVL_GRAD_STEP(7) PVL_GRAD_STEP(8)
+                    PVL_GRAD_STEP(9) PVL_GRAD_STEP(10) PVL_GRAD_STEP(11) PVL_GRAD_STEP(12)
+                    PVL_GRAD_STEP(13) PVL_GRAD_STEP(14) PVL_GRAD_STEP(15)
+                }
             }
-            const float sx = q.x, sy = q.y, sz = q.z, sm = q.w;
-            if (it < nt) {
-                if (tile != diag) PVL_TILE_STEP(0)
-                PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
-                PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
-                PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
-                PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
+            res = make_float4(acc.gx, acc.gy, acc.gz, acc.dh);
+        } else {
+            TileAcc acc = {0.f, 0.f, 0.f, 0.f};
+            for (int it = 0; it < ntmax; ++it) {
+                const int tile = t0 + it;
+                const int j = tile * 16 + l16;
+                float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+                if (it < nt && j < nb) {
+                    const int p = (PLAIN || dir == 26) ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
+                    q = A.xyzm[sb + p];
+                    q.x += ux;
+                    q.y += uy;
+                    q.z += uz;
+                }
+                const float sx = q.x, sy = q.y, sz = q.z, sm = q.w;
+                if (it < nt) {
+                    if (tile != diag) PVL_TILE_STEP(0)
+                    PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
+                    PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
+                    PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
+                    PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
+                }
             }
+            res = make_float4(acc.rho, acc.wc, acc.dh, acc.cnt);
         }
         if (recv_ok) {
             float *dst = reinterpret_cast<float *>(&L.acc[wave][ia - r_lo]);
-            atomicAdd(dst + 0, acc.rho);
-            atomicAdd(dst + 1, acc.wc);
-            atomicAdd(dst + 2, acc.dh);
-            atomicAdd(dst + 3, acc.cnt);
+            atomicAdd(dst + 0, res.x);
+            atomicAdd(dst + 1, res.y);
+            atomicAdd(dst + 2, res.z);
+            atomicAdd(dst + 3, res.w);
         }
     }
     __syncthreads();
@@ -489,6 +598,16 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
         const float invH = 1.0f / H;
         const float norm = (8.0f / kPi) * invH * invH * invH;
         const int o = A.orig[p];
+        if constexpr (ADJ) {
+            // (sr, sw, sd) is dL/dx; sc is the sum behind drho_dh
+            if (A.grad_pos) {
+                A.grad_pos[3 * (int64_t)o + 0] = sr;
+                A.grad_pos[3 * (int64_t)o + 1] = sw;
+                A.grad_pos[3 * (int64_t)o + 2] = sd;
+            }
+            if (A.grad_h) A.grad_h[o] = A.gcell[p] * (-norm * (kGamma * invH) * (sc + 3.0f * mi));
+            continue;
+        }
         if (A.rho) A.rho[o] = norm * (sr + mi);                          // self: w(0) = 1
         if (A.wcount) A.wcount[o] = norm * (sw + 1.0f);
         if (A.drho_dh) A.drho_dh[o] = -norm * (kGamma * invH) * (sd + 3.0f * mi);  // 1/h = gamma/H
@@ -496,7 +615,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
     }
 }
 
-template <bool PLAIN>
+template <int MODE>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) k_sweep_queue(SweepArgs A)
 {
     __shared__ SweepLds L;
@@ -506,7 +625,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 
     int item = blockIdx.x;
     while (item < nitems) {
         const int2 w = item < nbig ? A.items[item] : A.items[A.cap - nsmall + (item - nbig)];
-        sweep_item<PLAIN>(A, L, w.x, w.y);
+        sweep_item<MODE>(A, L, w.x, w.y);
         __syncthreads();
         if (threadIdx.x == 0) L.item = (int)gridDim.x + atomicAdd(A.head, 1);
         __syncthreads();
@@ -535,9 +654,9 @@ __global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, 
 
 int queue_capacity(int64_t n, int64_t ncell) { return (int)(ncell + n / kChunk + 1); }
 
-hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
-                              float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                              const int *dflags, const SweepTuning &tune, bool plain)
+// Queue set-up and the persistent sweep in the given mode.
+static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                                     SweepArgs A, const SweepTuning &tune, int mode)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
     const int cap = queue_capacity(n, ncell);
@@ -546,7 +665,6 @@ hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int6
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_queue_items, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st,
                        c.cell_start, ncell, cap, c.items, c.qcount);
-    SweepArgs A;
     A.box = c.box;
     A.cell_box = c.cell_box;
     A.start = c.cell_start;
@@ -557,11 +675,6 @@ hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int6
     A.sidx = c.sidx;
     A.skey = c.skey;
     A.n = n;
-    A.rho = rho;
-    A.wcount = wcount;
-    A.drho_dh = drho_dh;
-    A.ncount = ncount;
-    A.dflags = dflags;
     A.items = c.items;
     A.qcount = c.qcount;
     A.head = c.qcount + 2;
@@ -572,11 +685,38 @@ hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int6
     int64_t grid = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
     if (grid > ncell) grid = ncell;
     if (grid < 1) grid = 1;
-    if (plain)
-        hipLaunchKernelGGL(k_sweep_queue<true>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    if (mode == kModePlain)
+        hipLaunchKernelGGL(k_sweep_queue<kModePlain>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    else if (mode == kModeAdjoint)
+        hipLaunchKernelGGL(k_sweep_queue<kModeAdjoint>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     else
-        hipLaunchKernelGGL(k_sweep_queue<false>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+        hipLaunchKernelGGL(k_sweep_queue<kModeSorted>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                              float *rho, float *wcount, float *drho_dh, int32_t *ncount,
+                              const int *dflags, const SweepTuning &tune, bool plain)
+{
+    SweepArgs A = {};
+    A.rho = rho;
+    A.wcount = wcount;
+    A.drho_dh = drho_dh;
+    A.ncount = ncount;
+    A.dflags = dflags;
+    return launch_queue_sweep(st, c, n, ncell, A, tune, plain ? kModePlain : kModeSorted);
+}
+
+hipError_t launch_backward_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                                 float *grad_pos, float *grad_h, const int *dflags,
+                                 const SweepTuning &tune)
+{
+    SweepArgs A = {};
+    A.gcell = c.gcell;
+    A.grad_pos = grad_pos;
+    A.grad_h = grad_h;
+    A.dflags = dflags;
+    return launch_queue_sweep(st, c, n, ncell, A, tune, kModeAdjoint);
 }
 
 }  // namespace pvl
