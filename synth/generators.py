@@ -26,10 +26,12 @@ from scipy.spatial import cKDTree
 __all__ = [
     "GAMMA", "GUARD", "ParticleSet", "h_for_neighbours", "finest_grid",
     "guard_violations", "uniform_set", "lattice_set", "plummer_set",
-    "adjoint_set", "batched_sets", "workload", "WORKLOADS",
+    "adjoint_set", "batched_sets", "batched_sizes", "BatchedSet", "batched_workload",
+    "workload", "WORKLOADS",
 ]
 
 GAMMA = 1.825742     # cubic-spline support H over smoothing length h (3D)
+_WORKERS = -1        # threads of the k-d tree queries (-1: all cores)
 GUARD = 1e-5         # relative guard band around every receiver's cut-off
 _CHECK = 1.25e-5     # the check is a little wider than the band it enforces
 
@@ -74,12 +76,13 @@ def _wrap32(x64: np.ndarray, L: float) -> np.ndarray:
 
 
 def guard_violations(pos: np.ndarray, h: np.ndarray, L: float = 1.0,
-                     band: float = _CHECK, workers: int = -1, subset=None,
+                     band: float = _CHECK, workers: int | None = None, subset=None,
                      tree=None) -> np.ndarray:
     """Indices i having some j with |r_ij - H_i| <= band * H_i (periodic, fp64).
     With `subset`, only those receivers are examined."""
     p = pos.astype(np.float64)
     H = GAMMA * h.astype(np.float64)
+    workers = _WORKERS if workers is None else workers
     if tree is None:
         tree = cKDTree(p, boxsize=L)
     idx = np.arange(p.shape[0]) if subset is None else np.asarray(subset)
@@ -178,12 +181,13 @@ def _plummer_points(rng, n, centre, a, L):
     return out[:n]
 
 
-def _knn_h(pos, L, ngb=48, workers=-1):
+def _knn_h(pos, L, ngb=48, workers=None):
     """h_i such that exactly ngb particles lie inside H_i = GAMMA h_i: H_i is the
     midpoint of the ngb-th and (ngb+1)-th neighbour distance.  Where that gap is
     narrower than twice the guard band, the widest gap among neighbours
     ngb-2 .. ngb+2 is used instead."""
     p = pos.astype(np.float64)
+    workers = _WORKERS if workers is None else workers
     tree = cKDTree(p, boxsize=L)
     k = ngb + 4                                   # self + neighbours 1 .. ngb+3
     d, _ = tree.query(p, k=k, workers=workers)    # d[:, 0] = 0 (self)
@@ -248,12 +252,13 @@ def adjoint_set(n: int, seed: int, jitter: float = 0.2, L: float = 1.0) -> Parti
 
 
 def batched_sets(nbox: int = 256, seed: int = 5, nmin: int = 4096, nmax: int = 262144,
-                 n_spheres_full: int = 64, full_n: int = 1 << 22,
-                 only: list | None = None) -> list:
+                 n_spheres: int = 64, only: list | None = None) -> list:
     """nbox independent unit boxes with log-uniform particle counts in [nmin, nmax];
-    even boxes are uniform with lognormal h, odd boxes are Plummer-clustered with
-    max(1, round(64 N_b / 2^22)) spheres.  `only` restricts which boxes are built
-    (the sizes and seeds of the others are still drawn)."""
+    even boxes are uniform with lognormal h, odd boxes follow the clustered
+    recipe (half uniform, half in `n_spheres` Plummer spheres, kNN h) at their
+    own size, so every clustered box has the same density contrast.  `only`
+    restricts which boxes are built (the sizes and seeds of the others are
+    still drawn)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     sizes = np.rint(np.exp(rng.uniform(math.log(nmin), math.log(nmax), nbox))).astype(np.int64)
     seeds = rng.integers(1, 2 ** 31 - 1, nbox)
@@ -266,14 +271,82 @@ def batched_sets(nbox: int = 256, seed: int = 5, nmin: int = 4096, nmax: int = 2
         if b % 2 == 0:
             out.append(uniform_set(nb, int(seeds[b]), hmode="lognormal", name=f"box{b}-uniform-{nb}"))
         else:
-            ns = max(1, int(round(n_spheres_full * nb / full_n)))
-            out.append(plummer_set(nb, int(seeds[b]), n_spheres=ns, name=f"box{b}-clustered-{nb}"))
+            out.append(plummer_set(nb, int(seeds[b]), n_spheres=n_spheres,
+                                   name=f"box{b}-clustered-{nb}"))
     return out
 
 
 def batched_sizes(nbox: int = 256, seed: int = 5, nmin: int = 4096, nmax: int = 262144):
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.rint(np.exp(rng.uniform(math.log(nmin), math.log(nmax), nbox))).astype(np.int64)
+
+
+@dataclasses.dataclass
+class BatchedSet:
+    """Independent periodic boxes laid end to end: box b holds particles
+    offsets[b] .. offsets[b+1] of the concatenated arrays."""
+    sets: list               # ParticleSet per box
+    offsets: np.ndarray      # (nbox + 1,) int64
+    pos: np.ndarray          # (N, 3) float32
+    h: np.ndarray            # (N,) float32
+    m: np.ndarray            # (N,) float32
+    boxes: list              # (Lx, Ly, Lz) per box
+    grids: list              # cells per side per box (finest legal)
+    seed: int
+    name: str
+
+    @property
+    def n(self) -> int:
+        return int(self.offsets[-1])
+
+    @property
+    def nbox(self) -> int:
+        return len(self.sets)
+
+
+def _one_box(args):
+    nbox, seed, nmin, nmax, b = args
+    return batched_sets(nbox, seed, nmin, nmax, only=[b])[b]
+
+
+def _single_threaded_trees():
+    global _WORKERS
+    _WORKERS = 1
+
+
+def batched_workload(nbox: int = 256, seed: int = 5, nmin: int = 4096, nmax: int = 262144,
+                     name: str | None = None, progress=None, jobs: int | None = None) -> BatchedSet:
+    """The boxes of batched_sets, concatenated, each quoted on its finest legal
+    grid (cells per side = floor(L / largest cut-off), at least 3).  Boxes are
+    drawn in `jobs` worker processes (fresh interpreters; each box depends only
+    on its own seed, so the result does not depend on jobs)."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import os
+    if jobs is None:
+        jobs = min(16, os.cpu_count() or 1)
+    work = [(nbox, seed, nmin, nmax, b) for b in range(nbox)]
+    sets = []
+    if jobs > 1:
+        with cf.ProcessPoolExecutor(jobs, mp_context=mp.get_context("spawn"),
+                                    initializer=_single_threaded_trees) as ex:
+            for b, s in enumerate(ex.map(_one_box, work, chunksize=1)):
+                sets.append(s)
+                if progress is not None and (b + 1) % 32 == 0:
+                    progress(f"box {b + 1}/{nbox}")
+    else:
+        for b, w in enumerate(work):
+            sets.append(_one_box(w))
+            if progress is not None and (b + 1) % 32 == 0:
+                progress(f"box {b + 1}/{nbox}")
+    offsets = np.zeros(nbox + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum([s.n for s in sets])
+    grids = [finest_grid(s.h, s.box[0]) for s in sets]
+    if min(grids) < 3:
+        raise ValueError("a box's largest cut-off leaves fewer than 3 cells per side")
+    return BatchedSet(sets, offsets, np.concatenate([s.pos for s in sets]),
+                      np.concatenate([s.h for s in sets]), np.concatenate([s.m for s in sets]),
+                      [s.box for s in sets], grids, seed, name or f"batched-{nbox}")
 
 
 # Named workloads (sizes of the paper-shaped benchmark configurations).
@@ -286,13 +359,19 @@ WORKLOADS = {
     "clustered-4m": dict(kind="plummer", n=1 << 22, seed=3),
     # 2^20 uniform particles, h jittered +-20%, with a perturbed copy for the target.
     "adjoint-1m": dict(kind="adjoint", n=1 << 20, seed=4),
+    # 256 unit boxes of 4096 .. 262144 particles (log-uniform), alternately uniform
+    # with lognormal h and Plummer-clustered, ~15.4M particles in all.
+    "batched-256": dict(kind="batched", nbox=256, seed=5),
 }
 
 
-def workload(name: str, **over) -> ParticleSet:
+def workload(name: str, progress=None, **over):
+    """The named workload: a ParticleSet, or a BatchedSet for "batched-256"."""
     spec = dict(WORKLOADS[name])
     spec.update(over)
     kind = spec.pop("kind")
+    if kind == "batched":
+        return batched_workload(spec["nbox"], spec["seed"], name=name, progress=progress)
     if kind == "uniform":
         return uniform_set(spec["n"], spec["seed"], hmode=spec["hmode"], grid=spec.get("grid"),
                            name=name)
