@@ -45,12 +45,26 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-1m-lognormal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default sweep parameters instead of the autotuned ones")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel "
                          "for scaling hardware byte counters)")
     return ap.parse_args()
+
+
+def _autotune(a, ctx, cells, g_rho, targets):
+    """Run the library's autotuner for each sweep (untimed set-up)."""
+    if a.no_autotune:
+        return {t: {"params": ctx.params(t)} for t in targets}
+    out = {}
+    for t in targets:
+        print(f"[bench] autotuning the {t} sweep", file=sys.stderr, flush=True)
+        before, after, p = ctx.autotune(cells, t, g_rho if t == "adjoint" else None, reps=3)
+        out[t] = {"default_ms": before, "tuned_ms": after, "params": p}
+    return out
 
 
 def _time_loop(fn, steps, warmup, torch):
@@ -117,6 +131,11 @@ def main():
     cand_plain, _ = ctx.census()
     ctx.set_census(False)
 
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    g_rho = torch.randn(s.n, generator=gen, device=dev)
+    tuning = _autotune(a, ctx, cells, g_rho, ("density", "plain", "adjoint"))
+
     def step_sorted():
         ctx.build_cells(pos, h, m, s.box, grid, cells)
         ctx.sort_cells(cells)
@@ -139,9 +158,6 @@ def main():
     ms_sweep, _ = _time_loop(lambda: ctx.density(cells, "sorted", out_s), a.steps, 1, torch)
     ms_sweep_plain, _ = _time_loop(lambda: ctx.density(cells, "plain", out_p), a.steps, 1, torch)
     # adjoint sweep for a seeded upstream gradient (dL/drho)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(7)
-    g_rho = torch.randn(s.n, generator=gen, device=dev)
     out_g = (torch.empty((s.n, 3), device=dev), torch.empty(s.n, device=dev))
     ms_adj, _ = _time_loop(lambda: ctx.density_backward(cells, g_rho, out_g), a.steps, 1, torch)
     ctx.check()
@@ -183,6 +199,7 @@ def main():
                       "adjoint_sweep": ms_adj},
         "candidates_per_particle": {"sorted": cand_sorted / n, "plain": cand_plain / n,
                                     "in_range": inr / n},
+        "autotune": tuning,
         "wall_ms_per_step": wall_sorted,
         "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
@@ -224,6 +241,7 @@ def bench_batched(a, b, torch, pvl, t0):
     ctx.density(cells, "sorted")
     cand, inr = ctx.census()
     ctx.set_census(False)
+    tuning = _autotune(a, ctx, cells, g_rho, ("density", "adjoint"))
 
     def step():
         ctx.build_cells_batched(off, pos, h, m, b.boxes, b.grids, cells)
@@ -304,6 +322,7 @@ def bench_batched(a, b, torch, pvl, t0):
         "stages_ms": {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep,
                       "adjoint_sweep": ms_adj},
         "candidates_per_particle": {"sorted": cand / n, "in_range": inr / n},
+        "autotune": tuning,
         "wall_ms_per_step": wall_graph,
         "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",

@@ -169,22 +169,50 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
 
 /* Tuning parameters of the sweep kernels (all results are identical up to
  * floating-point summation order; only speed changes).  Values persist on
- * the context.  The autotuner picks them per workload.
+ * the context; the sorted-pair density sweep, the adjoint sweep and the
+ * plain cell-list sweep keep separate sets: add PV_PARAM_ADJOINT or
+ * PV_PARAM_PLAIN to a parameter to address theirs (e.g. PV_PARAM_ADJOINT +
+ * PV_PARAM_CHUNK).  pv_autotune picks them per workload.
  *   PV_PARAM_REACH_ORDER  1: order each direction's receivers by the reach of
  *                         their cut-off past the shared face before blocking
  *                         them into rows of 16 (tighter loop bounds, costs a
  *                         sort per cell); 0: use the key order.  Default 0.
+ *                         The adjoint and plain sweeps ignore it.
  *   PV_PARAM_TASK_SORT    1: run row tasks longest first so the rows of a wave
  *                         finish together; 0: natural order.  Default 1.
  *   PV_PARAM_QUEUE_WGS    persistent workgroups per compute unit of the
- *                         work-queue sweeps (1..32).  Default 4. */
+ *                         work-queue sweeps (1..32).  Default 4.
+ *   PV_PARAM_CHUNK        receivers per work item, i.e. per workgroup's LDS
+ *                         accumulator tile: a multiple of 16 in 32..256.
+ *                         Cells with more particles are split into x-slabs
+ *                         of this many receivers.  Default 256.
+ * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,
     PV_PARAM_TASK_SORT = 2,
-    PV_PARAM_QUEUE_WGS = 3
+    PV_PARAM_QUEUE_WGS = 3,
+    PV_PARAM_CHUNK = 4,
+    PV_PARAM_ADJOINT = 16,
+    PV_PARAM_PLAIN = 32
 } pv_param;
-pv_status pv_set_param(pv_ctx *ctx, pv_param param, int value);
-pv_status pv_get_param(pv_ctx *ctx, pv_param param, int *value);
+pv_status pv_set_param(pv_ctx *ctx, int param, int value);
+pv_status pv_get_param(pv_ctx *ctx, int param, int *value);
+
+/* Autotuner.  Times the sorted-pair density sweep (PV_TUNE_DENSITY), the
+ * adjoint sweep (PV_TUNE_ADJOINT, for the upstream gradient grad_rho, device,
+ * n floats in original order) or the plain cell-list sweep (PV_TUNE_PLAIN)
+ * on `cells` for every combination of the
+ * parameters above (chunk 64/128/256, 1..8 workgroups per compute unit, task
+ * order, receiver order), `reps` timed runs each after one warm-up, and keeps
+ * the fastest on the context.  times_ms (host, may be NULL) receives the mean
+ * time of the setting in place before the call and of the chosen one.  The
+ * kernels write into temporary device buffers that the call allocates and
+ * frees; the call synchronises the context's stream and must not be
+ * captured.  Errors: PV_ESTATE if the cells are not sorted (density and
+ * adjoint). */
+typedef enum { PV_TUNE_DENSITY = 0, PV_TUNE_ADJOINT = 1, PV_TUNE_PLAIN = 2 } pv_tune_target;
+pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const float *grad_rho,
+                      int reps, float times_ms[2]);
 
 /* Release a cell structure.  NULL is accepted. */
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells);

@@ -21,7 +21,9 @@ struct pv_ctx {
     unsigned long long *dcensus = nullptr;  // [0] pairs tested, [1] pairs in range
     int census_on = 0;
     int *hpinned = nullptr;                 // pinned read-back area (64 bytes)
-    pvl::SweepTuning tune;
+    pvl::SweepTuning tune;                  // density sweeps
+    pvl::SweepTuning tune_adj;              // adjoint sweep
+    pvl::SweepTuning tune_plain;            // plain cell-list sweep
 };
 
 struct pv_cells {
@@ -153,7 +155,8 @@ pv_status pv_create(int device, void *hip_stream, pv_ctx **out)
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
-        ctx->tune.num_cu = prop.multiProcessorCount;
+        ctx->tune.num_cu = ctx->tune_adj.num_cu = ctx->tune_plain.num_cu =
+            prop.multiProcessorCount;
     if (hipMemset(ctx->dflags, 0, 4 * sizeof(int)) != hipSuccess ||
         hipMemset(ctx->dcensus, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -364,7 +367,8 @@ pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rh
     if (ctx->census_on) HIPCHK(ctx, pvl::launch_zero(ctx->stream, ctx->dcensus, 4));
     HIPCHK(ctx, pvl::launch_sweep(ctx->stream, cells->d, cells->n, cells->ncell, (int)algo, rho,
                                   wcount, drho_dh, ncount, ctx->dflags,
-                                  ctx->census_on ? ctx->dcensus : nullptr, ctx->tune));
+                                  ctx->census_on ? ctx->dcensus : nullptr,
+                                  algo == PV_PLAIN_CELL ? ctx->tune_plain : ctx->tune));
     return PV_OK;
 }
 
@@ -377,7 +381,7 @@ pv_status pv_density_backward(pv_ctx *ctx, const pv_cells *cells, const float *g
     if (!cells->sorted) return fail(ctx, PV_ESTATE, "pv_sort_cells must run before the adjoint");
     if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
     HIPCHK(ctx, pvl::launch_backward(ctx->stream, cells->d, cells->n, cells->ncell, grad_rho,
-                                     grad_pos, grad_h, ctx->dflags, ctx->tune));
+                                     grad_pos, grad_h, ctx->dflags, ctx->tune_adj));
     return PV_OK;
 }
 
@@ -467,29 +471,134 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2])
     return PV_OK;
 }
 
-pv_status pv_set_param(pv_ctx *ctx, pv_param param, int value)
+namespace {
+// The parameter set a pv_param value addresses, and the parameter within it.
+pvl::SweepTuning *param_set(pv_ctx *ctx, int &param)
+{
+    if (param >= PV_PARAM_PLAIN) {
+        param -= PV_PARAM_PLAIN;
+        return &ctx->tune_plain;
+    }
+    if (param >= PV_PARAM_ADJOINT) {
+        param -= PV_PARAM_ADJOINT;
+        return &ctx->tune_adj;
+    }
+    return &ctx->tune;
+}
+}  // namespace
+
+pv_status pv_set_param(pv_ctx *ctx, int param, int value)
 {
     if (!ctx) return PV_EINVAL;
+    pvl::SweepTuning &t = *param_set(ctx, param);
     switch (param) {
-    case PV_PARAM_REACH_ORDER: ctx->tune.reach_order = value ? 1 : 0; return PV_OK;
-    case PV_PARAM_TASK_SORT: ctx->tune.task_sort = value ? 1 : 0; return PV_OK;
+    case PV_PARAM_REACH_ORDER: t.reach_order = value ? 1 : 0; return PV_OK;
+    case PV_PARAM_TASK_SORT: t.task_sort = value ? 1 : 0; return PV_OK;
     case PV_PARAM_QUEUE_WGS:
         if (value < 1 || value > 32) return fail(ctx, PV_EINVAL, "queue_wgs must be 1..32");
-        ctx->tune.queue_wgs_per_cu = value;
+        t.queue_wgs_per_cu = value;
+        return PV_OK;
+    case PV_PARAM_CHUNK:
+        if (value < 32 || value > 256 || value % 16 != 0)
+            return fail(ctx, PV_EINVAL, "chunk must be a multiple of 16 in 32..256");
+        t.chunk = value;
         return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
 
-pv_status pv_get_param(pv_ctx *ctx, pv_param param, int *value)
+pv_status pv_get_param(pv_ctx *ctx, int param, int *value)
 {
     if (!ctx || !value) return PV_EINVAL;
+    const pvl::SweepTuning &t = *param_set(ctx, param);
     switch (param) {
-    case PV_PARAM_REACH_ORDER: *value = ctx->tune.reach_order; return PV_OK;
-    case PV_PARAM_TASK_SORT: *value = ctx->tune.task_sort; return PV_OK;
-    case PV_PARAM_QUEUE_WGS: *value = ctx->tune.queue_wgs_per_cu; return PV_OK;
+    case PV_PARAM_REACH_ORDER: *value = t.reach_order; return PV_OK;
+    case PV_PARAM_TASK_SORT: *value = t.task_sort; return PV_OK;
+    case PV_PARAM_QUEUE_WGS: *value = t.queue_wgs_per_cu; return PV_OK;
+    case PV_PARAM_CHUNK: *value = t.chunk; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
+}
+
+pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const float *grad_rho,
+                      int reps, float times_ms[2])
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (target != PV_TUNE_DENSITY && target != PV_TUNE_ADJOINT && target != PV_TUNE_PLAIN)
+        return fail(ctx, PV_EINVAL, "bad tuning target");
+    const bool adj = target == PV_TUNE_ADJOINT;
+    const bool plain = target == PV_TUNE_PLAIN;
+    if (adj && !grad_rho && cells->n > 0) return fail(ctx, PV_EINVAL, "grad_rho is NULL");
+    if (reps < 1 || reps > 100) return fail(ctx, PV_EINVAL, "reps must be 1..100");
+    if (!plain && !cells->sorted)
+        return fail(ctx, PV_ESTATE, "pv_sort_cells must run before tuning");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    pvl::SweepTuning &cur = adj ? ctx->tune_adj : (plain ? ctx->tune_plain : ctx->tune);
+    if (cells->n == 0) {
+        if (times_ms) times_ms[0] = times_ms[1] = 0.0f;
+        return PV_OK;
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    // scratch outputs: 4 words per particle either way
+    void *scratch = nullptr;
+    HIPCHK(ctx, hipMalloc(&scratch, sizeof(float) * 4 * (size_t)cells->n));
+    float *f = (float *)scratch;
+    const int64_t n = cells->n;
+    auto run = [&](const pvl::SweepTuning &t) -> hipError_t {
+        if (adj)
+            return pvl::launch_backward(ctx->stream, cells->d, n, cells->ncell, grad_rho, f,
+                                        f + 3 * n, ctx->dflags, t);
+        return pvl::launch_sweep(ctx->stream, cells->d, n, cells->ncell,
+                                 plain ? PV_PLAIN_CELL : PV_SORTED_PAIR, f, f + n,
+                                 f + 2 * n, (int32_t *)(f + 3 * n), ctx->dflags, nullptr, t);
+    };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    auto time_of = [&](const pvl::SweepTuning &t, float *ms) -> hipError_t {
+        hipError_t r = run(t);
+        if (r == hipSuccess) r = hipEventRecord(e0, ctx->stream);
+        for (int k = 0; k < reps && r == hipSuccess; ++k) r = run(t);
+        if (r == hipSuccess) r = hipEventRecord(e1, ctx->stream);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        if (r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
+        *ms /= (float)reps;
+        return r;
+    };
+    float before = 0.0f, best_ms = 0.0f;
+    pvl::SweepTuning best = cur;
+    if (e == hipSuccess) e = time_of(cur, &before);
+    best_ms = before;
+    static const int chunks[] = {64, 128, 256};
+    static const int wgs[] = {1, 2, 3, 4, 5, 6, 8};
+    for (int ch : chunks)
+        for (int w : wgs)
+            for (int ts = 0; ts < 2; ++ts)
+                for (int ro = 0; ro < (adj || plain ? 1 : 2); ++ro) {
+                    if (e != hipSuccess) break;
+                    pvl::SweepTuning t = cur;
+                    t.chunk = ch;
+                    t.queue_wgs_per_cu = w;
+                    t.task_sort = ts;
+                    t.reach_order = ro;
+                    float ms = 0.0f;
+                    e = time_of(t, &ms);
+                    if (e == hipSuccess && ms < best_ms) {
+                        best_ms = ms;
+                        best = t;
+                    }
+                }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (e != hipSuccess) return fail(ctx, PV_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+    cur = best;
+    if (times_ms) {
+        times_ms[0] = before;
+        times_ms[1] = best_ms;
+    }
+    return PV_OK;
 }
 
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells)

@@ -101,6 +101,7 @@ struct SweepTuning {
     int reach_order = 0;
     int task_sort = 1;
     int queue_wgs_per_cu = 4;   // persistent workgroups per compute unit
+    int chunk = 256;            // receivers per work item (multiple of 16, 32..256)
     int num_cu = 256;           // compute units of the device
 };
 

@@ -27,7 +27,8 @@
 // source tiles whose x lies within the block's range widened by its largest
 // cut-off on both sides.
 //
-// Work items are (cell, chunk of at most kChunk receivers); a cell's chunks are
+// Work items are (cell, chunk of at most `chunk` receivers, a tuning parameter
+// of at most kChunk); a cell's chunks are
 // consecutive x-slabs.  For a chunk of a large cell the active receivers of
 // every direction are compacted out of the cell's sorted lists in order.
 // Persistent workgroups take items from a device queue that lists the chunks
@@ -56,7 +57,8 @@ constexpr int kModeSorted = 0;
 constexpr int kModePlain = 1;
 constexpr int kModeAdjoint = 2;
 
-constexpr int kChunk = 256;                    // receivers per work item
+constexpr int kChunk = 256;                    // largest receivers per work item
+constexpr int kChunkMin = 32;                  // smallest (sizes the queue)
 constexpr int kMaxTasks = 27 * (kChunk / 16);  // task slots per item
 constexpr int kMaxRecv = 26 * kChunk;          // compacted receiver lists per item
 constexpr int kSelfAxis = 4;                   // d = (1, 0, 0): cell order is x order
@@ -188,6 +190,7 @@ struct SweepArgs {
     int cap;
     int reach_order;
     int task_sort;
+    int chunk;           // receivers per work item: a multiple of 16 in [kChunkMin, kChunk]
 };
 
 struct SweepLds {
@@ -212,10 +215,10 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
     const int64_t n = A.n;
     const int sa = A.start[a];
     const int na = A.start[a + 1] - sa;
-    const int r_lo = chunk * kChunk;
-    const int r_hi = min(r_lo + kChunk, na);
+    const int r_lo = chunk * A.chunk;
+    const int r_hi = min(r_lo + A.chunk, na);
     const int nr = r_hi - r_lo;
-    const bool whole = na <= kChunk;
+    const bool whole = na <= A.chunk;
     const BoxDesc &B = A.box[A.cell_box[a]];
     const CellGeom ga = cell_geom(B, a);
     const float slack = 1.52587890625e-5f * (B.edge[0] + B.edge[1] + B.edge[2]);
@@ -275,7 +278,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
                 L.recv_off[d] = roff;
                 roff += L.act_cell[d];
             }
-            L.flag = (!ADJ && A.reach_order && roff <= kMaxRecv) ? 1 : 0;
+            // the ordering keys and indices (6 bytes per receiver) borrow the
+            // accumulator space
+            L.flag = (!ADJ && A.reach_order && roff * 6 <= (int)sizeof(L.acc)) ? 1 : 0;
         }
         __syncthreads();
         listed = L.flag != 0;
@@ -284,9 +289,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             // their cut-off reaches (key + H toward a neighbour ahead on the
             // axis, key - H toward one behind); the set-up arrays borrow the
             // accumulator space
-            float *rv = reinterpret_cast<float *>(&L.acc[0][0]);
-            uint16_t *ria = reinterpret_cast<uint16_t *>(rv + kMaxRecv);
             const int nrecv = L.recv_off[25] + L.act_cell[25];
+            float *rv = reinterpret_cast<float *>(&L.acc[0][0]);
+            uint16_t *ria = reinterpret_cast<uint16_t *>(rv + nrecv);
             for (int q = tid; q < nrecv; q += blockDim.x) {
                 int dir = 0;
                 while (dir < 25 && L.recv_off[dir + 1] <= q) ++dir;
@@ -636,14 +641,14 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 
 // Work items: the chunks of cells larger than one chunk at the front, in any
 // order; single-chunk cells at the back, counted from the end.
 __global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, int cap,
-                              int2 *__restrict__ items, int *__restrict__ qcount)
+                              int chunk, int2 *__restrict__ items, int *__restrict__ qcount)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
     const int na = start[c + 1] - start[c];
     if (na <= 0) return;
-    if (na > kChunk) {
-        const int nch = (na + kChunk - 1) / kChunk;
+    if (na > chunk) {
+        const int nch = (na + chunk - 1) / chunk;
         const int p = atomicAdd(&qcount[0], nch);
         for (int k = 0; k < nch; ++k) items[p + k] = make_int2((int)c, k);
     } else {
@@ -652,7 +657,7 @@ __global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, 
     }
 }
 
-int queue_capacity(int64_t n, int64_t ncell) { return (int)(ncell + n / kChunk + 1); }
+int queue_capacity(int64_t n, int64_t ncell) { return (int)(ncell + n / kChunkMin + 1); }
 
 // Queue set-up and the persistent sweep in the given mode.
 static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
@@ -664,7 +669,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     hipError_t e = launch_zero(st, c.qcount, 3);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_queue_items, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st,
-                       c.cell_start, ncell, cap, c.items, c.qcount);
+                       c.cell_start, ncell, cap, tune.chunk, c.items, c.qcount);
     A.box = c.box;
     A.cell_box = c.cell_box;
     A.start = c.cell_start;
@@ -681,6 +686,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.cap = cap;
     A.reach_order = tune.reach_order;
     A.task_sort = tune.task_sort;
+    A.chunk = tune.chunk;
     // persistent workgroups: a few per compute unit, never more than the cells
     int64_t grid = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
     if (grid > ncell) grid = ncell;

@@ -27,9 +27,13 @@ EXPORTS = (
     "pv_create", "pv_destroy", "pv_set_stream", "pv_last_error", "pv_build_cells",
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
-    "pv_free_cells", "pv_set_param", "pv_get_param",
+    "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune",
 )
-PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3}
+PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4}
+PV_PARAM_ADJOINT = 16
+PV_PARAM_PLAIN = 32
+TUNE_TARGETS = {"density": 0, "adjoint": 1, "plain": 2}
+_SET_OFFSET = {"density": 0, "adjoint": PV_PARAM_ADJOINT, "plain": PV_PARAM_PLAIN}
 
 _STATUS = {
     PV_EINVAL: "PV_EINVAL", PV_ENOMEM: "PV_ENOMEM", PV_EHIP: "PV_EHIP",
@@ -74,6 +78,7 @@ def load_library(path: str = LIB_PATH):
         "pv_free_cells": ([P, P], i32),
         "pv_set_param": ([P, i32, i32], i32),
         "pv_get_param": ([P, i32, P], i32),
+        "pv_autotune": ([P, P, i32, P, i32, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -262,14 +267,30 @@ class Context:
         self._sync_stream()
         self._call("pv_check")
 
-    def set_param(self, name: str, value: int) -> None:
-        """Sweep tuning parameter (see pv_param in include/pvl.h)."""
-        self._call("pv_set_param", PARAMS[name], int(value))
+    def set_param(self, name: str, value: int, sweep: str = "density") -> None:
+        """Tuning parameter (see pv_param in include/pvl.h) of one sweep:
+        "density" (sorted pair), "adjoint" or "plain"."""
+        self._call("pv_set_param", PARAMS[name] + _SET_OFFSET[sweep], int(value))
 
-    def get_param(self, name: str) -> int:
+    def get_param(self, name: str, sweep: str = "density") -> int:
         v = C.c_int()
-        self._call("pv_get_param", PARAMS[name], C.byref(v))
+        self._call("pv_get_param", PARAMS[name] + _SET_OFFSET[sweep], C.byref(v))
         return v.value
+
+    def params(self, sweep: str = "density") -> dict:
+        return {k: self.get_param(k, sweep) for k in PARAMS}
+
+    def autotune(self, cells: Cells, target: str = "density", grad_rho=None, reps: int = 3):
+        """Pick the fastest parameters of one sweep ("density", "adjoint" or
+        "plain") for these cells (pv_autotune).  Returns (ms before, ms after,
+        chosen parameters)."""
+        if target == "adjoint":
+            _dev_f32(grad_rho, cells.n, 0, "grad_rho", self.device)
+        t = (C.c_float * 2)()
+        self._sync_stream()
+        self._call("pv_autotune", cells.handle, TUNE_TARGETS[target],
+                   _ptr(grad_rho) if target == "adjoint" else None, int(reps), t)
+        return float(t[0]), float(t[1]), self.params(target)
 
     def set_census(self, on: bool) -> None:
         self._call("pv_set_census", 1 if on else 0)

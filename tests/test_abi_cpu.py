@@ -90,3 +90,31 @@ def test_python_binding_refuses_without_library(tmp_path):
             pvl.load_library(str(tmp_path / "missing.so"))
     finally:
         pvl._lib = saved
+
+
+def test_tuning_parameters_without_gpu(lib, vctx):
+    """Parameters are validated and kept per sweep (density / adjoint)."""
+    from paper_1804_06231_amd.pvl import PARAMS, PV_PARAM_ADJOINT, PV_PARAM_PLAIN
+    v = C.c_int()
+    defaults = {"reach_order": 0, "task_sort": 1, "queue_wgs": 4, "chunk": 256}
+    for name, p in PARAMS.items():
+        for off in (0, PV_PARAM_ADJOINT, PV_PARAM_PLAIN):
+            assert lib.pv_get_param(vctx, p + off, C.byref(v)) == 0
+            assert v.value == defaults[name], name
+    assert lib.pv_set_param(vctx, PARAMS["chunk"], 128) == 0
+    assert lib.pv_get_param(vctx, PARAMS["chunk"], C.byref(v)) == 0 and v.value == 128
+    assert lib.pv_get_param(vctx, PARAMS["chunk"] + PV_PARAM_ADJOINT, C.byref(v)) == 0
+    assert v.value == 256                                         # the adjoint's is separate
+    assert lib.pv_get_param(vctx, PARAMS["chunk"] + PV_PARAM_PLAIN, C.byref(v)) == 0
+    assert v.value == 256
+    for bad in (16, 100, 272, 0):
+        assert lib.pv_set_param(vctx, PARAMS["chunk"], bad) == -1
+    assert lib.pv_get_param(vctx, PARAMS["chunk"], C.byref(v)) == 0 and v.value == 128
+    assert lib.pv_set_param(vctx, PARAMS["queue_wgs"], 0) == -1
+    assert lib.pv_set_param(vctx, PARAMS["queue_wgs"], 33) == -1
+    assert lib.pv_set_param(vctx, 9, 1) == -1                     # unknown
+    assert lib.pv_get_param(vctx, 9, C.byref(v)) == -1
+    # the autotuner validates before it needs a device
+    t = (C.c_float * 2)()
+    assert lib.pv_autotune(vctx, None, 0, None, 3, t) == -1
+    assert lib.pv_autotune(None, None, 0, None, 3, t) == -1

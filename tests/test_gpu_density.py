@@ -237,3 +237,76 @@ def test_clustered_small(ctx):
         _flush(f"clustered-60k {algo}")
         cells, out = run_density(ctx, s, algo)
         compare_density(out, oracle_for(s).density(), label=f"clustered-{algo}")
+
+
+@pytest.fixture(scope="module")
+def clustered_ref():
+    s = plummer_set(40000, 82, n_spheres=16)
+    o = oracle_for(s)
+    rng = np.random.Generator(np.random.PCG64(83))
+    G = rng.standard_normal(s.n).astype(np.float32)
+    return s, o.density(), G, o.grad(G.astype(np.float64))
+
+
+@pytest.mark.parametrize("chunk,wgs,task_sort,reach", [
+    (32, 1, 0, 0), (64, 2, 1, 1), (128, 8, 0, 1), (256, 3, 1, 1), (48, 5, 1, 0)])
+def test_tuning_parameters_keep_results(ctx, clustered_ref, chunk, wgs, task_sort, reach):
+    """Every tuning setting gives the oracle's results: cells larger than the
+    chunk are split into several work items, receivers may be reach-ordered."""
+    s, ref, G, gref = clustered_ref
+    for sw in ("density", "adjoint"):
+        ctx.set_param("chunk", chunk, sw)
+        ctx.set_param("queue_wgs", wgs, sw)
+        ctx.set_param("task_sort", task_sort, sw)
+        ctx.set_param("reach_order", reach, sw)
+    try:
+        _flush(f"tuning chunk={chunk} wgs={wgs} task_sort={task_sort} reach={reach}")
+        cells, out = run_density(ctx, s, "sorted")
+        assert cells.info()["max_occupancy"] > 2 * chunk
+        compare_density(out, ref, label=f"chunk {chunk}")
+        gp, gh = ctx.density_backward(cells, torch.from_numpy(G).to(dev()))
+        ctx.check()
+        gp, gh = gp.cpu().numpy(), gh.cpu().numpy()
+        ex = np.max(np.abs(gp - gref["gx"]) / np.maximum(gref["gx_abs"], 1e-300))
+        eh = np.max(np.abs(gh - gref["gh"]) / np.maximum(gref["gh_abs"], 1e-300))
+        assert ex < 1e-5 and eh < 1e-5, (ex, eh)
+    finally:
+        for sw in ("density", "adjoint"):
+            ctx.set_param("chunk", 256, sw)
+            ctx.set_param("queue_wgs", 4, sw)
+            ctx.set_param("task_sort", 1, sw)
+            ctx.set_param("reach_order", 0, sw)
+
+
+def test_autotune(ctx, clustered_ref):
+    """The autotuner keeps a setting at least as fast as the one in place, and
+    the tuned sweeps still give the oracle's results."""
+    import paper_1804_06231_amd as pvl
+    s, ref, G, gref = clustered_ref
+    c2 = pvl.Context(0)
+    try:
+        pos, h, m = upload(s)
+        cells = c2.build_cells(pos, h, m, s.box)
+        c2.sort_cells(cells)
+        before, after, p = c2.autotune(cells, "density", reps=2)
+        _flush(f"autotune density: {before:.3f} -> {after:.3f} ms, {p}")
+        assert after <= before and p["chunk"] in (64, 128, 256) and 1 <= p["queue_wgs"] <= 8
+        g = torch.from_numpy(G).to(dev())
+        before_a, after_a, pa = c2.autotune(cells, "adjoint", g, reps=2)
+        _flush(f"autotune adjoint: {before_a:.3f} -> {after_a:.3f} ms, {pa}")
+        assert after_a <= before_a and pa["reach_order"] == 0
+        before_p, after_p, pp = c2.autotune(cells, "plain", reps=1)
+        _flush(f"autotune plain: {before_p:.3f} -> {after_p:.3f} ms, {pp}")
+        assert after_p <= before_p
+        out = [t.cpu().numpy() for t in c2.density(cells, "sorted")]
+        compare_density(out, ref, label="tuned")
+        out = [t.cpu().numpy() for t in c2.density(cells, "plain")]
+        compare_density(out, ref, label="tuned plain")
+        gp, gh = c2.density_backward(cells, g)
+        c2.check()
+        ex = np.max(np.abs(gp.cpu().numpy() - gref["gx"]) / np.maximum(gref["gx_abs"], 1e-300))
+        assert ex < 1e-5
+        with pytest.raises(pvl.PVError):
+            c2.autotune(c2.build_cells(pos, h, m, s.box), "density")   # not sorted
+    finally:
+        c2.close()
