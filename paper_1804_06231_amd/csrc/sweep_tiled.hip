@@ -519,6 +519,14 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
         int ntmax = nt;
         ntmax = max(ntmax, __shfl_xor(ntmax, 16));
         ntmax = max(ntmax, __shfl_xor(ntmax, 32));
+        // source of this lane in tile `it` of the row (-1: none).  The loads are
+        // software-pipelined: while a tile is computed, the next tile's
+        // source data and the index of the one after are in flight.
+        auto src_of = [&](int it) -> int {
+            const int j = (t0 + it) * 16 + l16;
+            if (it >= nt || j >= nb) return -1;
+            return (PLAIN || dir == 26) ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
+        };
         float4 res;
         if constexpr (ADJ) {
             // receiver constants; a lane without a receiver sits far away so
@@ -529,21 +537,27 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             const float ck = Gi * ((8.0f / kPi) * (invH * invH) * (invH * invH));
             const float mi = pi.w;
             GradAcc acc = {0.f, 0.f, 0.f, 0.f};
+            float4 qn;
+            float hn, gn;
+            auto load_src = [&](int p) {
+                qn = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+                hn = gn = 0.0f;
+                if (p >= 0) {
+                    qn = A.xyzm[sb + p];
+                    hn = A.Hc[sb + p];
+                    gn = A.gcell[sb + p];
+                }
+            };
+            int pn = src_of(0);
+            load_src(pn);
+            pn = src_of(1);
             for (int it = 0; it < ntmax; ++it) {
                 const int tile = t0 + it;
-                const int j = tile * 16 + l16;
-                float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-                float hj = 0.0f, gj = 0.0f;
-                if (it < nt && j < nb) {
-                    const int p = dir == 26 ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
-                    q = A.xyzm[sb + p];
-                    q.x += ux;
-                    q.y += uy;
-                    q.z += uz;
-                    hj = A.Hc[sb + p];
-                    gj = A.gcell[sb + p];
-                }
-                const float sx = q.x, sy = q.y, sz = q.z, sm = q.w;
+                const float4 q = qn;
+                const float hj = hn, gj = gn;
+                load_src(pn);
+                pn = src_of(it + 2);
+                const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
                 const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
                 const float sh2 = hj * hj;
                 const float sc = gj * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
@@ -559,18 +573,18 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             res = make_float4(acc.gx, acc.gy, acc.gz, acc.dh);
         } else {
             TileAcc acc = {0.f, 0.f, 0.f, 0.f};
+            auto load_src = [&](int p) {
+                return p >= 0 ? A.xyzm[sb + p] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
+            };
+            int pn = src_of(0);
+            float4 qn = load_src(pn);
+            pn = src_of(1);
             for (int it = 0; it < ntmax; ++it) {
                 const int tile = t0 + it;
-                const int j = tile * 16 + l16;
-                float4 q = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-                if (it < nt && j < nb) {
-                    const int p = (PLAIN || dir == 26) ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
-                    q = A.xyzm[sb + p];
-                    q.x += ux;
-                    q.y += uy;
-                    q.z += uz;
-                }
-                const float sx = q.x, sy = q.y, sz = q.z, sm = q.w;
+                const float4 q = qn;
+                qn = load_src(pn);
+                pn = src_of(it + 2);
+                const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
                 if (it < nt) {
                     if (tile != diag) PVL_TILE_STEP(0)
                     PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
@@ -621,7 +635,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(5, 8))) k_sweep_queue(SweepArgs A)
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(MODE == kModeAdjoint ? 4 : 5, 8))) k_sweep_queue(SweepArgs A)
 {
     __shared__ SweepLds L;
     if (A.dflags[0]) return;
