@@ -1,71 +1,154 @@
 // Cell binning: a counting sort of the particles into the cells of each box
 // (Section 2 of the paper: cells of edge >= the cut-off, each cell's particles
 // stored together), finished by a per-cell sort on (x, original index): the
-// cell-ordered layout then depends neither on atomic arrival order nor on the
-// order of the input, and consecutive particles of a cell form x-slabs.
+// cell-ordered layout then depends neither on arrival order nor on the order
+// of the input, and consecutive particles of a cell form x-slabs.
+//
+// The counting sort needs no global atomics.  The particles of each box are
+// cut into chunks (one workgroup each); a workgroup counts its chunk's
+// particles per cell in LDS (the LDS atomic gives each particle its slot among
+// the chunk's particles of that cell) and writes the counts as one row of the
+// box's chunks x cells matrix (coalesced).  A pass down every cell's column
+// turns the counts into the cell's offsets per chunk and its total; the scan
+// of the totals gives the cell starts.
 //
 //   k_box_hmax    max cut-off per box (auto grid)
-//   k_bin_count   cell of every particle, per-cell counts and max cut-off
+//   k_bin_local   cell of every particle, per-chunk cell counts, cut-off check
+//   k_bin_columns per cell: offsets of the chunks' shares, particle count
 //   k_scan        exclusive scan of the counts -> cell_start; occupancy check
+//                 (k_tile_sums / k_scan / k_tile_scan when there are many cells)
 //   k_scatter     particles -> scatter-ordered staging records
 //   k_cell_finish per cell: order by (x, original index), shift positions to
 //                 the cell origin, write the cell-ordered structure of arrays
+//                 and the cell's largest cut-off (one kernel per size class)
 #include "device_util.h"
 
 namespace pvl {
 
-__global__ void k_box_hmax(const BoxDesc *__restrict__ box, int nbox, int64_t n,
-                           const float *__restrict__ h, uint32_t *__restrict__ box_hmax)
+// Largest cut-off per box.  A workgroup reduces a contiguous range of
+// kBoxHmaxSpan particles; when the range lies in one box the workgroup issues a
+// single atomic, otherwise (a box boundary inside the range) each lane flushes
+// its running maximum whenever its box changes.
+constexpr int kBoxHmaxSpan = 16 * kBlock;
+
+__global__ void __launch_bounds__(kBlock) k_box_hmax(const BoxDesc *__restrict__ box, int nbox,
+                                                     int64_t n, const float *__restrict__ h,
+                                                     uint32_t *__restrict__ box_hmax)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t v = 0;
-    int b = -1;
-    if (p < n) {
-        b = box_of_particle(box, nbox, p);
-        v = __float_as_uint(kGamma * h[p]);
-    }
-    // reduce within the wavefront when every lane has the same box
-    int b0 = __shfl(b, 0);
-    bool same = __all(b == b0);
-    if (same) {
-        for (int off = 32; off > 0; off >>= 1) {
-            uint32_t o = __shfl_xor(v, off);
-            v = v > o ? v : o;
+    __shared__ uint32_t red[kBlock / 64];
+    const int64_t p0 = (int64_t)blockIdx.x * kBoxHmaxSpan;
+    const int64_t p1 = p0 + kBoxHmaxSpan < n ? p0 + kBoxHmaxSpan : n;
+    const int b0 = box_of_particle(box, nbox, p0);
+    const bool one_box = box_of_particle(box, nbox, p1 - 1) == b0;
+    uint32_t v = 0;   // positive floats order as their bits
+    int cur = b0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        if (!one_box) {
+            const int b = box_of_particle(box, nbox, p);
+            if (b != cur) {
+                if (v) atomicMax(&box_hmax[cur], v);
+                cur = b;
+                v = 0;
+            }
         }
-        if ((threadIdx.x & 63) == 0 && b0 >= 0) atomicMax(&box_hmax[b0], v);
-    } else if (b >= 0) {
-        atomicMax(&box_hmax[b], v);
+        v = max(v, __float_as_uint(kGamma * h[p]));
+    }
+    if (!one_box) {
+        if (v) atomicMax(&box_hmax[cur], v);
+        return;
+    }
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = max(m, red[w]);
+        atomicMax(&box_hmax[b0], m);
     }
 }
 
-__global__ void k_bin_count(const BoxDesc *__restrict__ box, int nbox, int64_t n,
-                            const float *__restrict__ pos, const float *__restrict__ h,
-                            int32_t *__restrict__ cellid, int32_t *__restrict__ slot,
-                            int32_t *__restrict__ count, int *__restrict__ dflags)
+// Cells per LDS histogram pass of k_bin_local (64 KB); boxes with more cells
+// are counted in several passes over the chunk.
+constexpr int kBinSeg = 16384;
+constexpr int kBinThreads = 1024;
+
+// One workgroup per chunk: blocks[g] = (box, chunk index within the box, first
+// particle, end).  Writes cellid and slot of every particle and the chunk's
+// row of the box's count matrix: binm[moff + chunk * cells of the box + local cell].
+__global__ void __launch_bounds__(kBinThreads) k_bin_local(
+    const BoxDesc *__restrict__ box, const int4 *__restrict__ blocks,
+    const float *__restrict__ pos, const float *__restrict__ h, int32_t *__restrict__ cellid,
+    int32_t *__restrict__ slot, int32_t *__restrict__ binm, int *__restrict__ dflags)
 {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const BoxDesc &B = box[box_of_particle(box, nbox, p)];
-    float x = wrap_coord(pos[3 * p + 0], B.L[0], 1.0f / B.L[0]);
-    float y = wrap_coord(pos[3 * p + 1], B.L[1], 1.0f / B.L[1]);
-    float z = wrap_coord(pos[3 * p + 2], B.L[2], 1.0f / B.L[2]);
-    int cx = cell_coord(x, B.inv_edge[0], B.g[0]);
-    int cy = cell_coord(y, B.inv_edge[1], B.g[1]);
-    int cz = cell_coord(z, B.inv_edge[2], B.g[2]);
-    int c = B.cell_off + (cx * B.g[1] + cy) * B.g[2] + cz;
-    cellid[p] = c;
-    // arrival order within the cell; made deterministic later by the
-    // per-cell sort on the original index
-    slot[p] = atomicAdd(&count[c], 1);
-    float H = kGamma * h[p];
-    float emin = fminf(B.edge[0], fminf(B.edge[1], B.edge[2]));
-    if (!(H <= emin) || !(H > 0.0f)) atomicOr(dflags, kErrGrid);
+    __shared__ uint32_t hist[kBinSeg];
+    const int4 blk = blocks[blockIdx.x];
+    const BoxDesc &B = box[blk.x];
+    const int ncb = B.g[0] * B.g[1] * B.g[2];
+    const float inv0 = 1.0f / B.L[0], inv1 = 1.0f / B.L[1], inv2 = 1.0f / B.L[2];
+    const float emin = fminf(B.edge[0], fminf(B.edge[1], B.edge[2]));
+    bool bad = false;
+    for (int seg = 0; seg < ncb; seg += kBinSeg) {
+        const int segn = min(kBinSeg, ncb - seg);
+        for (int t = threadIdx.x; t < segn; t += blockDim.x) hist[t] = 0u;
+        __syncthreads();
+        for (int p = blk.z + threadIdx.x; p < blk.w; p += blockDim.x) {
+            int cl;
+            if (seg == 0) {
+                const float x = wrap_coord(pos[3 * (int64_t)p + 0], B.L[0], inv0);
+                const float y = wrap_coord(pos[3 * (int64_t)p + 1], B.L[1], inv1);
+                const float z = wrap_coord(pos[3 * (int64_t)p + 2], B.L[2], inv2);
+                const int cx = cell_coord(x, B.inv_edge[0], B.g[0]);
+                const int cy = cell_coord(y, B.inv_edge[1], B.g[1]);
+                const int cz = cell_coord(z, B.inv_edge[2], B.g[2]);
+                cl = (cx * B.g[1] + cy) * B.g[2] + cz;
+                cellid[p] = B.cell_off + cl;
+                const float H = kGamma * h[p];
+                bad |= !(H <= emin) || !(H > 0.0f);
+            } else {
+                cl = cellid[p] - B.cell_off;
+            }
+            // arrival order within the chunk's share of the cell; made
+            // deterministic later by the per-cell sort on the original index
+            if (cl >= seg && cl < seg + segn) slot[p] = (int32_t)atomicAdd(&hist[cl - seg], 1u);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < segn; t += blockDim.x)
+            binm[(int64_t)B.moff + (int64_t)blk.y * ncb + seg + t] = (int32_t)hist[t];
+        __syncthreads();
+    }
+    if (bad) atomicOr(dflags, kErrGrid);
 }
 
-// Single workgroup: exclusive scan of count[0..ncell) into start[0..ncell],
-// largest count into dflags[1], overflow flagged.
-__global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restrict__ count,
-                                                int32_t *__restrict__ start,
+// Per cell: the chunks' counts become exclusive offsets (in place) and the
+// cell's particle count goes to count[c].  Reads and writes are coalesced
+// across the cells of a box.
+__global__ void k_bin_columns(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
+                              int64_t ncell, int32_t *__restrict__ binm, int32_t *__restrict__ count)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncell) return;
+    const BoxDesc &B = box[cell_box[c]];
+    const int64_t ncb = (int64_t)B.g[0] * B.g[1] * B.g[2];
+    int32_t *col = binm + B.moff + (c - B.cell_off);
+    int32_t run = 0;
+    // eight independent loads in flight per step
+    for (int j0 = 0; j0 < B.nblk; j0 += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = j0 + k < B.nblk ? col[(j0 + k) * ncb] : 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (j0 + k < B.nblk) col[(j0 + k) * ncb] = run;
+            run += v[k];
+        }
+    }
+    count[c] = run;
+}
+
+// Single workgroup: exclusive scan of count[0..ncell) into start[0..ncell]
+// (the two may be the same array); with dflags, the largest count goes to
+// dflags[1] and overflow is flagged.
+__global__ void __launch_bounds__(1024) k_scan(int64_t ncell, const int32_t *count, int32_t *start,
                                                 int *__restrict__ dflags)
 {
     __shared__ int32_t part[1024];
@@ -95,6 +178,7 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restric
         run += v;
     }
     if (threadIdx.x == T - 1) start[ncell] = part[T - 1];
+    if (!dflags) return;
     for (int off = 32; off > 0; off >>= 1) {
         int32_t o = __shfl_xor(mx, off);
         mx = mx > o ? mx : o;
@@ -105,20 +189,112 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, int32_t *__restric
     }
 }
 
+// Many cells: the counts are scanned in tiles of kScanTile.  k_tile_sums sums
+// every tile (and checks occupancy), k_scan scans the tile sums into tile
+// offsets, k_tile_scan scans each tile from its offset.
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 8;
+constexpr int kScanTile = kScanThreads * kScanPer;
+
+int scan_scratch_words(int64_t ncell) { return (int)(ncell / kScanTile + 2); }
+
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *red, int32_t &total)
+{
+    // inclusive scan in each wave, then over the wave totals
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t inc = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(inc, off);
+        if (lane >= off) inc += o;
+    }
+    if (lane == 63) red[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        const int nw = (int)(blockDim.x >> 6);
+        int32_t w = lane < nw ? red[lane] : 0;
+        int32_t winc = w;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t o = __shfl_up(winc, off);
+            if (lane >= off) winc += o;
+        }
+        if (lane < nw) red[lane] = winc - w;
+        if (lane == nw - 1) red[63] = winc;
+    }
+    __syncthreads();
+    total = red[63];
+    return red[wave] + inc - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_tile_sums(int64_t ncell,
+                                                            const int32_t *__restrict__ count,
+                                                            int32_t *__restrict__ tsum,
+                                                            int *__restrict__ dflags)
+{
+    __shared__ int32_t red[64];
+    const int64_t c0 = (int64_t)blockIdx.x * kScanTile;
+    int32_t sum = 0, mx = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        const int64_t c = c0 + (int64_t)k * kScanThreads + threadIdx.x;   // coalesced
+        const int32_t v = c < ncell ? count[c] : 0;
+        sum += v;
+        mx = max(mx, v);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sum += __shfl_xor(sum, off);
+        mx = max(mx, __shfl_xor(mx, off));
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        tsum[blockIdx.x] = t;
+    }
+    if (dflags && (threadIdx.x & 63) == 0) {
+        atomicMax(&dflags[1], mx);
+        if (mx > PV_MAX_CELL) atomicOr(&dflags[0], kErrOverflow);
+    }
+}
+
+// count and start may be the same array (each thread reads its values first).
+__global__ void __launch_bounds__(kScanThreads) k_tile_scan(int64_t ncell, const int32_t *count,
+                                                            const int32_t *__restrict__ toff,
+                                                            int32_t *start)
+{
+    __shared__ int32_t red[64];
+    const int64_t c0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    int32_t sum = 0;
+    for (int k = 0; k < kScanPer; ++k) {
+        v[k] = c0 + k < ncell ? count[c0 + k] : 0;
+        sum += v[k];
+    }
+    int32_t total;
+    int32_t run = toff[blockIdx.x] + block_exclusive_scan(sum, red, total);
+    for (int k = 0; k < kScanPer; ++k) {
+        if (c0 + k < ncell) start[c0 + k] = run;
+        run += v[k];
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) start[ncell] = toff[gridDim.x];
+}
+
 // Staging record of one particle: 32 bytes, written with one aligned store pair.
-__global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n,
+__global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n, int chunk,
                           const float *__restrict__ pos, const float *__restrict__ h,
                           const float *__restrict__ mass, const int32_t *__restrict__ cellid,
-                          const int32_t *__restrict__ slot, const int32_t *__restrict__ start,
-                          float4 *__restrict__ stage)
+                          const int32_t *__restrict__ slot, const int32_t *__restrict__ binm,
+                          const int32_t *__restrict__ start, float4 *__restrict__ stage)
 {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const BoxDesc &B = box[box_of_particle(box, nbox, p)];
+    const int j = (int)((p - B.part_off) / chunk);
     float x = wrap_coord(pos[3 * p + 0], B.L[0], 1.0f / B.L[0]);
     float y = wrap_coord(pos[3 * p + 1], B.L[1], 1.0f / B.L[1]);
     float z = wrap_coord(pos[3 * p + 2], B.L[2], 1.0f / B.L[2]);
-    int64_t q = start[cellid[p]] + slot[p];
+    const int64_t ncb = (int64_t)B.g[0] * B.g[1] * B.g[2];
+    const int c = cellid[p];
+    const int64_t q = start[c] + binm[(int64_t)B.moff + j * ncb + (c - B.cell_off)] + slot[p];
     stage[2 * q] = make_float4(x, y, z, kGamma * h[p]);
     stage[2 * q + 1] = make_float4(mass[p], __int_as_float((int)p), 0.f, 0.f);
 }
@@ -127,14 +303,107 @@ __global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n,
 // original index) with a bucket sort in LDS (buckets are equal x ranges of
 // the cell; the exact rank inside a bucket compares bucket mates), shift the
 // positions to the cell origin, write the cell-ordered arrays and the cell's
-// largest cut-off.
-constexpr int kFinishMaxBuckets = 1024;
-
-__global__ void __launch_bounds__(kBlock) k_cell_finish(
+// largest cut-off.  Cells of at most MAXC particles (64 or 256) take a
+// workgroup of MAXC threads, one particle each, with small LDS arrays, so
+// that many cells share a compute unit; larger cells take k_cell_finish_large.
+template <int MAXC, int NB>
+__global__ void __launch_bounds__(MAXC) k_cell_finish_small(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
-    uint32_t *__restrict__ cell_hmax)
+    uint32_t *__restrict__ cell_hmax, int min_cnt)
+{
+    __shared__ float key[MAXC];
+    __shared__ int32_t okey[MAXC];
+    __shared__ uint16_t border[MAXC];
+    __shared__ uint32_t hist[NB];
+    __shared__ uint32_t hred[MAXC / 64];
+    const int c = blockIdx.x;
+    const int s0 = start[c];
+    const int cnt = start[c + 1] - s0;
+    if (cnt < min_cnt || cnt > MAXC) return;
+    if (cnt == 0) {
+        if (threadIdx.x == 0) cell_hmax[c] = 0u;
+        return;
+    }
+    const BoxDesc &B = box[cell_box[c]];
+    const CellGeom G = cell_geom(B, c);
+    const float scale = (float)NB / B.edge[0];
+    for (int t = threadIdx.x; t < NB; t += blockDim.x) hist[t] = 0u;
+    const int r = threadIdx.x;
+    const bool on = r < cnt;
+    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), m = a;
+    if (on) {
+        a = stage[2 * (int64_t)(s0 + r)];
+        m = stage[2 * (int64_t)(s0 + r) + 1];
+    }
+    const float k = a.x - G.ox;
+    const int my_orig = __float_as_int(m.y);
+    key[r] = k;
+    okey[r] = my_orig;
+    int b = (int)(k * scale);
+    b = b < 0 ? 0 : (b >= NB ? NB - 1 : b);
+    __syncthreads();
+    const uint32_t sl = on ? atomicAdd(&hist[b], 1u) : 0u;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        constexpr int per = NB >= 64 ? NB / 64 : 1;
+        uint32_t v[per];
+        uint32_t loc = 0;
+#pragma unroll
+        for (int q = 0; q < per; ++q) {
+            v[q] = lane * per + q < NB ? hist[lane * per + q] : 0u;
+            loc += v[q];
+        }
+        uint32_t inc = loc;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+            if (lane >= off) inc += o;
+        }
+        uint32_t run = inc - loc;
+#pragma unroll
+        for (int q = 0; q < per; ++q) {
+            if (lane * per + q < NB) hist[lane * per + q] = run;
+            run += v[q];
+        }
+    }
+    __syncthreads();
+    const int q0 = (int)hist[b];
+    if (on) border[q0 + (int)sl] = (uint16_t)r;
+    __syncthreads();
+    uint32_t hm = 0u;
+    if (on) {
+        const int q1 = b + 1 < NB ? (int)hist[b + 1] : cnt;
+        int rank = q0;
+        for (int q = q0; q < q1; ++q) {
+            const int r2 = border[q];
+            const float k2 = key[r2];
+            rank += (k2 < k) || (k2 == k && okey[r2] < my_orig);
+        }
+        xyzm[s0 + rank] = make_float4(k, a.y - G.oy, a.z - G.oz, m.x);
+        Hout[s0 + rank] = a.w;
+        orig[s0 + rank] = my_orig;
+        hm = __float_as_uint(a.w);
+    }
+    // largest cut-off of the cell (positive floats order as their bits)
+    for (int off = 32; off > 0; off >>= 1) hm = max(hm, (uint32_t)__shfl_xor((int)hm, off));
+    if ((threadIdx.x & 63) == 0) hred[threadIdx.x >> 6] = hm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t mx = 0u;
+        for (int w = 0; w < MAXC / 64; ++w) mx = max(mx, hred[w]);
+        cell_hmax[c] = mx;
+    }
+}
+
+constexpr int kFinishMaxBuckets = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_cell_finish_large(
+    const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
+    const int32_t *__restrict__ start, const float4 *__restrict__ stage,
+    float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
+    uint32_t *__restrict__ cell_hmax, int min_cnt)
 {
     __shared__ float key[PV_MAX_CELL];
     __shared__ uint16_t slot[PV_MAX_CELL];
@@ -144,7 +413,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish(
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
-    if (cnt <= 0 || cnt > PV_MAX_CELL) {
+    if (cnt < min_cnt) return;
+    if (cnt > PV_MAX_CELL) {
         if (threadIdx.x == 0) cell_hmax[c] = 0u;
         return;
     }
@@ -262,28 +532,88 @@ hipError_t launch_box_hmax(hipStream_t st, const DevCells &c, int nbox, int64_t 
                            const float *h)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_box_hmax, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox, n,
-                       h, c.box_hmax);
+    hipLaunchKernelGGL(k_box_hmax, dim3(blocks_for(n, kBoxHmaxSpan)), dim3(kBlock), 0, st, c.box,
+                       nbox, n, h, c.box_hmax);
     return hipGetLastError();
 }
 
-hipError_t launch_bin(hipStream_t st, const DevCells &c, int nbox, int64_t n, int64_t ncell,
-                      const float *pos, const float *h, const float *mass, int *dflags)
+// Exclusive scan of count[0..len) into start[0..len] (in place allowed);
+// with dflags, occupancy is checked on the way.
+static void launch_scan(hipStream_t st, int64_t len, const int32_t *count, int32_t *start,
+                        int32_t *scan_tmp, int *dflags)
+{
+    if (len <= kScanTile) {
+        hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, len, count, start, dflags);
+        return;
+    }
+    const unsigned nt = (unsigned)((len + kScanTile - 1) / kScanTile);
+    hipLaunchKernelGGL(k_tile_sums, dim3(nt), dim3(kScanThreads), 0, st, len, count, scan_tmp,
+                       dflags);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, (int64_t)nt, scan_tmp, scan_tmp,
+                       (int *)nullptr);
+    hipLaunchKernelGGL(k_tile_scan, dim3(nt), dim3(kScanThreads), 0, st, len, count, scan_tmp,
+                       start);
+}
+
+hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, int nbox, int64_t n,
+                      int64_t ncell, const float *pos, const float *h, const float *mass,
+                      int *dflags)
 {
     hipLaunchKernelGGL(k_cell_box, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box, nbox,
                        ncell, c.cell_box);
-    if (n > 0) {
-        hipLaunchKernelGGL(k_bin_count, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox,
-                           n, pos, h, c.cellid, c.slot, c.cursor, dflags);
-    }
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, ncell, c.cursor, c.cell_start, dflags);
+    hipLaunchKernelGGL(k_bin_local, dim3((unsigned)plan.nblocks), dim3(kBinThreads), 0, st, c.box,
+                       c.bin_blocks, pos, h, c.cellid, c.slot, c.binm, dflags);
+    hipLaunchKernelGGL(k_bin_columns, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box,
+                       c.cell_box, ncell, c.binm, c.cell_start);
+    launch_scan(st, ncell, c.cell_start, c.cell_start, c.scan_tmp, dflags);
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox, n,
-                           pos, h, mass, c.cellid, c.slot, c.cell_start, c.stage);
+                           plan.chunk, pos, h, mass, c.cellid, c.slot, c.binm, c.cell_start,
+                           c.stage);
     }
-    hipLaunchKernelGGL(k_cell_finish, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax);
+    // size classes: at most 64 particles (and empty cells), 65..256, more
+    hipLaunchKernelGGL((k_cell_finish_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
+                       c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax, 0);
+    hipLaunchKernelGGL((k_cell_finish_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0,
+                       st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
+                       c.cell_hmax, 65);
+    hipLaunchKernelGGL(k_cell_finish_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                       c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax, 257);
     return hipGetLastError();
+}
+
+// Chunking of the count matrix: chunks of `chunk` particles (at least one per
+// box), grown until the matrix has at most kBinMaxMatrix entries or the
+// chunks reach 2^22 particles.
+BinPlan plan_binning(std::vector<BoxDesc> &boxes, std::vector<int4> &blocks)
+{
+    constexpr int64_t kBinMaxMatrix = 32 << 20;
+    BinPlan plan;
+    auto nblk_of = [](const BoxDesc &B, int ch) { return B.n > 0 ? (B.n + ch - 1) / ch : 1; };
+    auto mtot_of = [&](int ch) {
+        int64_t t = 0;
+        for (const BoxDesc &B : boxes) t += (int64_t)B.g[0] * B.g[1] * B.g[2] * nblk_of(B, ch);
+        return t;
+    };
+    int chunk = 16384;
+    while (mtot_of(chunk) > kBinMaxMatrix && chunk < (1 << 22)) chunk *= 2;
+    blocks.clear();
+    int64_t moff = 0;
+    for (int b = 0; b < (int)boxes.size(); ++b) {
+        BoxDesc &B = boxes[b];
+        B.nblk = nblk_of(B, chunk);
+        B.moff = (int)moff;
+        for (int j = 0; j < B.nblk; ++j) {
+            const int lo = B.part_off + std::min(B.n, j * chunk);
+            const int hi = B.part_off + std::min(B.n, (j + 1) * chunk);
+            blocks.push_back(make_int4(b, j, lo, hi));
+        }
+        moff += (int64_t)B.g[0] * B.g[1] * B.g[2] * B.nblk;
+    }
+    plan.chunk = chunk;
+    plan.mtot = moff;
+    plan.nblocks = (int64_t)blocks.size();
+    return plan;
 }
 
 }  // namespace pvl

@@ -32,8 +32,11 @@ struct pv_cells {
     int64_t ncell = 0;
     std::vector<BoxDesc> hbox;
     std::vector<BoxDesc> uploaded;  // what d.box currently holds
+    std::vector<int4> hblocks;      // binning chunks
+    std::vector<int4> uploaded_blocks;
+    pvl::BinPlan plan;
     DevCells d;
-    int64_t cap_n = 0, cap_cell = 0, cap_box = 0;
+    int64_t cap_n = 0, cap_cell = 0, cap_box = 0, cap_m = 0, cap_blocks = 0;
     bool sorted = false;
 };
 
@@ -62,22 +65,27 @@ hipError_t dev_alloc(T **p, int64_t count)
 
 void free_dev(DevCells &d)
 {
-    void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cursor, d.cellid, d.slot, d.stage,
+    void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cellid, d.slot, d.stage,
                     d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
-                    d.items, d.qcount};
+                    d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DevCells();
 }
 
-pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, int nbox)
+pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, int nbox,
+                          int64_t mtot, int64_t nblocks)
 {
-    if (n <= c->cap_n && ncell <= c->cap_cell && nbox <= c->cap_box) return PV_OK;
+    if (n <= c->cap_n && ncell <= c->cap_cell && nbox <= c->cap_box && mtot <= c->cap_m &&
+        nblocks <= c->cap_blocks)
+        return PV_OK;
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     free_dev(c->d);
     c->uploaded.clear();
+    c->uploaded_blocks.clear();
     int64_t N = std::max<int64_t>(n, c->cap_n), C = std::max<int64_t>(ncell, c->cap_cell);
     int64_t Bx = std::max<int64_t>(nbox, c->cap_box);
+    int64_t M = std::max<int64_t>(mtot, c->cap_m), NB = std::max<int64_t>(nblocks, c->cap_blocks);
     DevCells &d = c->d;
     hipError_t e = hipSuccess;
 #define ALLOC(ptr, cnt) if (e == hipSuccess) e = dev_alloc(&ptr, cnt)
@@ -86,7 +94,6 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.cell_box, C);
     ALLOC(d.cell_start, C + 1);
     ALLOC(d.cell_hmax, C);
-    ALLOC(d.cursor, C);
     ALLOC(d.cellid, N);
     ALLOC(d.slot, N);
     ALLOC(d.stage, 2 * N);
@@ -98,15 +105,20 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.gcell, N);
     ALLOC(d.items, pvl::queue_capacity(N, C));
     ALLOC(d.qcount, 4);
+    ALLOC(d.scan_tmp, pvl::scan_scratch_words(C));
+    ALLOC(d.binm, M);
+    ALLOC(d.bin_blocks, NB);
 #undef ALLOC
     if (e != hipSuccess) {
         free_dev(c->d);
-        c->cap_n = c->cap_cell = c->cap_box = 0;
+        c->cap_n = c->cap_cell = c->cap_box = c->cap_m = c->cap_blocks = 0;
         return fail(ctx, PV_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
     }
     c->cap_n = N;
     c->cap_cell = C;
     c->cap_box = Bx;
+    c->cap_m = M;
+    c->cap_blocks = NB;
     return PV_OK;
 }
 
@@ -117,11 +129,19 @@ bool boxes_equal(const std::vector<BoxDesc> &a, const std::vector<BoxDesc> &b)
 
 pv_status upload_boxes(pv_ctx *ctx, pv_cells *c)
 {
-    if (boxes_equal(c->hbox, c->uploaded)) return PV_OK;
+    const bool same_blocks =
+        c->hblocks.size() == c->uploaded_blocks.size() &&
+        (c->hblocks.empty() ||
+         memcmp(c->hblocks.data(), c->uploaded_blocks.data(), sizeof(int4) * c->hblocks.size()) == 0);
+    if (boxes_equal(c->hbox, c->uploaded) && same_blocks) return PV_OK;
     HIPCHK(ctx, hipMemcpyAsync(c->d.box, c->hbox.data(), sizeof(BoxDesc) * c->hbox.size(),
                                hipMemcpyHostToDevice, ctx->stream));
+    if (!c->hblocks.empty())
+        HIPCHK(ctx, hipMemcpyAsync(c->d.bin_blocks, c->hblocks.data(), sizeof(int4) * c->hblocks.size(),
+                                   hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     c->uploaded = c->hbox;
+    c->uploaded_blocks = c->hblocks;
     return PV_OK;
 }
 
@@ -247,7 +267,8 @@ pv_status pv_build_cells_batched(pv_ctx *ctx, int nbox, const int64_t *offsets,
     };
     pv_status st;
     if (autogrid) {
-        st = ensure_capacity(ctx, c, n, std::max<int64_t>(c->cap_cell, 27 * nbox), nbox);
+        c->hblocks.clear();
+        st = ensure_capacity(ctx, c, n, std::max<int64_t>(c->cap_cell, 27 * nbox), nbox, 0, 0);
         if (st != PV_OK) { if (fresh) { pv_free_cells(ctx, c); } return st; }
         c->n = n;
         if ((st = upload_boxes(ctx, c)) != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
@@ -298,16 +319,17 @@ pv_status pv_build_cells_batched(pv_ctx *ctx, int nbox, const int64_t *offsets,
         B.cell_off = coff;
         coff += B.g[0] * B.g[1] * B.g[2];
     }
-    st = ensure_capacity(ctx, c, n, ncell, nbox);
+    c->plan = pvl::plan_binning(c->hbox, c->hblocks);
+    st = ensure_capacity(ctx, c, n, ncell, nbox, c->plan.mtot, c->plan.nblocks);
     if (st != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
     c->nbox = nbox;
     c->n = n;
     c->ncell = ncell;
     c->sorted = false;
     if ((st = upload_boxes(ctx, c)) != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
-    hipError_t e = pvl::launch_zero(ctx->stream, c->d.cursor, ncell);
-    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, ctx->dflags + 1, 1);
-    if (e == hipSuccess) e = pvl::launch_bin(ctx->stream, c->d, nbox, n, ncell, pos, h, mass, ctx->dflags);
+    hipError_t e = pvl::launch_zero(ctx->stream, ctx->dflags + 1, 1);
+    if (e == hipSuccess)
+        e = pvl::launch_bin(ctx->stream, c->d, c->plan, nbox, n, ncell, pos, h, mass, ctx->dflags);
     if (e != hipSuccess) {
         if (fresh) pv_free_cells(ctx, c);
         return fail(ctx, PV_EHIP, std::string("binning launch: ") + hipGetErrorString(e));

@@ -29,7 +29,9 @@ struct BoxDesc {
     int cell_off;       // first global cell of this box
     int part_off;       // first particle of this box (input and cell order)
     int n;              // particles in the box
-    int pad;
+    int nblk;           // binning chunks of the box (rows of its count matrix)
+    int moff;           // first entry of the box's count matrix
+    int pad[3];
 };
 
 // The 13 canonical cell offsets: those d in {-1,0,1}^3 \ 0 whose first
@@ -74,7 +76,6 @@ struct DevCells {
     int32_t *cell_box = nullptr;  // ncell: owning box
     int32_t *cell_start = nullptr;// ncell + 1: first slot (global, cell order)
     uint32_t *cell_hmax = nullptr;// ncell: max cut-off in the cell (fp32 bits)
-    int32_t *cursor = nullptr;    // ncell: scatter cursors / counts
     int32_t *cellid = nullptr;    // n: global cell of each input particle
     int32_t *slot = nullptr;      // n: arrival rank of the particle within its cell
     float4 *stage = nullptr;      // 2n: per particle (x, y, z, H) wrapped, (m, index bits, -, -)
@@ -87,15 +88,31 @@ struct DevCells {
     int2 *items = nullptr;        // work queue of (cell, receiver chunk)
     int *qcount = nullptr;        // [0] large-cell chunks, [1] single-chunk cells, [2] head
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
+    int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
+    int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
+    int4 *bin_blocks = nullptr;   // binning chunks: (box, chunk in box, first, end particle)
+};
+
+// Chunking of the binning count sort (see plan_binning).
+struct BinPlan {
+    int chunk = 16384;     // particles per chunk
+    int64_t mtot = 0;      // entries of the count matrices
+    int64_t nblocks = 0;   // chunks (workgroups of the counting kernel)
 };
 
 // Launch wrappers (each lives next to its kernels).
 hipError_t launch_box_hmax(hipStream_t st, const DevCells &c, int nbox, int64_t n,
                            const float *h);
-hipError_t launch_bin(hipStream_t st, const DevCells &c, int nbox, int64_t n, int64_t ncell,
-                      const float *pos, const float *h, const float *mass, int *dflags);
+// Fill BoxDesc::nblk / moff of every box (whose g, n and part_off are set)
+// and the chunk table.
+BinPlan plan_binning(std::vector<BoxDesc> &boxes, std::vector<int4> &blocks);
+hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, int nbox, int64_t n,
+                      int64_t ncell, const float *pos, const float *h, const float *mass,
+                      int *dflags);
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell);
 hipError_t launch_zero(hipStream_t st, void *p, int64_t words);
+// Words of scratch the cell-count scan needs for ncell cells.
+int scan_scratch_words(int64_t ncell);
 // Sweep tuning (see pv_param).
 struct SweepTuning {
     int reach_order = 0;

@@ -2,18 +2,18 @@
 // are projected on the axis joining the cell centres and sorted along it; 13
 // axes cover all 26 neighbour directions once the +- symmetry is used).
 //
-// One workgroup per cell.  For each axis s the key of particle r is its
-// cell-relative position projected on d_s / |d_s|.  The keys are bucket
-// sorted in LDS: the cell's key range along the axis is cut into equal
-// buckets (the bucket index is a monotone function of the key), a histogram
-// and its prefix sum place every bucket, and each particle's final rank is its
-// bucket's start plus the number of bucket mates with a smaller (key, in-cell
-// rank) pair.  Equal keys keep in-cell order, so the result is deterministic,
-// and the work is linear in the occupancy unless a bucket is crowded.
-//
-// Each thread reads the positions of its particles once and computes their
-// keys for every axis of the pass; ranks are resolved in LDS and the sorted
-// lists are written out in order, so the global stores are coalesced.
+// One workgroup per cell, sized to the cell: cells of at most 64, 256 or 512
+// particles take a workgroup of that many threads, one particle per thread;
+// larger cells a 256-thread workgroup that loops over its particles and
+// handles as many axes per pass as fit the LDS.  For each axis s the key
+// of particle r is its cell-relative position projected on d_s / |d_s|.  The
+// keys are bucket sorted in LDS: the cell's key range along the axis is cut
+// into equal buckets (the bucket index is a monotone function of the key), a
+// histogram and its prefix sum place every bucket, and each particle's final
+// rank is its bucket's start plus the number of bucket mates with a smaller
+// (key, in-cell rank) pair.  Equal keys keep in-cell order, so the result is
+// deterministic, and the work is linear in the occupancy unless a bucket is
+// crowded.
 // Output per axis: the in-cell ranks (uint16) in key order and the keys (fp32).
 #include "device_util.h"
 
@@ -36,19 +36,127 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
     return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
 }
 
-__global__ void __launch_bounds__(kBlock) k_sort13(const BoxDesc *__restrict__ box,
+// Cells of at most MAXC particles, one particle per thread (blockDim = MAXC),
+// all 13 axes at once with the axis loops unrolled so that their LDS traffic
+// overlaps.  NB buckets per axis.  Only the positions, the histograms and the
+// bucket-order lists live in LDS (about 16 KB for MAXC = 256), so several
+// cells share a compute unit; keys are recomputed from the positions where a
+// bucket mate's key is needed, bit-identically (same fused operations).  Each
+// particle writes its own entry of the sorted lists at its rank.
+template <int MAXC, int NB>
+__global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict__ box,
+                                                      const int32_t *__restrict__ cell_box,
+                                                      const int32_t *__restrict__ start,
+                                                      const float4 *__restrict__ xyzm, int64_t n,
+                                                      uint16_t *__restrict__ sidx,
+                                                      float *__restrict__ skey, int min_cnt)
+{
+    __shared__ float4 pos[MAXC];
+    __shared__ uint32_t hist[13][NB];
+    __shared__ uint16_t border[13][MAXC];
+    __shared__ float ax_kmin[13], ax_scale[13];
+    const int c = blockIdx.x;
+    const int s0 = start[c];
+    const int cnt = start[c + 1] - s0;
+    if (cnt < min_cnt || cnt > MAXC) return;
+    const BoxDesc &B = box[cell_box[c]];
+    if (threadIdx.x < 13) {
+        float e[3];
+        dir_axis(threadIdx.x, e);
+        const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
+                           fminf(e[2], 0.f) * B.edge[2];
+        const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
+                           fmaxf(e[2], 0.f) * B.edge[2];
+        ax_kmin[threadIdx.x] = kmin;
+        ax_scale[threadIdx.x] = (float)NB / (kmax - kmin);
+    }
+    for (int t = threadIdx.x; t < 13 * NB; t += blockDim.x) (&hist[0][0])[t] = 0u;
+    const int r = threadIdx.x;
+    const bool on = r < cnt;
+    const float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    pos[r] = p;
+    __syncthreads();
+    float k[13];
+    int b[13];
+    uint32_t sl[13];
+#pragma unroll
+    for (int g = 0; g < 13; ++g) {
+        k[g] = proj_key(p.x, p.y, p.z, g);
+        b[g] = key_bucket(k[g], ax_kmin[g], ax_scale[g], NB);
+    }
+    if (on) {
+#pragma unroll
+        for (int g = 0; g < 13; ++g) sl[g] = atomicAdd(&hist[g][b[g]], 1u);
+    }
+    __syncthreads();
+    {
+        // exclusive scans of the 13 histograms, one wave per axis at a time,
+        // NB / 64 buckets per lane (NB <= 64: one bucket on the first lanes)
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        constexpr int per = NB >= 64 ? NB / 64 : 1;
+        for (int g = wave; g < 13; g += (int)(blockDim.x >> 6)) {
+            uint32_t v[per];
+            uint32_t loc = 0;
+#pragma unroll
+            for (int q = 0; q < per; ++q) {
+                v[q] = lane * per + q < NB ? hist[g][lane * per + q] : 0u;
+                loc += v[q];
+            }
+            uint32_t inc = loc;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+                if (lane >= off) inc += o;
+            }
+            uint32_t run = inc - loc;
+#pragma unroll
+            for (int q = 0; q < per; ++q) {
+                if (lane * per + q < NB) hist[g][lane * per + q] = run;
+                run += v[q];
+            }
+        }
+    }
+    __syncthreads();
+    int q0[13];
+    if (on) {
+#pragma unroll
+        for (int g = 0; g < 13; ++g) {
+            q0[g] = (int)hist[g][b[g]];
+            border[g][q0[g] + (int)sl[g]] = (uint16_t)r;
+        }
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+        for (int g = 0; g < 13; ++g) {
+            const int q1 = b[g] + 1 < NB ? (int)hist[g][b[g] + 1] : cnt;
+            int rank = q0[g];
+            for (int q = q0[g]; q < q1; ++q) {
+                const int r2 = border[g][q];
+                const float4 p2 = pos[r2];
+                const float k2 = proj_key(p2.x, p2.y, p2.z, g);
+                rank += (k2 < k[g]) || (k2 == k[g] && r2 < r);
+            }
+            const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
+            sidx[o] = (uint16_t)r;
+            skey[o] = k[g];
+        }
+    }
+}
+
+// Cells above the small sizes: G axes per pass, as many as fit the LDS.
+__global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restrict__ box,
                                                     const int32_t *__restrict__ cell_box,
                                                     const int32_t *__restrict__ start,
                                                     const float4 *__restrict__ xyzm, int64_t n,
                                                     uint16_t *__restrict__ sidx,
-                                                    float *__restrict__ skey)
+                                                    float *__restrict__ skey, int min_cnt)
 {
     __shared__ __align__(16) unsigned char lds[kSortLdsBytes];
     __shared__ float ax_kmin[13], ax_scale[13];
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
-    if (cnt <= 0 || cnt > PV_MAX_CELL) return;
+    if (cnt < min_cnt || cnt > PV_MAX_CELL) return;
     const BoxDesc &B = box[cell_box[c]];
     const int NB = sort_buckets(cnt);   // 128 whenever cnt <= kBlock
     // per axis: histogram (NB u32), keys (cnt f32), the arrival-slot list (later
@@ -70,87 +178,6 @@ __global__ void __launch_bounds__(kBlock) k_sort13(const BoxDesc *__restrict__ b
         ax_scale[threadIdx.x] = (float)NB / (kmax - kmin);
     }
     __syncthreads();
-
-    if (cnt <= kBlock) {
-        // one particle per thread, all 13 axes at once with the axis loops
-        // unrolled so that their LDS traffic overlaps
-        uint32_t *hist = reinterpret_cast<uint32_t *>(lds);                    // [13][128]
-        float *key = reinterpret_cast<float *>(lds + 13 * 128 * 4);           // [13][256]
-        uint16_t *border = reinterpret_cast<uint16_t *>(key + 13 * kBlock);   // [13][256]
-        uint16_t *forder = border + 13 * kBlock;                              // [13][256]
-        const int r = threadIdx.x;
-        const bool on = r < cnt;
-        for (int t = threadIdx.x; t < 13 * 128; t += blockDim.x) hist[t] = 0u;
-        __syncthreads();
-        float k[13];
-        int b[13];
-        uint32_t sl[13];
-        float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-        for (int g = 0; g < 13; ++g) {
-            k[g] = proj_key(p.x, p.y, p.z, g);
-            b[g] = key_bucket(k[g], ax_kmin[g], ax_scale[g], 128);
-        }
-        if (on) {
-#pragma unroll
-            for (int g = 0; g < 13; ++g) {
-                key[g * kBlock + r] = k[g];
-                sl[g] = atomicAdd(&hist[g * 128 + b[g]], 1u);
-            }
-        }
-        __syncthreads();
-        {
-            // exclusive scans: 13 axes of 128 buckets, two buckets per lane
-            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-            for (int g = wave; g < 13; g += (int)(blockDim.x >> 6)) {
-                uint32_t *hh = hist + g * 128;
-                const uint32_t v0 = hh[2 * lane], v1 = hh[2 * lane + 1];
-                const uint32_t loc = v0 + v1;
-                uint32_t inc = loc;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
-                    if (lane >= off) inc += o;
-                }
-                const uint32_t ex = inc - loc;
-                hh[2 * lane] = ex;
-                hh[2 * lane + 1] = ex + v0;
-            }
-        }
-        __syncthreads();
-        int q0[13];
-        if (on) {
-#pragma unroll
-            for (int g = 0; g < 13; ++g) {
-                q0[g] = (int)hist[g * 128 + b[g]];
-                border[g * kBlock + q0[g] + (int)sl[g]] = (uint16_t)r;
-            }
-        }
-        __syncthreads();
-        if (on) {
-#pragma unroll
-            for (int g = 0; g < 13; ++g) {
-                const int q1 = b[g] + 1 < 128 ? (int)hist[g * 128 + b[g] + 1] : cnt;
-                int rank = q0[g];
-                for (int q = q0[g]; q < q1; ++q) {
-                    const int r2 = border[g * kBlock + q];
-                    const float k2 = key[g * kBlock + r2];
-                    rank += (k2 < k[g]) || (k2 == k[g] && r2 < r);
-                }
-                forder[g * kBlock + rank] = (uint16_t)r;
-            }
-        }
-        __syncthreads();
-        if (on) {
-#pragma unroll
-            for (int g = 0; g < 13; ++g) {
-                const int rr = forder[g * kBlock + r];
-                const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + r);
-                sidx[o] = (uint16_t)rr;
-                skey[o] = key[g * kBlock + rr];
-            }
-        }
-        return;
-    }
 
     for (int sf = 0; sf < 13; sf += G) {
         const int ng = 13 - sf < G ? 13 - sf : G;
@@ -244,11 +271,21 @@ __global__ void __launch_bounds__(kBlock) k_sort13(const BoxDesc *__restrict__ b
     }
 }
 
+// One launch per size class over all cells, each taking the cells of its
+// class (at most 64 particles, 65..256, 257..512, more) and skipping the
+// others.  (Larger one-particle-per-thread classes measured slower than the
+// looping kernel: their LDS leaves two workgroups per compute unit.)
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sort13, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box, c.cell_box,
-                       c.cell_start, c.xyzm, n, c.sidx, c.skey);
+    hipLaunchKernelGGL((k_sort13_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st, c.box,
+                       c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 1);
+    hipLaunchKernelGGL((k_sort13_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0, st,
+                       c.box, c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 65);
+    hipLaunchKernelGGL((k_sort13_small<512, 256>), dim3((unsigned)ncell), dim3(512), 0, st,
+                       c.box, c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 257);
+    hipLaunchKernelGGL(k_sort13_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+                       c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 513);
     return hipGetLastError();
 }
 
