@@ -6,7 +6,9 @@ A step is one pass of the whole hot path over the resident particle set:
 build_cells (binning into cells, explicit grid) + sort_cells (13 per-axis
 sorts) + density (sorted-pair sweep with in-place finalisation).  The plain
 cell-list comparator (build_cells + density with the 27-cell brute force) is
-timed the same way.  Inputs are seeded synthetic particle sets already in HBM.
+timed the same way.  Both steps are timed as issued call by call and as a
+captured HIP graph (the reported figure); the sweep parameters are autotuned
+first.  Inputs are seeded synthetic particle sets already in HBM.
 
 Prints one JSON line: pair-interactions/s of the sorted-pair path (value), the
 plain comparator, ns/particle, the sweep kernel's roofline and the fp64 CPU
@@ -65,6 +67,22 @@ def _autotune(a, ctx, cells, g_rho, targets):
         before, after, p = ctx.autotune(cells, t, g_rho if t == "adjoint" else None, reps=3)
         out[t] = {"default_ms": before, "tuned_ms": after, "params": p}
     return out
+
+
+def _capture(fn, torch):
+    """Record fn (library calls only) into a HIP graph; one eager run on the
+    capture stream first, as graph capture requires."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        fn()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn()
+    torch.cuda.synchronize()
+    return graph
 
 
 def _time_loop(fn, steps, warmup, torch):
@@ -146,10 +164,18 @@ def main():
         ctx.density(cells, "plain", out_p)
 
     print("[bench] timing sorted-pair path", file=sys.stderr, flush=True)
-    ms_sorted, wall_sorted = _time_loop(step_sorted, a.steps, a.warmup, torch)
+    ms_sorted_eager, _ = _time_loop(step_sorted, a.steps, a.warmup, torch)
     print("[bench] timing plain cell-list path", file=sys.stderr, flush=True)
-    ms_plain, _ = _time_loop(step_plain, a.steps, a.warmup, torch)
+    ms_plain_eager, _ = _time_loop(step_plain, a.steps, a.warmup, torch)
     ctx.check()
+    # the same steps as captured HIP graphs (one launch per step)
+    print("[bench] timing both paths as HIP graphs", file=sys.stderr, flush=True)
+    g_sorted = _capture(step_sorted, torch)
+    ms_sorted, wall_sorted = _time_loop(g_sorted.replay, a.steps, a.warmup, torch)
+    g_plain = _capture(step_plain, torch)
+    ms_plain, _ = _time_loop(g_plain.replay, a.steps, a.warmup, torch)
+    ctx.check()
+    del g_sorted, g_plain
 
     # stage times (events on the stream the library launches on)
     ctx.build_cells(pos, h, m, s.box, grid, cells)
@@ -191,9 +217,10 @@ def main():
                    if "lognormal" in s.name else "see workload"},
         "ns_per_particle": ms_sorted * 1e6 / n,
         "pairs_in_range": pairs,
+        "eager_ms_per_step": ms_sorted_eager,
         "plain_cell_list": {"ms_per_step": ms_plain, "value": pairs / (ms_plain * 1e-3),
                             "ns_per_particle": ms_plain * 1e6 / n,
-                            "sweep_ms": ms_sweep_plain},
+                            "eager_ms_per_step": ms_plain_eager, "sweep_ms": ms_sweep_plain},
         "speedup_sorted_vs_plain": ms_plain / ms_sorted,
         "stages_ms": {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep,
                       "adjoint_sweep": ms_adj},
