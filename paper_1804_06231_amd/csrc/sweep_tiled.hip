@@ -62,6 +62,7 @@ constexpr int kChunkMin = 32;                  // smallest (sizes the queue)
 constexpr int kMaxTasks = 27 * (kChunk / 16);  // task slots per item
 constexpr int kMaxRecv = 26 * kChunk;          // compacted receiver lists per item
 constexpr int kSelfAxis = 4;                   // d = (1, 0, 0): cell order is x order
+constexpr int kReachBuckets = 16;              // reach levels of the receiver ordering
 
 // Value of lane (l + K) mod 16 of the same 16-lane row (DPP row_ror:K).
 template <int K>
@@ -278,46 +279,72 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
                 L.recv_off[d] = roff;
                 roff += L.act_cell[d];
             }
-            // the ordering keys and indices (6 bytes per receiver) borrow the
-            // accumulator space
-            L.flag = (!ADJ && A.reach_order && roff * 6 <= (int)sizeof(L.acc)) ? 1 : 0;
         }
         __syncthreads();
-        listed = L.flag != 0;
+        listed = !ADJ && A.reach_order;
         if (listed) {
-            // order each direction's receivers by how far past the shared face
-            // their cut-off reaches (key + H toward a neighbour ahead on the
-            // axis, key - H toward one behind); the set-up arrays borrow the
-            // accumulator space
-            const int nrecv = L.recv_off[25] + L.act_cell[25];
-            float *rv = reinterpret_cast<float *>(&L.acc[0][0]);
-            uint16_t *ria = reinterpret_cast<uint16_t *>(rv + nrecv);
-            for (int q = tid; q < nrecv; q += blockDim.x) {
-                int dir = 0;
-                while (dir < 25 && L.recv_off[dir + 1] <= q) ++dir;
-                int r = q - L.recv_off[dir];
+            // Receivers of a face direction are ordered by how far past the
+            // shared face their cut-off reaches (key + H toward a neighbour ahead
+            // on the axis, H - key toward one behind), quantised to
+            // kReachBuckets levels and interface-first within a level, so that
+            // the receivers of a block of 16 have similar loop bounds.  A
+            // stable counting sort made of wavefront ballots (one wavefront per
+            // direction, no atomics: the order is deterministic).  Edge and
+            // corner directions keep the interface-first key order.
+            for (int d = wave; d < 26; d += (int)(blockDim.x >> 6)) {
+                const int act = L.act_cell[d];
                 int dx, dy, dz, sign;
-                nb_offset(dir, dx, dy, dz);
-                int s = dir_canon(dx, dy, dz, &sign);
-                int qs = sign > 0 ? na - 1 - r : r;
-                int ia = sidx[(size_t)s * n + sa + qs];
-                float k = skey[(size_t)s * n + sa + qs];
-                float H = A.Hc[sa + ia];
-                rv[q] = sign > 0 ? -(k + H) : (k - H);
-                ria[q] = (uint16_t)ia;
-            }
-            __syncthreads();
-            for (int q = tid; q < nrecv; q += blockDim.x) {
-                int dir = 0;
-                while (dir < 25 && L.recv_off[dir + 1] <= q) ++dir;
-                int o = L.recv_off[dir], r = q - o, m = L.act_cell[dir];
-                float v = rv[q];
-                int rank = 0;
-                for (int k = 0; k < m; ++k) {
-                    float w = rv[o + k];
-                    rank += (w < v) || (w == v && k < r);
+                nb_offset(d, dx, dy, dz);
+                const int s = dir_canon(dx, dy, dz, &sign);
+                const float *ka = skey + (size_t)s * n + sa;
+                const uint16_t *il = sidx + (size_t)s * n + sa;
+                uint16_t *out = L.rlist + L.recv_off[d];
+                const bool face = (dx != 0) + (dy != 0) + (dz != 0) == 1;
+                if (!face) {
+                    for (int q = lane; q < act; q += 64) out[q] = il[sign > 0 ? na - 1 - q : q];
+                    continue;
                 }
-                L.rlist[o + rank] = ria[q];
+                const float lo = sign > 0 ? ka[0] : -ka[na - 1];
+                const float hi = (sign > 0 ? ka[na - 1] : -ka[0]) + hmax_a;
+                const float scale = (float)kReachBuckets / fmaxf(hi - lo, 1e-30f);
+                constexpr int R = kChunk / 64;
+                int bk[R], pos[R];
+                uint16_t iav[R];
+                const int nc = (act + 63) >> 6;
+#pragma unroll
+                for (int c = 0; c < R; ++c) {
+                    const int q = c * 64 + lane;
+                    bk[c] = kReachBuckets;   // no entry
+                    iav[c] = 0;
+                    pos[c] = 0;
+                    if (c < nc && q < act) {
+                        const int qs = sign > 0 ? na - 1 - q : q;
+                        const int ia = il[qs];
+                        const float k = ka[qs];
+                        const float H = A.Hc[sa + ia];
+                        const float T = sign > 0 ? k + H : H - k;
+                        const int b = (int)((hi - T) * scale);
+                        bk[c] = b < 0 ? 0 : (b >= kReachBuckets ? kReachBuckets - 1 : b);
+                        iav[c] = (uint16_t)ia;
+                    }
+                }
+                int run = 0;   // entries placed so far (wavefront-uniform)
+                for (int b = 0; b < kReachBuckets; ++b) {
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        if (c >= nc) break;
+                        const bool mine = bk[c] == b;
+                        const uint64_t m = __ballot(mine);
+                        if (mine)
+                            pos[c] = run + (int)__builtin_amdgcn_mbcnt_hi(
+                                               (uint32_t)(m >> 32),
+                                               __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        run += __popcll(m);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < R; ++c)
+                    if (c < nc && bk[c] < kReachBuckets) out[pos[c]] = iav[c];
             }
         }
     } else {
