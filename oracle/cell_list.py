@@ -51,6 +51,8 @@ def _load():
     lib.or_fd_loss.argtypes = [P, P, i64, C.c_int, C.c_double]
     lib.or_fd_loss.restype = C.c_double
     lib.or_fd_loss_many.argtypes = [P, P, P, P, P, i64, P]
+    lib.or_solve_h.argtypes = [P, C.c_double, P, P]
+    lib.or_solve_h.restype = i64
     _lib = lib
     return lib
 
@@ -137,6 +139,27 @@ class Oracle:
         self.lib.or_fd_loss_many(self.handle, _ptr(t), _ptr(ks), _ptr(comps), _ptr(eps),
                                  ks.size, _ptr(out))
         return out
+
+
+def solve_h_fp64(pos, m, h_lo, h_hi, eta, box=(1.0, 1.0, 1.0)):
+    """Per-particle root of rho_i(h) h^3 = m_i eta^3 by fp64 bisection on
+    [h_lo_i, h_hi_i] (pv_oracle.c: or_solve_h).  Raises if a bracket holds no
+    root."""
+    n = np.asarray(pos).reshape(-1, 3).shape[0]
+    hi = np.broadcast_to(np.asarray(h_hi, dtype=np.float64), (n,))
+    o = Oracle(pos, hi, m, box)
+    lo = np.ascontiguousarray(np.broadcast_to(np.asarray(h_lo, dtype=np.float64), (n,)))
+    out = np.zeros(o.n)
+    bad = o.lib.or_solve_h(o.handle, float(eta), _ptr(lo), _ptr(out))
+    if bad:
+        raise ValueError(f"oracle: {bad} brackets hold no root")
+    return out
+
+
+def eta_for_neighbours(ngb: float) -> float:
+    """eta with rho h^3 = m eta^3 equivalent to (4 pi / 3) H^3 wcount = ngb for
+    equal masses: eta^3 = 3 ngb / (4 pi gamma^3)."""
+    return (3.0 * ngb / (4.0 * math.pi * ORACLE_GAMMA ** 3)) ** (1.0 / 3.0)
 
 
 def density_fp64(pos, h, m, box=(1.0, 1.0, 1.0), grid=None, recv=None):

@@ -329,3 +329,77 @@ void or_fd_loss_many(const or_grid *G, const double *target, const int64_t *ks,
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t q = 0; q < m; ++q) out[q] = or_fd_loss(G, target, ks[q], comps[q], eps[q]);
 }
+
+/*
+ * Smoothing lengths from the density-smoothing-length relation
+ *
+ *   rho_i(h_i) h_i^3 = m_i eta^3,
+ *
+ * where rho_i(h) is the density of receiver i with its own cut-off gamma h and
+ * everything else fixed (rho_i depends on no other particle's h, so the
+ * particles' equations are independent).  With equal masses this is the
+ * neighbour-number condition (4 pi / 3) H_i^3 wcount_i = N_ngb with
+ * eta^3 = 3 N_ngb / (4 pi gamma^3).  g(h) = rho_i(h) h^3 - m_i eta^3 grows with
+ * h (every kernel term w(r / gamma h) grows with h, and new terms enter at
+ * w = 0), so the root is found by plain bisection in fp64 on [h_lo_i, h_hi_i].
+ * The grid G must be built with h = h_hi (its stencil then holds every
+ * candidate).  Returns the number of particles whose bracket holds no sign
+ * change (their h_out is left at -1).
+ */
+static double rho_at(const double *rj, const double *mj, int64_t k, double h)
+{
+    double H = OR_GAMMA * h, s = 0.0;
+    for (int64_t q = 0; q < k; ++q)
+        if (rj[q] < H) {
+            double w, dw;
+            or_kernel(rj[q] / H, &w, &dw);
+            s += mj[q] * w;
+        }
+    return 8.0 / (OR_PI * H * H * H) * s;
+}
+
+int64_t or_solve_h(const or_grid *G, double eta, const double *h_lo, double *h_out)
+{
+    int64_t bad = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : bad)
+    for (int64_t i = 0; i < G->n; ++i) {
+        /* the distances and masses of every candidate within the bracket */
+        const double Hhi = OR_GAMMA * G->h[i];
+        int64_t cap = 64, k = 0;
+        double *rj = (double *)malloc(sizeof(double) * cap);
+        double *mj = (double *)malloc(sizeof(double) * cap);
+        FOR_STENCIL(G, i, {
+            double d[3];
+            min_image(G, i, j, d);
+            double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (r < Hhi) {
+                if (k == cap) {
+                    cap *= 2;
+                    rj = (double *)realloc(rj, sizeof(double) * cap);
+                    mj = (double *)realloc(mj, sizeof(double) * cap);
+                }
+                rj[k] = r;
+                mj[k] = G->m[j];
+                ++k;
+            }
+        });
+        const double target = G->m[i] * eta * eta * eta;
+        double lo = h_lo[i], hi = G->h[i];
+        double glo = rho_at(rj, mj, k, lo) * lo * lo * lo - target;
+        double ghi = rho_at(rj, mj, k, hi) * hi * hi * hi - target;
+        if (!(glo < 0.0 && ghi > 0.0)) {
+            h_out[i] = -1.0;
+            ++bad;
+        } else {
+            for (int it = 0; it < 200 && hi - lo > 1e-14 * hi; ++it) {
+                double mid = 0.5 * (lo + hi);
+                double g = rho_at(rj, mj, k, mid) * mid * mid * mid - target;
+                if (g < 0.0) lo = mid; else hi = mid;
+            }
+            h_out[i] = 0.5 * (lo + hi);
+        }
+        free(rj);
+        free(mj);
+    }
+    return bad;
+}

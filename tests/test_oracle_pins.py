@@ -268,3 +268,49 @@ def test_census_projection_never_exceeds_distance():
         assert np.all(proj[r < Ha[:, None]] < Ha[np.nonzero(r < Ha[:, None])[0]])
         c, i, a = pair_census(xa, Ha, xb, e)
         assert i <= c <= a
+
+
+# ------------------------------------------------------- smoothing-length solve
+def test_solve_h_lattice_shells():
+    """On a simple cubic lattice every particle has the same density, a shell
+    sum over the textbook shell populations, so rho h^3 = m eta^3 reduces to one
+    equation in R = H / a: (8 / (pi gamma^3)) (R a / H)^3 ... written out below
+    and solved by scipy's brentq; the oracle's per-particle bisection must give
+    the same h for every particle."""
+    from scipy.optimize import brentq
+    from oracle import solve_h_fp64, eta_for_neighbours
+    shells = {int(k): int(v[0]) for k, v in _golden("lattice_shells.txt").items()}
+    M = 16
+    a = 1.0 / M
+    eta = eta_for_neighbours(48.0)
+    s = lattice_set(M, 2.0)
+
+    # rho(h) h^3 / m = (8 / (pi gamma^3)) (1 + sum_s count_s w(sqrt(s) a / (gamma h)))
+    def g(h):
+        H = ORACLE_GAMMA * h
+        tot = 1.0 + sum(c * kernel_w(math.sqrt(q) * a / H)[0] for q, c in shells.items()
+                        if math.sqrt(q) * a < H)
+        return 8.0 / (math.pi * ORACLE_GAMMA ** 3) * tot - eta ** 3
+    h_shell = brentq(g, 0.5 * eta * a, 1.6 * eta * a, xtol=1e-15)
+    h = solve_h_fp64(s.pos, s.m, 0.6 * eta * a, 1.5 * eta * a, eta)
+    assert np.max(np.abs(h - h_shell)) < 1e-12 * h_shell
+    # the shells inside the solved cut-off: 1, 2, 3, 4 and 5 (|k|^2 < R^2)
+    assert 5.0 < (ORACLE_GAMMA * h_shell / a) ** 2 < 6.0
+
+
+def test_solve_h_satisfies_relation_and_neighbour_number():
+    """At the solved h the density loop (a different code path from the
+    solver's) gives rho h^3 = m eta^3, and with equal masses the weighted
+    neighbour number (4 pi / 3) H^3 wcount equals the target."""
+    from oracle import solve_h_fp64, eta_for_neighbours
+    s = uniform_set(3000, 41, hmode="lognormal")
+    eta = eta_for_neighbours(48.0)
+    h0 = h_for_neighbours(3000)
+    h = solve_h_fp64(s.pos, s.m, 0.4 * h0, 1.9 * h0, eta)
+    o = Oracle(s.pos, h, s.m).density()
+    m = s.m.astype(np.float64)
+    assert np.max(np.abs(o["rho"] * h ** 3 / (m * eta ** 3) - 1.0)) < 1e-11
+    H = ORACLE_GAMMA * h
+    assert np.max(np.abs(4.0 * math.pi / 3.0 * H ** 3 * o["wcount"] - 48.0)) < 1e-9
+    with pytest.raises(ValueError):
+        solve_h_fp64(s.pos, s.m, 0.4 * h0, 0.5 * h0, eta)     # no root in the bracket
