@@ -187,6 +187,7 @@ def main():
     out_g = (torch.empty((s.n, 3), device=dev), torch.empty(s.n, device=dev))
     ms_adj, _ = _time_loop(lambda: ctx.density_backward(cells, g_rho, out_g), a.steps, 1, torch)
     ctx.check()
+    hsolve = _bench_hsolve(ctx, s, pos, m, torch)
 
     n = s.n
     value = pairs / (ms_sorted * 1e-3)
@@ -227,6 +228,7 @@ def main():
         "candidates_per_particle": {"sorted": cand_sorted / n, "plain": cand_plain / n,
                                     "in_range": inr / n},
         "autotune": tuning,
+        "h_iteration": hsolve,
         "wall_ms_per_step": wall_sorted,
         "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
@@ -361,6 +363,21 @@ def bench_batched(a, b, torch, pvl, t0):
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
+
+
+def _bench_hsolve(ctx, s, pos, m, torch):
+    """h-iteration on the workload's positions from a constant 48-neighbour
+    start: Newton on rho h^3 = m eta^3 to a relative residual of 1e-6."""
+    from synth import h_for_neighbours
+    h = torch.full((s.n,), h_for_neighbours(s.n, L=s.box[0]), dtype=torch.float32,
+                   device=pos.device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, res = ctx.solve_h(pos, m, h, s.box, ngb=48.0, tol=1e-6, max_iter=40)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"iterations": it, "residual": res, "ms": ms, "ms_per_iteration": ms / max(it, 1),
+            "start": "constant h of 48 neighbours at the mean density", "tol": 1e-6}
 
 
 def _cpu_baseline_batched(b, target_seconds):

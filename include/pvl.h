@@ -214,6 +214,30 @@ typedef enum { PV_TUNE_DENSITY = 0, PV_TUNE_ADJOINT = 1, PV_TUNE_PLAIN = 2 } pv_
 pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const float *grad_rho,
                       int reps, float times_ms[2]);
 
+/* Smoothing lengths from the density (the h-iteration around the density
+ * loop of an SPH code; not part of the paper's method).  Solves, for every
+ * particle, rho_i(h_i) h_i^3 = m_i eta^3 with eta^3 = 3 ngb / (4 pi gamma^3),
+ * rho_i taken with the particle's own cut-off gamma h_i; with equal masses this
+ * is the weighted neighbour number (4 pi / 3) H_i^3 wcount_i = ngb.  Each
+ * iteration builds the cells (auto grid), sorts them, runs the sorted-pair
+ * density for rho and drho_dh, and takes one Newton step per particle (steps
+ * limited to a factor 1.5).  The boxes are given as for
+ * pv_build_cells_batched (offsets host, nbox + 1; box host, 3 * nbox).
+ *   pos, mass  device, input order (pos n x 3)
+ *   h          device, n: the initial guess on entry, on return the last
+ *              evaluated h (the one whose residual is reported)
+ *   tol        stop when max_i |rho_i h_i^3 - m_i eta^3| / (m_i eta^3) <= tol
+ *   iters      host, may be NULL: density evaluations made
+ *   resid      host, may be NULL: that largest relative residual
+ * Returns PV_OK when the iterations ran (compare *resid with tol to see
+ * whether it converged within max_iter), or the error of a build (PV_EGRID when
+ * a cut-off outgrows a third of the box, PV_EOVERFLOW for a crowded cell).
+ * Allocates temporary device memory and synchronises every iteration; not for
+ * graph capture. */
+pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float *pos,
+                     const float *mass, float *h, const double *box, float ngb, float tol,
+                     int max_iter, int *iters, float *resid);
+
 /* Release a cell structure.  NULL is accepted. */
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells);
 

@@ -10,6 +10,7 @@ Nothing here computes densities on the CPU; without the built library the
 calls raise.
 """
 from .pvl import (Cells, Context, PVError, context, density, load_library,  # noqa: F401
-                  ALGOS, PV_MAX_CELL, PV_MAX_GRID, EXPORTS, LIB_PATH)
+                  ALGOS, PV_MAX_CELL, PV_MAX_GRID, EXPORTS, LIB_PATH, PV_OK, PV_EINVAL,
+                  PV_ENOMEM, PV_EHIP, PV_EGRID, PV_EOVERFLOW, PV_ESTATE)
 
 __all__ = ["Cells", "Context", "PVError", "context", "density", "load_library"]

@@ -623,6 +623,70 @@ pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const floa
     return PV_OK;
 }
 
+pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float *pos,
+                     const float *mass, float *h, const double *box, float ngb, float tol,
+                     int max_iter, int *iters, float *resid)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!(ngb > 0.0f) || !(tol > 0.0f)) return fail(ctx, PV_EINVAL, "ngb and tol must be > 0");
+    if (max_iter < 1 || max_iter > 1000) return fail(ctx, PV_EINVAL, "max_iter must be 1..1000");
+    if (nbox < 1 || !offsets) return fail(ctx, PV_EINVAL, "nbox < 1 or offsets is NULL");
+    const int64_t n = offsets[nbox];
+    if (n > 0 && (!pos || !mass || !h)) return fail(ctx, PV_EINVAL, "NULL particle array");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const float g = pvl::kGamma;
+    const float eta3 = 3.0f * ngb / (4.0f * pvl::kPi * g * g * g);
+    float *buf = nullptr;       // rho, drho_dh, h_next
+    uint32_t *dres = nullptr;
+    HIPCHK(ctx, hipMalloc((void **)&buf, sizeof(float) * 3 * (size_t)std::max<int64_t>(n, 1)));
+    if (hipMalloc((void **)&dres, sizeof(uint32_t)) != hipSuccess) {
+        (void)hipFree(buf);
+        return fail(ctx, PV_ENOMEM, "solve_h: device allocation failed");
+    }
+    float *rho = buf, *drho = buf + n, *hnext = buf + 2 * n;
+    pv_cells *cells = nullptr;
+    pv_status st = PV_OK;
+    float r = INFINITY;
+    int it = 0;
+    while (it < max_iter) {
+        ++it;
+        st = pv_build_cells_batched(ctx, nbox, offsets, pos, h, mass, box, nullptr, &cells);
+        if (st == PV_OK) st = pv_sort_cells(ctx, cells);
+        if (st == PV_OK) st = pv_density(ctx, cells, PV_SORTED_PAIR, rho, nullptr, drho, nullptr);
+        if (st == PV_OK) st = pv_check(ctx);
+        if (st != PV_OK) break;
+        hipError_t e = pvl::launch_zero(ctx->stream, dres, 1);
+        if (e == hipSuccess)
+            e = pvl::launch_h_newton(ctx->stream, n, rho, drho, mass, h, eta3, hnext, dres);
+        uint32_t rb = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ctx->hpinned, dres, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                               ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            st = fail(ctx, PV_EHIP, std::string("solve_h: ") + hipGetErrorString(e));
+            break;
+        }
+        rb = (uint32_t)ctx->hpinned[0];
+        memcpy(&r, &rb, sizeof(r));
+        // h stays the last evaluated one when the loop ends
+        if (r <= tol || it == max_iter) break;
+        e = pvl::launch_copy_f32(ctx->stream, n, hnext, h);
+        if (e != hipSuccess) {
+            st = fail(ctx, PV_EHIP, std::string("solve_h: ") + hipGetErrorString(e));
+            break;
+        }
+    }
+    if (cells) pv_free_cells(ctx, cells);
+    (void)hipFree(buf);
+    (void)hipFree(dres);
+    if (iters) *iters = it;
+    if (resid) *resid = r;
+    if (st == PV_OK) ctx->err.clear();
+    return st;
+}
+
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells)
 {
     if (!cells) return PV_OK;

@@ -138,4 +138,9 @@ hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t
                            const float *grad_rho, float *grad_pos, float *grad_h,
                            const int *dflags, const SweepTuning &tune);
 
+hipError_t launch_h_newton(hipStream_t st, int64_t n, const float *rho, const float *drho_dh,
+                           const float *mass, const float *h, float eta3, float *h_next,
+                           uint32_t *resid);
+hipError_t launch_copy_f32(hipStream_t st, int64_t n, const float *src, float *dst);
+
 }  // namespace pvl

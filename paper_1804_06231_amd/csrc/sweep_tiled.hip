@@ -87,17 +87,14 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH, Ti
 {
     float u = __builtin_amdgcn_sqrtf(r2) * invH;   // v_sqrt_f32, 1 ulp
     float u2 = u * u;
-    float v = 1.0f - u;
-    float v2 = v * v;
-    // inner piece (u < 1/2): w = 1 - 6u^2 + 6u^3, 3w + u w' = 3 - 30u^2 + 36u^3
-    float wi = fmaf(u2, fmaf(6.0f, u, -6.0f), 1.0f);
-    float di = fmaf(u2, fmaf(36.0f, u, -30.0f), 3.0f);
-    // outer piece: w = 2 (1-u)^3, 3w + u w' = 6 (1-u)^2 (1 - 2u)
-    float wo = 2.0f * v2 * v;
-    float dout = v2 * fmaf(-12.0f, u, 6.0f);
-    bool in = u < 0.5f;
-    float w = in ? wi : wo;
-    float d3 = in ? di : dout;
+    // inner piece (u < 1/2): w = 1 - 6u^2 + 6u^3, 3w + u w' = 3 - 30u^2 + 36u^3.
+    // The outer piece differs from it by t^3 and 3 t^2 (1 - 4u) with
+    // t = 1 - 2u, so with t = min(0, 1 - 2u) one expression covers both:
+    // w = 2 (1-u)^3 and 3w + u w' = 6 (1-u)^2 (1 - 2u) for u >= 1/2.
+    float t = fminf(fmaf(-2.0f, u, 1.0f), 0.0f);
+    float t2 = t * t;
+    float w = fmaf(u2, fmaf(6.0f, u, -6.0f), 1.0f) + t2 * t;
+    float d3 = fmaf(3.0f * t2, fmaf(-4.0f, u, 1.0f), fmaf(u2, fmaf(36.0f, u, -30.0f), 3.0f));
     a.rho = fmaf(mj, w, a.rho);
     a.wc += w;
     a.dh = fmaf(mj, d3, a.dh);
@@ -114,12 +111,15 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
 {
     float invr = __builtin_amdgcn_rsqf(r2);   // v_rsq_f32, 1 ulp
     float r = r2 * invr;
-    float uk = r * invHk, vk = 1.0f - uk;
-    float uj = r * invHj, vj = 1.0f - uj;
-    // w' = -12u + 18u^2 (u < 1/2), -6 (1-u)^2 (u >= 1/2); w as in the forward
-    float dwk = uk < 0.5f ? uk * fmaf(18.0f, uk, -12.0f) : -6.0f * vk * vk;
-    float wk = uk < 0.5f ? fmaf(uk * uk, fmaf(6.0f, uk, -6.0f), 1.0f) : 2.0f * vk * vk * vk;
-    float dwj = uj < 0.5f ? uj * fmaf(18.0f, uj, -12.0f) : -6.0f * vj * vj;
+    float uk = r * invHk;
+    float uj = r * invHj;
+    // w' = -12u + 18u^2 (u < 1/2), -6 (1-u)^2 (u >= 1/2): the outer piece is
+    // the inner one minus 6 t^2 with t = min(0, 1 - 2u); w as in the forward
+    float tk = fminf(fmaf(-2.0f, uk, 1.0f), 0.0f);
+    float tj = fminf(fmaf(-2.0f, uj, 1.0f), 0.0f);
+    float dwk = fmaf(-6.0f * tk, tk, uk * fmaf(18.0f, uk, -12.0f));
+    float wk = fmaf(uk * uk, fmaf(6.0f, uk, -6.0f), 1.0f) + tk * tk * tk;
+    float dwj = fmaf(-6.0f * tj, tj, uj * fmaf(18.0f, uj, -12.0f));
     bool ink = r2 < Hk2, inj = r2 < Hj2;
     float coef = (ink ? ck * mj * dwk : 0.0f) + (inj ? cj * mk * dwj : 0.0f);
     a.dh += ink ? mj * fmaf(uk, dwk, 3.0f * wk) : 0.0f;

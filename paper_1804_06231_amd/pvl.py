@@ -27,7 +27,7 @@ EXPORTS = (
     "pv_create", "pv_destroy", "pv_set_stream", "pv_last_error", "pv_build_cells",
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
-    "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune",
+    "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h",
 )
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4}
 PV_PARAM_ADJOINT = 16
@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
         "pv_set_param": ([P, i32, i32], i32),
         "pv_get_param": ([P, i32, P], i32),
         "pv_autotune": ([P, P, i32, P, i32, P], i32),
+        "pv_solve_h": ([P, i32, P, P, P, P, P, C.c_float, C.c_float, i32, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -262,6 +263,31 @@ class Context:
         self._sync_stream()
         self._call("pv_density_backward", cells.handle, _ptr(grad_rho), _ptr(gp), _ptr(gh))
         return gp, gh
+
+    def solve_h(self, pos, mass, h, box=(1.0, 1.0, 1.0), ngb: float = 48.0, tol: float = 1e-6,
+                max_iter: int = 30, offsets=None, boxes=None):
+        """Solve rho_i(h_i) h_i^3 = m_i eta^3 (eta from the weighted neighbour
+        number ngb) in place in h (pv_solve_h).  One box, or several with
+        offsets/boxes as in build_cells_batched.  Returns (iterations, largest
+        relative residual)."""
+        n = int(pos.shape[0])
+        _dev_f32(pos, n, 3, "pos", self.device)
+        _dev_f32(mass, n, 0, "mass", self.device)
+        _dev_f32(h, n, 0, "h", self.device)
+        if offsets is None:
+            offsets, boxes = [0, n], [box]
+        nbox = len(offsets) - 1
+        off = (C.c_int64 * (nbox + 1))(*[int(x) for x in offsets])
+        bx = []
+        for b in boxes:
+            bx.extend([float(b)] * 3 if isinstance(b, (int, float)) else [float(x) for x in b])
+        barr = (C.c_double * (3 * nbox))(*bx)
+        it = C.c_int()
+        res = C.c_float()
+        self._sync_stream()
+        self._call("pv_solve_h", nbox, off, _ptr(pos), _ptr(mass), _ptr(h), barr, float(ngb),
+                   float(tol), int(max_iter), C.byref(it), C.byref(res))
+        return it.value, res.value
 
     def check(self) -> None:
         self._sync_stream()
