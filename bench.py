@@ -188,6 +188,8 @@ def main():
     ms_adj, _ = _time_loop(lambda: ctx.density_backward(cells, g_rho, out_g), a.steps, 1, torch)
     ctx.check()
     hsolve = _bench_hsolve(ctx, s, pos, m, torch)
+    reuse = _bench_reuse(a, ctx, s, pos, h, m, grid, out_s, torch)
+    reuse["speedup_vs_rebuild"] = ms_sorted / reuse["ms_per_step"]
 
     n = s.n
     value = pairs / (ms_sorted * 1e-3)
@@ -229,6 +231,7 @@ def main():
                                     "in_range": inr / n},
         "autotune": tuning,
         "h_iteration": hsolve,
+        "verlet_reuse": reuse,
         "wall_ms_per_step": wall_sorted,
         "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
@@ -363,6 +366,35 @@ def bench_batched(a, b, torch, pvl, t0):
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
+
+
+def _bench_reuse(a, ctx, s, pos, h, m, grid, out, torch):
+    """Steps that keep the cells and their sorted lists (Section 2's reuse with
+    bounds widened by the displacement): drift every particle by a fixed small
+    step, then the sorted-pair density.  The step length leaves room in the
+    cells for all the steps timed here."""
+    cells = ctx.build_cells(pos, h, m, s.box, grid)
+    ctx.sort_cells(cells)
+    info = cells.info()
+    room = min(s.box) / max(info["grid"]) - info["hmax"]
+    nstep = a.warmup + 2 * (a.steps + 1) + 4
+    dx = room / (4.0 * nstep)
+    gen = torch.Generator(device=pos.device)
+    gen.manual_seed(11)
+    d = torch.randn((s.n, 3), generator=gen, device=pos.device)
+    d = d / d.norm(dim=1, keepdim=True) * dx
+
+    def step():
+        ctx.drift(cells, d)
+        ctx.density(cells, "sorted", out)
+
+    ms_eager, _ = _time_loop(step, a.steps, a.warmup, torch)
+    graph = _capture(step, torch)
+    ms, _ = _time_loop(graph.replay, a.steps, 0, torch)
+    ctx.check()
+    del graph
+    return {"ms_per_step": ms, "eager_ms_per_step": ms_eager, "displacement_per_step": dx,
+            "step": "drift + sorted-pair density on kept cells and sorted lists"}
 
 
 def _bench_hsolve(ctx, s, pos, m, torch):

@@ -141,8 +141,10 @@ pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rh
 pv_status pv_density_backward(pv_ctx *ctx, const pv_cells *cells, const float *grad_rho,
                               float *grad_pos, float *grad_h);
 
-/* Synchronise the context's stream and report device-detected errors
- * (PV_EOVERFLOW, PV_EGRID) raised since the last check. */
+/* Synchronise the context's stream and report device-detected errors raised
+ * since the last check: PV_EOVERFLOW (a crowded cell), PV_EGRID (a cut-off
+ * above the cell edge, or h <= 0), PV_ESTATE (particles moved by pv_drift
+ * farther than the cells allow). */
 pv_status pv_check(pv_ctx *ctx);
 
 /* Describe a cell structure (host outputs, any may be NULL; box 0 for grid).
@@ -213,6 +215,19 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value);
 typedef enum { PV_TUNE_DENSITY = 0, PV_TUNE_ADJOINT = 1, PV_TUNE_PLAIN = 2 } pv_tune_target;
 pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const float *grad_rho,
                       int reps, float times_ms[2]);
+
+/* Move the particles of sorted cells without rebuilding them (Section 2: the
+ * sorted lists can be reused over several time steps when every projected
+ * bound is widened by the particles' displacement).  disp: device, n x 3, input
+ * order, added to the stored positions (the caller's pos arrays are not
+ * touched).  Each cell accumulates a bound on its particles' displacement since
+ * the build; later pv_density / pv_density_backward calls widen their bounds by
+ * the bounds of the two cells of each pair, so the results are those of the
+ * moved positions.  The cells stay usable while largest cut-off + the two
+ * displacement bounds fit the cell edge; past that the sweeps flag the error
+ * word and pv_check returns PV_ESTATE (rebuild with pv_build_cells).  After a
+ * drift, pv_sort_cells is refused (PV_ESTATE): rebuild instead. */
+pv_status pv_drift(pv_ctx *ctx, pv_cells *cells, const float *disp);
 
 /* Smoothing lengths from the density (the h-iteration around the density
  * loop of an SPH code; not part of the paper's method).  Solves, for every

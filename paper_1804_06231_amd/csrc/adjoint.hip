@@ -22,7 +22,7 @@ __global__ void k_gather_grad(int64_t n, const int32_t *__restrict__ orig,
 
 hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                            const float *grad_rho, float *grad_pos, float *grad_h,
-                           const int *dflags, const SweepTuning &tune)
+                           int *dflags, const SweepTuning &tune)
 {
     if (n == 0 || ncell == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gather_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n,

@@ -513,6 +513,44 @@ __global__ void k_cell_box(const BoxDesc *__restrict__ box, int nbox, int64_t nc
     cell_box[c] = lo;
 }
 
+// One workgroup per cell: add each particle's displacement (input order) to
+// its cell-relative position, and the largest displacement of the cell to the
+// cell's accumulated bound (single writer); the structure-wide largest bound
+// goes to dx_all.
+__global__ void __launch_bounds__(kBlock) k_drift(const int32_t *__restrict__ start,
+                                                  const int32_t *__restrict__ orig,
+                                                  const float *__restrict__ disp,
+                                                  float4 *__restrict__ xyzm,
+                                                  float *__restrict__ cell_dx,
+                                                  uint32_t *__restrict__ dx_all)
+{
+    __shared__ float red[kBlock / 64];
+    const int c = blockIdx.x;
+    const int s0 = start[c], s1 = start[c + 1];
+    float mx = 0.0f;
+    for (int p = s0 + threadIdx.x; p < s1; p += blockDim.x) {
+        const int64_t o = orig[p];
+        const float dx = disp[3 * o + 0], dy = disp[3 * o + 1], dz = disp[3 * o + 2];
+        float4 q = xyzm[p];
+        q.x += dx;
+        q.y += dy;
+        q.z += dz;
+        xyzm[p] = q;
+        // |d| rounded up a little so that the bound stays an upper bound
+        mx = fmaxf(mx, sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) * 1.0000005f);
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.0f;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmaxf(m, red[w]);
+        const float acc = (cell_dx[c] + m) * 1.0000005f;
+        cell_dx[c] = acc;
+        atomicMax(dx_all, __float_as_uint(acc));
+    }
+}
+
 __global__ void k_zero(uint32_t *__restrict__ p, int64_t words)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,6 +563,14 @@ hipError_t launch_zero(hipStream_t st, void *p, int64_t words)
 {
     if (words <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero, dim3(blocks_for(words, 256)), dim3(256), 0, st, (uint32_t *)p, words);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(hipStream_t st, const DevCells &c, int64_t ncell, const float *disp)
+{
+    if (ncell == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_drift, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.cell_start, c.orig,
+                       disp, c.xyzm, c.cell_dx, c.dx_all);
     return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ struct pv_cells {
     DevCells d;
     int64_t cap_n = 0, cap_cell = 0, cap_box = 0, cap_m = 0, cap_blocks = 0;
     bool sorted = false;
+    bool drifted = false;   // positions moved by pv_drift since the build
 };
 
 namespace {
@@ -67,7 +68,7 @@ void free_dev(DevCells &d)
 {
     void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cellid, d.slot, d.stage,
                     d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
-                    d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks};
+                    d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks, d.cell_dx, d.dx_all};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DevCells();
@@ -108,6 +109,8 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.scan_tmp, pvl::scan_scratch_words(C));
     ALLOC(d.binm, M);
     ALLOC(d.bin_blocks, NB);
+    ALLOC(d.cell_dx, C);
+    ALLOC(d.dx_all, 1);
 #undef ALLOC
     if (e != hipSuccess) {
         free_dev(c->d);
@@ -327,7 +330,10 @@ pv_status pv_build_cells_batched(pv_ctx *ctx, int nbox, const int64_t *offsets,
     c->ncell = ncell;
     c->sorted = false;
     if ((st = upload_boxes(ctx, c)) != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
+    c->drifted = false;
     hipError_t e = pvl::launch_zero(ctx->stream, ctx->dflags + 1, 1);
+    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, c->d.cell_dx, ncell);
+    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, c->d.dx_all, 1);
     if (e == hipSuccess)
         e = pvl::launch_bin(ctx->stream, c->d, c->plan, nbox, n, ncell, pos, h, mass, ctx->dflags);
     if (e != hipSuccess) {
@@ -372,6 +378,8 @@ pv_status pv_sort_cells(pv_ctx *ctx, pv_cells *cells)
     if (!ctx) return PV_EINVAL;
     if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
     if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    if (cells->drifted)
+        return fail(ctx, PV_ESTATE, "cells moved by pv_drift are rebuilt, not re-sorted");
     HIPCHK(ctx, pvl::launch_sort13(ctx->stream, cells->d, cells->n, cells->ncell));
     cells->sorted = true;
     return PV_OK;
@@ -421,6 +429,10 @@ pv_status pv_check(pv_ctx *ctx)
         if (bits & pvl::kErrOverflow)
             return fail(ctx, PV_EOVERFLOW, "a cell held " + std::to_string(ctx->hpinned[1]) +
                                                " particles (max " + std::to_string(PV_MAX_CELL) + ")");
+        if (bits & pvl::kErrDrift)
+            return fail(ctx, PV_ESTATE, "particles moved farther since the build than the cell "
+                                        "edge leaves room for (largest cut-off + twice the "
+                                        "displacement > edge): rebuild the cells");
         return fail(ctx, PV_EGRID, "a cut-off exceeded the cell edge (grid too fine) or h <= 0");
     }
     return PV_OK;
@@ -620,6 +632,18 @@ pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const floa
         times_ms[0] = before;
         times_ms[1] = best_ms;
     }
+    return PV_OK;
+}
+
+pv_status pv_drift(pv_ctx *ctx, pv_cells *cells, const float *disp)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (!disp && cells->n > 0) return fail(ctx, PV_EINVAL, "disp is NULL");
+    if (!cells->sorted) return fail(ctx, PV_ESTATE, "pv_sort_cells must run before pv_drift");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    HIPCHK(ctx, pvl::launch_drift(ctx->stream, cells->d, cells->ncell, disp));
+    cells->drifted = true;
     return PV_OK;
 }
 

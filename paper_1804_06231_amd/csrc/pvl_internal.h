@@ -19,6 +19,7 @@ constexpr int kBlock = 256;
 // Device error bits.
 constexpr int kErrOverflow = 1;
 constexpr int kErrGrid = 2;
+constexpr int kErrDrift = 4;   // particles moved farther than the cells allow
 
 // One periodic box of a (possibly batched) cell structure, as the kernels see it.
 struct BoxDesc {
@@ -90,6 +91,8 @@ struct DevCells {
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
     int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
     int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
+    float *cell_dx = nullptr;     // ncell: accumulated largest displacement since the build
+    uint32_t *dx_all = nullptr;   // largest cell_dx of the structure (fp32 bits)
     int4 *bin_blocks = nullptr;   // binning chunks: (box, chunk in box, first, end particle)
 };
 
@@ -127,17 +130,18 @@ int queue_capacity(int64_t n, int64_t ncell);
 
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                        const int *dflags, unsigned long long *census, const SweepTuning &tune);
+                        int *dflags, unsigned long long *census, const SweepTuning &tune);
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                              const int *dflags, const SweepTuning &tune, bool plain);
+                              int *dflags, const SweepTuning &tune, bool plain);
 hipError_t launch_backward_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
-                                 float *grad_pos, float *grad_h, const int *dflags,
+                                 float *grad_pos, float *grad_h, int *dflags,
                                  const SweepTuning &tune);
 hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                            const float *grad_rho, float *grad_pos, float *grad_h,
-                           const int *dflags, const SweepTuning &tune);
+                           int *dflags, const SweepTuning &tune);
 
+hipError_t launch_drift(hipStream_t st, const DevCells &c, int64_t ncell, const float *disp);
 hipError_t launch_h_newton(hipStream_t st, int64_t n, const float *rho, const float *drho_dh,
                            const float *mass, const float *h, float eta3, float *h_next,
                            uint32_t *resid);

@@ -154,9 +154,9 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
     const float *__restrict__ Hc, const int32_t *__restrict__ orig,
-    const uint16_t *__restrict__ sidx, const float *__restrict__ skey, int64_t n, float *rho,
-    float *wcount, float *drho_dh, int32_t *ncount, const int *__restrict__ dflags,
-    unsigned long long *census, int only_above)
+    const uint16_t *__restrict__ sidx, const float *__restrict__ skey,
+    const float *__restrict__ cell_dx, int64_t n, float *rho, float *wcount, float *drho_dh,
+    int32_t *ncount, const int *__restrict__ dflags, unsigned long long *census, int only_above)
 {
     if (dflags[0]) return;
     const int a = blockIdx.x;
@@ -196,6 +196,8 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
                 dir_axis(s, e);
                 float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
                 float ki = proj_key(pi.x, pi.y, pi.z, s);
+                // sorted keys may predate a drift: widen by both cells' bounds
+                const float mg = cell_dx[a] + cell_dx[b];
                 const float *kb = skey + (size_t)s * n + sb;
                 const uint16_t *ib = sidx + (size_t)s * n + sb;
                 PairFrame f = pair_frame(pi.x, pi.y, pi.z, dx, dy, dz, sx, sy, sz);
@@ -203,10 +205,10 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
                 if (sign > 0) {
                     // neighbour ahead: key_j + se - key_i < H_i  ->  prefix
                     j0 = 0;
-                    j1 = bsearch_keys(kb, nb, (ki - se) + Hi + slack, false);
+                    j1 = bsearch_keys(kb, nb, (ki - se) + Hi + slack + mg, false);
                 } else {
                     // neighbour behind: key_i - (key_j + se) < H_i  ->  suffix
-                    j0 = bsearch_keys(kb, nb, (ki - se) - Hi - slack, true);
+                    j0 = bsearch_keys(kb, nb, (ki - se) - Hi - slack - mg, true);
                     j1 = nb;
                 }
                 for (int j = j0; j < j1; ++j) {
@@ -227,7 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
 
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                        const int *dflags, unsigned long long *census,
+                        int *dflags, unsigned long long *census,
                         const SweepTuning &tune)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
@@ -240,8 +242,8 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
                                drho_dh, ncount, dflags, census, 0);
         else
             hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                               c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey, n,
-                               rho, wcount, drho_dh, ncount, dflags, census, 0);
+                               c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey,
+                               c.cell_dx, n, rho, wcount, drho_dh, ncount, dflags, census, 0);
     } else {
         return launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags, tune,
                                   algo == PV_PLAIN_CELL);

@@ -184,7 +184,9 @@ struct SweepArgs {
     int32_t *ncount;
     const float *gcell;          // adjoint: upstream gradient in cell order
     float *grad_pos, *grad_h;    // adjoint outputs (input order)
-    const int *dflags;
+    int *dflags;
+    const float *cell_dx;        // accumulated displacement bound per cell (pv_drift)
+    const uint32_t *dx_all;      // its largest value (fp32 bits)
     const int2 *items;   // queue: [0, nbig) large-cell chunks, [cap - nsmall, cap) cells
     const int *qcount;   // [0] nbig, [1] nsmall
     int *head;           // items taken after the first static round
@@ -224,7 +226,16 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
     const CellGeom ga = cell_geom(B, a);
     const float slack = 1.52587890625e-5f * (B.edge[0] + B.edge[1] + B.edge[2]);
     const float hmax_a = __uint_as_float(A.cell_hmax[a]);
+    // Section 2: sorted lists stay usable after the particles move, with every
+    // projected bound widened by the displacements; the cells stay usable while
+    // H + dx_i + dx_j fits the edge
+    const float dx_a = A.cell_dx[a];
     const int tid = threadIdx.x;
+    if (tid == 0) {
+        const float dx_all = __uint_as_float(*A.dx_all);
+        const float emin = fminf(B.edge[0], fminf(B.edge[1], B.edge[2]));
+        if (dx_all > 0.0f && hmax_a + dx_a + dx_all > emin) atomicOr(A.dflags, kErrDrift);
+    }
     const int wave = tid >> 6, lane = tid & 63;
     const uint16_t *sidx = A.sidx;
     const float *skey = A.skey;
@@ -248,7 +259,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             const float *ka = skey + (size_t)s * n + sa;
             const float *kb = skey + (size_t)s * n + sb;
             // the adjoint also keeps pairs decided by the source's cut-off
-            const float reach = ADJ ? fmaxf(hmax_a, __uint_as_float(A.cell_hmax[b])) : hmax_a;
+            const float reach = (ADJ ? fmaxf(hmax_a, __uint_as_float(A.cell_hmax[b])) : hmax_a) +
+                                (dx_a + A.cell_dx[b]);
             if (sign > 0) {
                 // receivers with key_i + reach > key_b[0] + se
                 float thr = (kb[0] + se) - reach - slack;
@@ -422,7 +434,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             float hb = ADJ ? hmax_a : 0.0f;
             if (!ADJ)
                 for (int r = r0; r < r1; ++r) hb = fmaxf(hb, A.Hc[sa + r]);
-            const float lo_k = ka[r0] - hb - slack, hi_k = ka[r1 - 1] + hb + slack;
+            const float lo_k = ka[r0] - hb - slack - 2.0f * dx_a;
+            const float hi_k = ka[r1 - 1] + hb + slack + 2.0f * dx_a;
             int lo = 0, hi = na;
             while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] <= lo_k) lo = m + 1; else hi = m; }
             const int j0 = lo;
@@ -447,6 +460,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             const float *kb = skey + (size_t)s * n + sb;
             const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[dir]);
             const float hmax_b = __uint_as_float(A.cell_hmax[b]);
+            const float mg = dx_a + A.cell_dx[b];
             // block reach: the largest key + H (ahead) or smallest key - H (behind)
             float T = sign > 0 ? -INFINITY : INFINITY;
             for (int r = r0; r < r1; ++r) {
@@ -466,12 +480,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             }
             int nsrc;
             if (sign > 0) {
-                T = (T - se) + slack;
+                T = (T - se) + slack + mg;
                 int lo = 0, hi = nb;
                 while (lo < hi) { int m = (lo + hi) >> 1; if (kb[m] < T) lo = m + 1; else hi = m; }
                 nsrc = lo;
             } else {
-                T = (T - se) - slack;
+                T = (T - se) - slack - mg;
                 int lo = 0, hi = nb;
                 while (lo < hi) { int m = (lo + hi) >> 1; if (kb[m] <= T) lo = m + 1; else hi = m; }
                 nsrc = nb - lo;
@@ -722,6 +736,8 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.sidx = c.sidx;
     A.skey = c.skey;
     A.n = n;
+    A.cell_dx = c.cell_dx;
+    A.dx_all = c.dx_all;
     A.items = c.items;
     A.qcount = c.qcount;
     A.head = c.qcount + 2;
@@ -744,7 +760,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
 
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                              const int *dflags, const SweepTuning &tune, bool plain)
+                              int *dflags, const SweepTuning &tune, bool plain)
 {
     SweepArgs A = {};
     A.rho = rho;
@@ -756,7 +772,7 @@ hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int6
 }
 
 hipError_t launch_backward_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
-                                 float *grad_pos, float *grad_h, const int *dflags,
+                                 float *grad_pos, float *grad_h, int *dflags,
                                  const SweepTuning &tune)
 {
     SweepArgs A = {};

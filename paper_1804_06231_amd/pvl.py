@@ -27,7 +27,7 @@ EXPORTS = (
     "pv_create", "pv_destroy", "pv_set_stream", "pv_last_error", "pv_build_cells",
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
-    "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h",
+    "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h", "pv_drift",
 )
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4}
 PV_PARAM_ADJOINT = 16
@@ -80,6 +80,7 @@ def load_library(path: str = LIB_PATH):
         "pv_get_param": ([P, i32, P], i32),
         "pv_autotune": ([P, P, i32, P, i32, P], i32),
         "pv_solve_h": ([P, i32, P, P, P, P, P, C.c_float, C.c_float, i32, P, P], i32),
+        "pv_drift": ([P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -251,6 +252,13 @@ class Context:
         self._sync_stream()
         self._call("pv_density", cells.handle, ALGOS[algo], _ptr(rho), _ptr(wc), _ptr(dh), _ptr(nc))
         return rho, wc, dh, nc
+
+    def drift(self, cells: Cells, disp) -> None:
+        """Move the cells' particles by disp (n x 3, input order) keeping the
+        sorted lists (pv_drift)."""
+        _dev_f32(disp, cells.n, 3, "disp", self.device)
+        self._sync_stream()
+        self._call("pv_drift", cells.handle, _ptr(disp))
 
     def density_backward(self, cells: Cells, grad_rho, out=None):
         n = cells.n

@@ -26,7 +26,7 @@ from scipy.spatial import cKDTree
 __all__ = [
     "GAMMA", "GUARD", "ParticleSet", "h_for_neighbours", "finest_grid",
     "guard_violations", "uniform_set", "lattice_set", "plummer_set",
-    "adjoint_set", "batched_sets", "batched_sizes", "BatchedSet", "batched_workload",
+    "adjoint_set", "drift_set", "batched_sets", "batched_sizes", "BatchedSet", "batched_workload",
     "workload", "WORKLOADS",
 ]
 
@@ -248,6 +248,43 @@ def adjoint_set(n: int, seed: int, jitter: float = 0.2, L: float = 1.0) -> Parti
     sig = 0.05 * L * n ** (-1.0 / 3.0)
     pert = _wrap32(s.pos.astype(np.float64) + rng.normal(0.0, sig, (n, 3)), L)
     s.extra["pos_target"] = pert
+    return s
+
+
+def drift_set(n: int, seed: int, steps: int, dmax: float, L: float = 1.0) -> ParticleSet:
+    """Uniform particles with lognormal h plus `steps` displacement vectors
+    (extra["disp"], each (n, 3) fp32, |d| <= dmax per particle and step, random
+    directions).  h is nudged until the guard band holds for the starting
+    positions and for every configuration pos + sum of the first k
+    displacements (fp64), so neighbour counts can be compared exactly at each
+    step."""
+    s = uniform_set(n, seed, hmode="lognormal", L=L, guard=False, name=f"drift-{n}")
+    rng = np.random.Generator(np.random.PCG64([seed, 0x3C6EF372]))
+    disp = []
+    for _ in range(steps):
+        v = rng.standard_normal((n, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        r = dmax * rng.random(n) ** (1.0 / 3.0)
+        disp.append((v * r[:, None]).astype(np.float32))
+    confs = [s.pos.astype(np.float64)]
+    for d in disp:
+        confs.append(confs[-1] + d.astype(np.float64))
+    h = s.h.copy()
+    for _ in range(32):
+        clean = True
+        for x in confs:
+            xw = np.mod(x, L)
+            bad = guard_violations(xw, h, L)
+            if bad.size:
+                clean = False
+                h[bad] = (h[bad].astype(np.float64) * (1.0 + 5e-5)).astype(np.float32)
+        if clean:
+            break
+    else:
+        raise RuntimeError("guard band: drift set did not settle")
+    s.h = h
+    s.extra["disp"] = disp
+    s.extra["positions"] = confs
     return s
 
 
