@@ -104,7 +104,7 @@ def _time_loop(fn, steps, warmup, torch):
 def main():
     a = _args()
     if a.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {a.gpus}); "
+        print(f"bench.py: measures one GPU only (asked for --gpus {a.gpus}); "
               "the path runs on a single MI355X and has no multi-GPU mode.", file=sys.stderr)
         sys.exit(2)
     import torch

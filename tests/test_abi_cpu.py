@@ -20,7 +20,7 @@ def _declared():
 def lib():
     from paper_1804_06231_amd.pvl import load_library, LIB_PATH
     if not os.path.exists(LIB_PATH):
-        pytest.fail("libpvl.so is not built (run __graft_entry__.build())")
+        pytest.fail("libpvl.so is not built (python -m paper_1804_06231_amd.build)")
     return load_library()
 
 
