@@ -53,6 +53,10 @@ def _load():
     lib.or_fd_loss_many.argtypes = [P, P, P, P, P, i64, P]
     lib.or_solve_h.argtypes = [P, C.c_double, P, P]
     lib.or_solve_h.restype = i64
+    lib.or_lj.argtypes = [P, C.c_double, C.c_double, P, i64, P, P, P]
+    lib.or_lj.restype = None
+    lib.or_lj_energy_moved.argtypes = [P, C.c_double, C.c_double, i64, C.c_int, C.c_double]
+    lib.or_lj_energy_moved.restype = C.c_double
     _lib = lib
     return lib
 
@@ -128,6 +132,24 @@ class Oracle:
         self.lib.or_density_grad(self.handle, _ptr(G), _ptr(r), k, _ptr(out["gx"]),
                                  _ptr(out["gh"]), _ptr(out["gx_abs"]), _ptr(out["gh_abs"]))
         return out
+
+    def lj(self, eps, sigma, recv=None):
+        """Lennard-Jones force (k, 3), energy (k,) and |term| sums (k, 3) over
+        pairs within each receiver's cut-off."""
+        if recv is None:
+            k, r = self.n, None
+        else:
+            r = np.ascontiguousarray(np.asarray(recv, dtype=np.int64))
+            k = r.size
+        out = {"force": np.zeros((k, 3)), "energy": np.zeros(k), "f_abs": np.zeros((k, 3))}
+        self.lib.or_lj(self.handle, float(eps), float(sigma), _ptr(r), k, _ptr(out["force"]),
+                       _ptr(out["energy"]), _ptr(out["f_abs"]))
+        return out
+
+    def lj_energy_moved(self, eps, sigma, k, comp, delta):
+        """Total Lennard-Jones energy with particle k's coordinate comp moved by delta."""
+        return self.lib.or_lj_energy_moved(self.handle, float(eps), float(sigma), int(k),
+                                           int(comp), float(delta))
 
     def fd_loss(self, target, ks, comps, eps):
         """Central differences of L = sum (rho - target)^2 for each (k, comp, eps)."""

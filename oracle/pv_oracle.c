@@ -403,3 +403,81 @@ int64_t or_solve_h(const or_grid *G, double eta, const double *h_lo, double *h_o
     }
     return bad;
 }
+
+/*
+ * Lennard-Jones forces and energies over the same neighbour sets (the paper's
+ * introduction: the pseudo-Verlet list serves molecular dynamics as well as
+ * SPH).  For every pair with r_ij < H_i (H_i = GAMMA h_i, the receiver's
+ * cut-off):
+ *
+ *   U(r) = 4 eps [ (sigma/r)^12 - (sigma/r)^6 ]
+ *   F_i  = sum_j (24 eps / r^2) [ 2 (sigma/r)^12 - (sigma/r)^6 ] (x_i - x_j)_mi
+ *   E_i  = 1/2 sum_j U(r_ij)          (so that sum_i E_i is the total energy
+ *                                      when every cut-off is the same)
+ *
+ * f_abs (may be NULL) receives, per component, the sum of the terms'
+ * magnitudes: the scale against which the signed force is compared.
+ */
+void or_lj(const or_grid *G, double eps, double sigma, const int64_t *recv, int64_t nrecv,
+           double *force, double *energy, double *f_abs)
+{
+    int64_t nr = recv ? nrecv : G->n;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t q = 0; q < nr; ++q) {
+        int64_t i = recv ? recv[q] : q;
+        double H = OR_GAMMA * G->h[i];
+        double f[3] = {0, 0, 0}, fa[3] = {0, 0, 0}, e = 0.0;
+        FOR_STENCIL(G, i, {
+            if (j != i) {
+                double d[3];
+                min_image(G, i, j, d);      /* d = x_j - x_i */
+                double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if (sqrt(r2) < H) {
+                    double s2 = sigma * sigma / r2, s6 = s2 * s2 * s2, s12 = s6 * s6;
+                    double c = 24.0 * eps / r2 * (2.0 * s12 - s6);
+                    for (int a = 0; a < 3; ++a) {
+                        f[a] -= c * d[a];
+                        fa[a] += fabs(c * d[a]);
+                    }
+                    e += 2.0 * eps * (s12 - s6);
+                }
+            }
+        });
+        for (int a = 0; a < 3; ++a) {
+            force[3 * q + a] = f[a];
+            if (f_abs) f_abs[3 * q + a] = fa[a];
+        }
+        energy[q] = e;
+    }
+}
+
+/* Total energy sum_i E_i with particle k's coordinate `comp` (0..2) moved by
+ * delta, in fp64: for force = -dE/dx checks by central differences.  Every
+ * receiver is re-evaluated (small sets only). */
+double or_lj_energy_moved(const or_grid *G, double eps, double sigma, int64_t k, int comp,
+                          double delta)
+{
+    double tot = 0.0;
+#pragma omp parallel for reduction(+ : tot) schedule(dynamic, 64)
+    for (int64_t i = 0; i < G->n; ++i) {
+        double H = OR_GAMMA * G->h[i];
+        double xi[3] = {G->x[3 * i], G->x[3 * i + 1], G->x[3 * i + 2]};
+        if (i == k) xi[comp] += delta;
+        double e = 0.0;
+        for (int64_t j = 0; j < G->n; ++j) {
+            if (j == i) continue;
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double t = G->x[3 * j + a] + ((j == k && a == comp) ? delta : 0.0) - xi[a];
+                t -= G->L[a] * nearbyint(t / G->L[a]);
+                r2 += t * t;
+            }
+            if (sqrt(r2) < H) {
+                double s2 = sigma * sigma / r2, s6 = s2 * s2 * s2;
+                e += 2.0 * eps * (s6 * s6 - s6);
+            }
+        }
+        tot += e;
+    }
+    return tot;
+}

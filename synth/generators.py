@@ -26,7 +26,7 @@ from scipy.spatial import cKDTree
 __all__ = [
     "GAMMA", "GUARD", "ParticleSet", "h_for_neighbours", "finest_grid",
     "guard_violations", "uniform_set", "lattice_set", "plummer_set",
-    "adjoint_set", "drift_set", "batched_sets", "batched_sizes", "BatchedSet", "batched_workload",
+    "adjoint_set", "drift_set", "lj_set", "batched_sets", "batched_sizes", "BatchedSet", "batched_workload",
     "workload", "WORKLOADS",
 ]
 
@@ -249,6 +249,34 @@ def adjoint_set(n: int, seed: int, jitter: float = 0.2, L: float = 1.0) -> Parti
     pert = _wrap32(s.pos.astype(np.float64) + rng.normal(0.0, sig, (n, 3)), L)
     s.extra["pos_target"] = pert
     return s
+
+
+def lj_set(M: int, seed: int, jitter: float = 0.2, rc_over_a: float = 2.5,
+           L: float = 1.0) -> ParticleSet:
+    """Molecular-dynamics-like set: a simple cubic lattice of M^3 sites (spacing
+    a = L / M) with every particle displaced uniformly in [-jitter a, jitter a]^3,
+    so no two particles come closer than (1 - 2 jitter) a; one cut-off
+    r_c = rc_over_a * a for all (h = r_c / GAMMA); m = 1/N.  Particles that break
+    the guard band get their displacement re-drawn from a sub-seeded stream."""
+    a = L / M
+    g = np.arange(M, dtype=np.float64) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    sites = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    n = sites.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pos = _wrap32(sites + rng.uniform(-jitter * a, jitter * a, (n, 3)), L)
+    h = np.full(n, rc_over_a * a / GAMMA, dtype=np.float32)
+    for it in range(1, 64):
+        bad = guard_violations(pos, h, L)
+        if bad.size == 0:
+            break
+        r2 = np.random.Generator(np.random.PCG64([seed, 0xBB67AE85, it]))
+        pos[bad] = _wrap32(sites[bad] + r2.uniform(-jitter * a, jitter * a, (bad.size, 3)), L)
+    else:
+        raise RuntimeError("guard band: lattice jitter re-draw did not converge")
+    m = np.full(n, 1.0 / n, dtype=np.float32)
+    return ParticleSet(pos, h, m, (L, L, L), seed, f"lj-{M}", None,
+                       {"sigma": a, "rc": rc_over_a * a})
 
 
 def drift_set(n: int, seed: int, steps: int, dmax: float, L: float = 1.0) -> ParticleSet:

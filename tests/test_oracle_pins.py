@@ -16,7 +16,7 @@ from scipy import integrate
 from oracle import Oracle, kernel_w, ORACLE_GAMMA
 from oracle.allpairs import density_allpairs
 from oracle.census import face_pair_fractions, pair_census
-from synth import uniform_set, lattice_set, GAMMA, h_for_neighbours
+from synth import uniform_set, lattice_set, lj_set, GAMMA, h_for_neighbours
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -314,3 +314,53 @@ def test_solve_h_satisfies_relation_and_neighbour_number():
     assert np.max(np.abs(4.0 * math.pi / 3.0 * H ** 3 * o["wcount"] - 48.0)) < 1e-9
     with pytest.raises(ValueError):
         solve_h_fp64(s.pos, s.m, 0.4 * h0, 0.5 * h0, eta)     # no root in the bracket
+
+
+# -------------------------------------------------------------- Lennard-Jones
+def test_lj_pair_minimum():
+    """Two particles at the textbook minimum r = 2^(1/6) sigma: zero force and a
+    pair energy of -eps (each particle holds half)."""
+    sigma, eps = 0.05, 1.7
+    r = 2.0 ** (1.0 / 6.0) * sigma
+    pos = np.array([[0.4, 0.5, 0.5], [0.4 + r, 0.5, 0.5]])
+    h = np.full(2, 0.2 / ORACLE_GAMMA)
+    o = Oracle(pos, h, np.ones(2)).lj(eps, sigma)
+    assert np.max(np.abs(o["force"])) < 1e-12 * eps / sigma       # the natural force scale
+    assert np.allclose(o["energy"], -0.5 * eps, rtol=1e-13)
+    # and off the minimum the pair is pushed apart / pulled together
+    for dr, sign in ((-0.1 * sigma, -1.0), (0.1 * sigma, 1.0)):
+        p2 = pos.copy()
+        p2[1, 0] += dr
+        f = Oracle(p2, h, np.ones(2)).lj(eps, sigma)["force"]
+        assert np.sign(f[0, 0]) == sign and f[1, 0] == -f[0, 0]
+
+
+def test_lj_lattice_shell_sum():
+    """Perfect simple cubic lattice: every force vanishes by symmetry and each
+    particle's energy is half the shell sum of U(a sqrt(s)) over the textbook
+    shell populations inside the cut-off."""
+    shells = {int(k): int(v[0]) for k, v in _golden("lattice_shells.txt").items()}
+    M, a = 8, 1.0 / 8
+    s = lj_set(M, 1, jitter=0.0, rc_over_a=2.2)
+    sigma, eps = a, 1.0
+    o = Oracle(s.pos, s.h, s.m).lj(eps, sigma)
+    assert np.max(np.abs(o["force"])) < 1e-12 * np.max(o["f_abs"])
+    rc = ORACLE_GAMMA * float(s.h[0])
+    U = lambda r: 4.0 * eps * ((sigma / r) ** 12 - (sigma / r) ** 6)
+    e = 0.5 * sum(c * U(a * math.sqrt(q)) for q, c in shells.items() if a * math.sqrt(q) < rc)
+    assert np.allclose(o["energy"], e, rtol=1e-12)
+
+
+def test_lj_force_is_minus_energy_gradient():
+    """Jittered lattice: the force on a particle equals minus the fp64 central
+    difference of the total energy, and the forces sum to zero."""
+    s = lj_set(8, 2, jitter=0.2, rc_over_a=2.2)
+    sigma, eps = 1.0 / 8, 1.0
+    o = Oracle(s.pos, s.h, s.m)
+    f = o.lj(eps, sigma)
+    assert np.all(np.abs(f["force"].sum(0)) < 1e-10 * f["f_abs"].sum(0))
+    d = 1e-6
+    for k in (0, 17, 300, 511):
+        for c in range(3):
+            fd = -(o.lj_energy_moved(eps, sigma, k, c, d) - o.lj_energy_moved(eps, sigma, k, c, -d)) / (2 * d)
+            assert abs(fd - f["force"][k, c]) < 1e-6 * f["f_abs"][k, c] + 1e-9, (k, c)
