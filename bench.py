@@ -190,6 +190,7 @@ def main():
     hsolve = _bench_hsolve(ctx, s, pos, m, torch)
     reuse = _bench_reuse(a, ctx, s, pos, h, m, grid, out_s, torch)
     reuse["speedup_vs_rebuild"] = ms_sorted / reuse["ms_per_step"]
+    lj = _bench_lj(a, ctx, torch)
 
     n = s.n
     value = pairs / (ms_sorted * 1e-3)
@@ -232,6 +233,7 @@ def main():
         "autotune": tuning,
         "h_iteration": hsolve,
         "verlet_reuse": reuse,
+        "lennard_jones": lj,
         "wall_ms_per_step": wall_sorted,
         "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
@@ -395,6 +397,39 @@ def _bench_reuse(a, ctx, s, pos, h, m, grid, out, torch):
     del graph
     return {"ms_per_step": ms, "eager_ms_per_step": ms_eager, "displacement_per_step": dx,
             "step": "drift + sorted-pair density on kept cells and sorted lists"}
+
+
+def _bench_lj(a, ctx, torch):
+    """Second workload through the same sweep: Lennard-Jones forces and energies
+    on 10^6 particles (jittered 100^3 lattice, cut-off 2.5 spacings); a step is
+    build_cells + sort_cells + the force sweep, timed as a HIP graph."""
+    from synth import workload
+    s = workload("lj-1m")
+    dev = torch.device("cuda", 0)
+    pos, h, m = (torch.from_numpy(x).to(dev) for x in (s.pos, s.h, s.m))
+    cells = ctx.build_cells(pos, h, m, s.box)
+    grid = cells.info()["grid"]
+    ctx.sort_cells(cells)
+    _, _, _, nc = ctx.density(cells, "sorted")
+    pairs = int(nc.sum().item())
+    f = torch.empty((s.n, 3), device=dev)
+    e = torch.empty(s.n, device=dev)
+    sigma, eps = s.extra["sigma"], 1.0
+
+    def step():
+        ctx.build_cells(pos, h, m, s.box, grid, cells)
+        ctx.sort_cells(cells)
+        ctx.lj(cells, eps, sigma, (f, e))
+
+    graph = _capture(step, torch)
+    ms, _ = _time_loop(graph.replay, a.steps, a.warmup, torch)
+    ms_sweep, _ = _time_loop(lambda: ctx.lj(cells, eps, sigma, (f, e)), a.steps, 1, torch)
+    ctx.check()
+    del graph
+    return {"workload": s.name, "n": s.n, "grid": list(grid), "pairs_in_range": pairs,
+            "ms_per_step": ms, "pair_interactions_per_s": pairs / (ms * 1e-3),
+            "force_sweep_ms": ms_sweep,
+            "step": "build_cells + sort_cells + Lennard-Jones sweep, one HIP graph launch"}
 
 
 def _bench_hsolve(ctx, s, pos, m, torch):

@@ -216,6 +216,18 @@ typedef enum { PV_TUNE_DENSITY = 0, PV_TUNE_ADJOINT = 1, PV_TUNE_PLAIN = 2 } pv_
 pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const float *grad_rho,
                       int reps, float times_ms[2]);
 
+/* Lennard-Jones forces and energies over the same neighbour sets (the
+ * method serves molecular dynamics as well as SPH): for every pair with
+ * r_ij < H_i (the receiver's cut-off; build the cells with h = r_c / gamma for
+ * one cut-off r_c),
+ *   force_i  = sum_j (24 eps / r^2) [2 (sigma/r)^12 - (sigma/r)^6] (x_i - x_j)
+ *   energy_i = 1/2 sum_j 4 eps [(sigma/r)^12 - (sigma/r)^6]   (unshifted)
+ * force: device n x 3, energy: device n, input order; either may be NULL.
+ * Sorted-pair sweep with the density's tuning parameters; coincident
+ * particles are skipped.  Requires pv_sort_cells. */
+pv_status pv_lj(pv_ctx *ctx, const pv_cells *cells, float eps, float sigma, float *force,
+                float *energy);
+
 /* Move the particles of sorted cells without rebuilding them (Section 2: the
  * sorted lists can be reused over several time steps when every projected
  * bound is widened by the particles' displacement).  disp: device, n x 3, input

@@ -53,7 +53,7 @@ def _load():
     lib.or_fd_loss_many.argtypes = [P, P, P, P, P, i64, P]
     lib.or_solve_h.argtypes = [P, C.c_double, P, P]
     lib.or_solve_h.restype = i64
-    lib.or_lj.argtypes = [P, C.c_double, C.c_double, P, i64, P, P, P]
+    lib.or_lj.argtypes = [P, C.c_double, C.c_double, P, i64, P, P, P, P]
     lib.or_lj.restype = None
     lib.or_lj_energy_moved.argtypes = [P, C.c_double, C.c_double, i64, C.c_int, C.c_double]
     lib.or_lj_energy_moved.restype = C.c_double
@@ -134,16 +134,17 @@ class Oracle:
         return out
 
     def lj(self, eps, sigma, recv=None):
-        """Lennard-Jones force (k, 3), energy (k,) and |term| sums (k, 3) over
-        pairs within each receiver's cut-off."""
+        """Lennard-Jones force (k, 3), energy (k,) and the |term| sums f_abs
+        (k, 3) and e_abs (k,) over pairs within each receiver's cut-off."""
         if recv is None:
             k, r = self.n, None
         else:
             r = np.ascontiguousarray(np.asarray(recv, dtype=np.int64))
             k = r.size
-        out = {"force": np.zeros((k, 3)), "energy": np.zeros(k), "f_abs": np.zeros((k, 3))}
+        out = {"force": np.zeros((k, 3)), "energy": np.zeros(k), "f_abs": np.zeros((k, 3)),
+               "e_abs": np.zeros(k)}
         self.lib.or_lj(self.handle, float(eps), float(sigma), _ptr(r), k, _ptr(out["force"]),
-                       _ptr(out["energy"]), _ptr(out["f_abs"]))
+                       _ptr(out["energy"]), _ptr(out["f_abs"]), _ptr(out["e_abs"]))
         return out
 
     def lj_energy_moved(self, eps, sigma, k, comp, delta):

@@ -415,18 +415,19 @@ int64_t or_solve_h(const or_grid *G, double eta, const double *h_lo, double *h_o
  *   E_i  = 1/2 sum_j U(r_ij)          (so that sum_i E_i is the total energy
  *                                      when every cut-off is the same)
  *
- * f_abs (may be NULL) receives, per component, the sum of the terms'
- * magnitudes: the scale against which the signed force is compared.
+ * f_abs and e_abs (may be NULL) receive the sums of the terms' magnitudes per
+ * force component and for the energy: the scales against which the signed
+ * sums are compared.
  */
 void or_lj(const or_grid *G, double eps, double sigma, const int64_t *recv, int64_t nrecv,
-           double *force, double *energy, double *f_abs)
+           double *force, double *energy, double *f_abs, double *e_abs)
 {
     int64_t nr = recv ? nrecv : G->n;
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t q = 0; q < nr; ++q) {
         int64_t i = recv ? recv[q] : q;
         double H = OR_GAMMA * G->h[i];
-        double f[3] = {0, 0, 0}, fa[3] = {0, 0, 0}, e = 0.0;
+        double f[3] = {0, 0, 0}, fa[3] = {0, 0, 0}, e = 0.0, ea = 0.0;
         FOR_STENCIL(G, i, {
             if (j != i) {
                 double d[3];
@@ -440,6 +441,7 @@ void or_lj(const or_grid *G, double eps, double sigma, const int64_t *recv, int6
                         fa[a] += fabs(c * d[a]);
                     }
                     e += 2.0 * eps * (s12 - s6);
+                    ea += fabs(2.0 * eps * (s12 - s6));
                 }
             }
         });
@@ -448,6 +450,7 @@ void or_lj(const or_grid *G, double eps, double sigma, const int64_t *recv, int6
             if (f_abs) f_abs[3 * q + a] = fa[a];
         }
         energy[q] = e;
+        if (e_abs) e_abs[q] = ea;
     }
 }
 

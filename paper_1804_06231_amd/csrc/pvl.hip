@@ -635,6 +635,19 @@ pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const floa
     return PV_OK;
 }
 
+pv_status pv_lj(pv_ctx *ctx, const pv_cells *cells, float eps, float sigma, float *force,
+                float *energy)
+{
+    if (!ctx) return PV_EINVAL;
+    if (!cells) return fail(ctx, PV_EINVAL, "cells is NULL");
+    if (!(eps > 0.0f) || !(sigma > 0.0f)) return fail(ctx, PV_EINVAL, "eps and sigma must be > 0");
+    if (!cells->sorted) return fail(ctx, PV_ESTATE, "pv_sort_cells must run before pv_lj");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    HIPCHK(ctx, pvl::launch_lj_tiled(ctx->stream, cells->d, cells->n, cells->ncell, eps, sigma,
+                                     force, energy, ctx->dflags, ctx->tune));
+    return PV_OK;
+}
+
 pv_status pv_drift(pv_ctx *ctx, pv_cells *cells, const float *disp)
 {
     if (!ctx) return PV_EINVAL;

@@ -134,6 +134,9 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
                               int *dflags, const SweepTuning &tune, bool plain);
+hipError_t launch_lj_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                           float eps, float sigma, float *force, float *energy, int *dflags,
+                           const SweepTuning &tune);
 hipError_t launch_backward_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                                  float *grad_pos, float *grad_h, int *dflags,
                                  const SweepTuning &tune);

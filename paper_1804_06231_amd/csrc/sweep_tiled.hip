@@ -48,7 +48,11 @@
 //     (G = dL/drho, W_r = dW/dr), so every output has one writer.  A pair
 //     counts when r < max(H_k, H_j): the bounds use max(H_k, largest cut-off
 //     of the source cell) in place of H_k, which keeps every pair that the
-//     source's own cut-off decides.
+//     source's own cut-off decides;
+//   * kModeLJ: Lennard-Jones forces and energies over the same pairs (the
+//     method serves molecular dynamics as well as SPH):
+//       F_i = sum_j (24 eps / r^2) [2 (sigma/r)^12 - (sigma/r)^6] (x_i - x_j),
+//       E_i = 1/2 sum_j 4 eps [(sigma/r)^12 - (sigma/r)^6]   over r < H_i.
 #include "device_util.h"
 
 namespace pvl {
@@ -56,6 +60,7 @@ namespace pvl {
 constexpr int kModeSorted = 0;
 constexpr int kModePlain = 1;
 constexpr int kModeAdjoint = 2;
+constexpr int kModeLJ = 3;
 
 constexpr int kChunk = 256;                    // largest receivers per work item
 constexpr int kChunkMin = 32;                  // smallest (sizes the queue)
@@ -144,6 +149,31 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
             grad_interact(dx, dy, dz, r2, mj, ij, cj, hj2, H2, invH, ck, mi, acc); \
     }
 
+// Lennard-Jones pair term (d = x_j - x_i, 0 < r2 < H_i^2).
+__device__ __forceinline__ void lj_interact(float dx, float dy, float dz, float r2, float sig2,
+                                            float eps, TileAcc &a)
+{
+    float inv = __builtin_amdgcn_rcpf(r2);   // v_rcp_f32, 1 ulp
+    float s2 = sig2 * inv;
+    float s6 = s2 * s2 * s2;
+    float s12 = s6 * s6;
+    float c = (24.0f * eps) * inv * fmaf(2.0f, s12, -s6);
+    // F_i += c (x_i - x_j) = -c d
+    a.rho = fmaf(-c, dx, a.rho);
+    a.wc = fmaf(-c, dy, a.wc);
+    a.dh = fmaf(-c, dz, a.dh);
+    a.cnt = fmaf(2.0f * eps, s12 - s6, a.cnt);
+}
+
+#define PVL_LJ_STEP(K)                                                    \
+    {                                                                     \
+        float dx = ror16<K>(sx) - tx;                                     \
+        float dy = ror16<K>(sy) - ty;                                     \
+        float dz = ror16<K>(sz) - tz;                                     \
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                   \
+        if (r2 < H2 && r2 > 0.0f) lj_interact(dx, dy, dz, r2, sig2, eps, acc); \
+    }
+
 #define PVL_TILE_STEP(K)                                                  \
     {                                                                     \
         float dx = ror16<K>(sx) - tx;                                     \
@@ -184,6 +214,8 @@ struct SweepArgs {
     int32_t *ncount;
     const float *gcell;          // adjoint: upstream gradient in cell order
     float *grad_pos, *grad_h;    // adjoint outputs (input order)
+    float lj_eps, lj_sigma2;     // Lennard-Jones parameters
+    float *force, *energy;       // Lennard-Jones outputs (input order)
     int *dflags;
     const float *cell_dx;        // accumulated displacement bound per cell (pv_drift)
     const uint32_t *dx_all;      // its largest value (fp32 bits)
@@ -215,6 +247,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
 {
     constexpr bool PLAIN = MODE == kModePlain;
     constexpr bool ADJ = MODE == kModeAdjoint;
+    constexpr bool LJ = MODE == kModeLJ;
     const int64_t n = A.n;
     const int sa = A.start[a];
     const int na = A.start[a + 1] - sa;
@@ -614,6 +647,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             res = make_float4(acc.gx, acc.gy, acc.gz, acc.dh);
         } else {
             TileAcc acc = {0.f, 0.f, 0.f, 0.f};
+            const float sig2 = A.lj_sigma2, eps = A.lj_eps;
             auto load_src = [&](int p) {
                 return p >= 0 ? A.xyzm[sb + p] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
             };
@@ -627,11 +661,19 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
                 pn = src_of(it + 2);
                 const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
                 if (it < nt) {
-                    if (tile != diag) PVL_TILE_STEP(0)
-                    PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
-                    PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
-                    PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
-                    PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
+                    if constexpr (LJ) {
+                        if (tile != diag) PVL_LJ_STEP(0)
+                        PVL_LJ_STEP(1) PVL_LJ_STEP(2) PVL_LJ_STEP(3) PVL_LJ_STEP(4)
+                        PVL_LJ_STEP(5) PVL_LJ_STEP(6) PVL_LJ_STEP(7) PVL_LJ_STEP(8)
+                        PVL_LJ_STEP(9) PVL_LJ_STEP(10) PVL_LJ_STEP(11) PVL_LJ_STEP(12)
+                        PVL_LJ_STEP(13) PVL_LJ_STEP(14) PVL_LJ_STEP(15)
+                    } else {
+                        if (tile != diag) PVL_TILE_STEP(0)
+                        PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
+                        PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
+                        PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
+                        PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
+                    }
                 }
             }
             res = make_float4(acc.rho, acc.wc, acc.dh, acc.cnt);
@@ -666,6 +708,16 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
                 A.grad_pos[3 * (int64_t)o + 2] = sd;
             }
             if (A.grad_h) A.grad_h[o] = A.gcell[p] * (-norm * (kGamma * invH) * (sc + 3.0f * mi));
+            continue;
+        }
+        if constexpr (LJ) {
+            // (sr, sw, sd) is the force, sc the energy
+            if (A.force) {
+                A.force[3 * (int64_t)o + 0] = sr;
+                A.force[3 * (int64_t)o + 1] = sw;
+                A.force[3 * (int64_t)o + 2] = sd;
+            }
+            if (A.energy) A.energy[o] = sc;
             continue;
         }
         if (A.rho) A.rho[o] = norm * (sr + mi);                          // self: w(0) = 1
@@ -753,6 +805,8 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
         hipLaunchKernelGGL(k_sweep_queue<kModePlain>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     else if (mode == kModeAdjoint)
         hipLaunchKernelGGL(k_sweep_queue<kModeAdjoint>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    else if (mode == kModeLJ)
+        hipLaunchKernelGGL(k_sweep_queue<kModeLJ>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     else
         hipLaunchKernelGGL(k_sweep_queue<kModeSorted>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     return hipGetLastError();
@@ -769,6 +823,19 @@ hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int6
     A.ncount = ncount;
     A.dflags = dflags;
     return launch_queue_sweep(st, c, n, ncell, A, tune, plain ? kModePlain : kModeSorted);
+}
+
+hipError_t launch_lj_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
+                           float eps, float sigma, float *force, float *energy, int *dflags,
+                           const SweepTuning &tune)
+{
+    SweepArgs A = {};
+    A.lj_eps = eps;
+    A.lj_sigma2 = sigma * sigma;
+    A.force = force;
+    A.energy = energy;
+    A.dflags = dflags;
+    return launch_queue_sweep(st, c, n, ncell, A, tune, kModeLJ);
 }
 
 hipError_t launch_backward_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,

@@ -28,6 +28,7 @@ EXPORTS = (
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
     "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h", "pv_drift",
+    "pv_lj",
 )
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4}
 PV_PARAM_ADJOINT = 16
@@ -81,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "pv_autotune": ([P, P, i32, P, i32, P], i32),
         "pv_solve_h": ([P, i32, P, P, P, P, P, C.c_float, C.c_float, i32, P, P], i32),
         "pv_drift": ([P, P, P], i32),
+        "pv_lj": ([P, P, C.c_float, C.c_float, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -252,6 +254,19 @@ class Context:
         self._sync_stream()
         self._call("pv_density", cells.handle, ALGOS[algo], _ptr(rho), _ptr(wc), _ptr(dh), _ptr(nc))
         return rho, wc, dh, nc
+
+    def lj(self, cells: Cells, eps: float, sigma: float, out=None):
+        """Lennard-Jones (force (n, 3), energy (n,)) over each particle's
+        cut-off (pv_lj)."""
+        n = cells.n
+        if out is None:
+            f = torch.empty((n, 3), dtype=torch.float32, device=self.device)
+            e = torch.empty(n, dtype=torch.float32, device=self.device)
+        else:
+            f, e = out
+        self._sync_stream()
+        self._call("pv_lj", cells.handle, float(eps), float(sigma), _ptr(f), _ptr(e))
+        return f, e
 
     def drift(self, cells: Cells, disp) -> None:
         """Move the cells' particles by disp (n x 3, input order) keeping the

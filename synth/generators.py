@@ -424,6 +424,9 @@ WORKLOADS = {
     "clustered-4m": dict(kind="plummer", n=1 << 22, seed=3),
     # 2^20 uniform particles, h jittered +-20%, with a perturbed copy for the target.
     "adjoint-1m": dict(kind="adjoint", n=1 << 20, seed=4),
+    # 10^6 particles on a jittered 100^3 lattice, one cut-off 2.5 lattice spacings
+    # (a molecular-dynamics shape for the Lennard-Jones forces).
+    "lj-1m": dict(kind="lj", M=100, seed=77, rc=2.5),
     # 256 unit boxes of 4096 .. 262144 particles (log-uniform), alternately uniform
     # with lognormal h and Plummer-clustered, ~15.4M particles in all.
     "batched-256": dict(kind="batched", nbox=256, seed=5),
@@ -444,4 +447,6 @@ def workload(name: str, progress=None, **over):
         return plummer_set(spec["n"], spec["seed"], name=name)
     if kind == "adjoint":
         return adjoint_set(spec["n"], spec["seed"])
+    if kind == "lj":
+        return lj_set(spec["M"], spec["seed"], rc_over_a=spec["rc"])
     raise ValueError(kind)
