@@ -47,6 +47,9 @@ def _args():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform-1m-lognormal")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--core", action="store_true",
+                    help="skip the h-iteration, list-reuse and Lennard-Jones sections (their "
+                         "density launches would mix into a profile of the sweep)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default sweep parameters instead of the autotuned ones")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -187,10 +190,13 @@ def main():
     out_g = (torch.empty((s.n, 3), device=dev), torch.empty(s.n, device=dev))
     ms_adj, _ = _time_loop(lambda: ctx.density_backward(cells, g_rho, out_g), a.steps, 1, torch)
     ctx.check()
-    hsolve = _bench_hsolve(ctx, s, pos, m, torch)
-    reuse = _bench_reuse(a, ctx, s, pos, h, m, grid, out_s, torch)
-    reuse["speedup_vs_rebuild"] = ms_sorted / reuse["ms_per_step"]
-    lj = _bench_lj(a, ctx, torch)
+    hsolve = reuse = lj = None
+    if not a.core:
+        print("[bench] h-iteration, list reuse, Lennard-Jones", file=sys.stderr, flush=True)
+        hsolve = _bench_hsolve(ctx, s, pos, m, torch)
+        reuse = _bench_reuse(a, ctx, s, pos, h, m, grid, out_s, torch)
+        reuse["speedup_vs_rebuild"] = ms_sorted / reuse["ms_per_step"]
+        lj = _bench_lj(a, ctx, torch)
 
     n = s.n
     value = pairs / (ms_sorted * 1e-3)
