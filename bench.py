@@ -134,7 +134,15 @@ def main():
 
     # grid: the workload's own, else the finest legal one (found once, then the
     # cell structure is rebuilt in place every step with that grid)
-    cells = ctx.build_cells(pos, h, m, s.box, s.grid)
+    # grid: the workload's own, else the autotuner's (the finest legal one
+    # with --no-autotune); the cell structure is rebuilt in place every step
+    grid_tune = None
+    grid = s.grid
+    if grid is None and not a.no_autotune:
+        print("[bench] autotuning the grid", file=sys.stderr, flush=True)
+        (grid,), t_fine, t_best = ctx.autotune_grid(pos, h, m, s.box, reps=3)
+        grid_tune = {"grid": list(grid), "finest_step_ms": t_fine, "tuned_step_ms": t_best}
+    cells = ctx.build_cells(pos, h, m, s.box, grid)
     grid = cells.info()["grid"]
     ctx.sort_cells(cells)
     out_s = ctx.density(cells, "sorted")
@@ -237,6 +245,7 @@ def main():
         "candidates_per_particle": {"sorted": cand_sorted / n, "plain": cand_plain / n,
                                     "in_range": inr / n},
         "autotune": tuning,
+        "grid_autotune": grid_tune,
         "h_iteration": hsolve,
         "verlet_reuse": reuse,
         "lennard_jones": lj,
@@ -272,7 +281,14 @@ def bench_batched(a, b, torch, pvl, t0):
     nc = torch.empty(n, dtype=torch.int32, device=dev)
     gp, gh = torch.empty((n, 3), device=dev), torch.empty(n, device=dev)
 
-    cells = ctx.build_cells_batched(off, pos, h, m, b.boxes, b.grids)
+    grids = b.grids
+    grid_tune = None
+    if not a.no_autotune:
+        print("[bench] autotuning the grids", file=sys.stderr, flush=True)
+        grids, t_fine, t_best = ctx.autotune_grid(pos, h, m, reps=2, offsets=off, boxes=b.boxes)
+        grid_tune = {"finest_step_ms": t_fine, "tuned_step_ms": t_best,
+                     "grids_per_side": [min(g[0] for g in grids), max(g[0] for g in grids)]}
+    cells = ctx.build_cells_batched(off, pos, h, m, b.boxes, grids)
     ctx.sort_cells(cells)
     ctx.density(cells, "sorted", (rho, wc, dh, nc))
     ctx.check()
@@ -284,7 +300,7 @@ def bench_batched(a, b, torch, pvl, t0):
     tuning = _autotune(a, ctx, cells, g_rho, ("density", "adjoint"))
 
     def step():
-        ctx.build_cells_batched(off, pos, h, m, b.boxes, b.grids, cells)
+        ctx.build_cells_batched(off, pos, h, m, b.boxes, grids, cells)
         ctx.sort_cells(cells)
         ctx.density(cells, "sorted", (rho, wc, dh, nc))
         ctx.density_backward(cells, g_rho, (gp, gh))
@@ -293,12 +309,12 @@ def bench_batched(a, b, torch, pvl, t0):
     boxes = []
     for k in range(b.nbox):
         sl = slice(off[k], off[k + 1])
-        c = ctx.build_cells(pos[sl], h[sl], m[sl], b.boxes[k], b.grids[k])
+        c = ctx.build_cells(pos[sl], h[sl], m[sl], b.boxes[k], grids[k])
         boxes.append((c, sl))
 
     def step_loop():
         for k, (c, sl) in enumerate(boxes):
-            ctx.build_cells(pos[sl], h[sl], m[sl], b.boxes[k], b.grids[k], c)
+            ctx.build_cells(pos[sl], h[sl], m[sl], b.boxes[k], grids[k], c)
             ctx.sort_cells(c)
             ctx.density(c, "sorted", (rho[sl], wc[sl], dh[sl], nc[sl]))
             ctx.density_backward(c, g_rho[sl], (gp[sl], gh[sl]))
@@ -321,7 +337,7 @@ def bench_batched(a, b, torch, pvl, t0):
     ms_loop, _ = _time_loop(step_loop, max(1, a.steps // 4), 1, torch)
     ctx.check()
     # stage times of the batched structure
-    ms_build, _ = _time_loop(lambda: ctx.build_cells_batched(off, pos, h, m, b.boxes, b.grids, cells),
+    ms_build, _ = _time_loop(lambda: ctx.build_cells_batched(off, pos, h, m, b.boxes, grids, cells),
                              a.steps, 1, torch)
     ms_sort, _ = _time_loop(lambda: ctx.sort_cells(cells), a.steps, 1, torch)
     ms_sweep, _ = _time_loop(lambda: ctx.density(cells, "sorted", (rho, wc, dh, nc)), a.steps, 1, torch)
@@ -351,7 +367,8 @@ def bench_batched(a, b, torch, pvl, t0):
         "config": {"workload": b.name, "n": n, "nbox": b.nbox, "seed": b.seed,
                    "particles_per_box": [min(np.diff(b.offsets).tolist()),
                                          max(np.diff(b.offsets).tolist())],
-                   "grids_per_side": [min(b.grids), max(b.grids)],
+                   "grids_per_side": [min(g[0] for g in grids) if grid_tune else min(b.grids),
+                                      max(g[0] for g in grids) if grid_tune else max(b.grids)],
                    "step": "build_cells + sort_cells + density + adjoint over all boxes, "
                            "one HIP graph launch"},
         "ns_per_particle": ms_graph * 1e6 / n,
@@ -363,6 +380,7 @@ def bench_batched(a, b, torch, pvl, t0):
                       "adjoint_sweep": ms_adj},
         "candidates_per_particle": {"sorted": cand / n, "in_range": inr / n},
         "autotune": tuning,
+        "grid_autotune": grid_tune,
         "wall_ms_per_step": wall_graph,
         "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
@@ -413,7 +431,12 @@ def _bench_lj(a, ctx, torch):
     s = workload("lj-1m")
     dev = torch.device("cuda", 0)
     pos, h, m = (torch.from_numpy(x).to(dev) for x in (s.pos, s.h, s.m))
-    cells = ctx.build_cells(pos, h, m, s.box)
+    grid_tune = None
+    grid = None
+    if not a.no_autotune:
+        (grid,), t_fine, t_best = ctx.autotune_grid(pos, h, m, s.box, reps=3)
+        grid_tune = {"finest_step_ms": t_fine, "tuned_step_ms": t_best}
+    cells = ctx.build_cells(pos, h, m, s.box, grid)
     grid = cells.info()["grid"]
     ctx.sort_cells(cells)
     _, _, _, nc = ctx.density(cells, "sorted")
@@ -434,7 +457,7 @@ def _bench_lj(a, ctx, torch):
     del graph
     return {"workload": s.name, "n": s.n, "grid": list(grid), "pairs_in_range": pairs,
             "ms_per_step": ms, "pair_interactions_per_s": pairs / (ms * 1e-3),
-            "force_sweep_ms": ms_sweep,
+            "force_sweep_ms": ms_sweep, "grid_autotune": grid_tune,
             "step": "build_cells + sort_cells + Lennard-Jones sweep, one HIP graph launch"}
 
 

@@ -216,6 +216,21 @@ typedef enum { PV_TUNE_DENSITY = 0, PV_TUNE_ADJOINT = 1, PV_TUNE_PLAIN = 2 } pv_
 pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const float *grad_rho,
                       int reps, float times_ms[2]);
 
+/* Grid autotuner.  The finest legal grid (floor(L / largest cut-off) per
+ * axis) minimises the cell volume but not always the time: with few particles
+ * per cell the 16-wide tiles run mostly empty.  Times a step (build with an
+ * explicit grid + sort + sorted-pair density, `reps` runs after one warm-up)
+ * for every box's finest grid scaled by 1, 0.85, 0.7, 0.6, 0.5, 0.42, 0.35 and
+ * 0.3 (at least 3 cells per axis), stopping at the first grid with a cell above
+ * PV_MAX_CELL or after two slower grids in a row, and writes the fastest to
+ * grid_out (host, 3 * nbox ints) for the caller's later builds.  Arguments as
+ * for pv_build_cells_batched.  times_ms (host, may be NULL): the step time at
+ * the finest grid and at the chosen one.  Allocates temporary device memory,
+ * synchronises, must not be captured. */
+pv_status pv_autotune_grid(pv_ctx *ctx, int nbox, const int64_t *offsets, const float *pos,
+                           const float *h, const float *mass, const double *box, int reps,
+                           int *grid_out, float times_ms[2]);
+
 /* Lennard-Jones forces and energies over the same neighbour sets (the
  * method serves molecular dynamics as well as SPH): for every pair with
  * r_ij < H_i (the receiver's cut-off; build the cells with h = r_c / gamma for

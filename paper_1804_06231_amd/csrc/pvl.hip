@@ -635,6 +635,93 @@ pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const floa
     return PV_OK;
 }
 
+pv_status pv_autotune_grid(pv_ctx *ctx, int nbox, const int64_t *offsets, const float *pos,
+                           const float *h, const float *mass, const double *box, int reps,
+                           int *grid_out, float times_ms[2])
+{
+    if (!ctx) return PV_EINVAL;
+    if (nbox < 1 || !offsets || !box || !grid_out)
+        return fail(ctx, PV_EINVAL, "nbox < 1 or a NULL host array");
+    if (reps < 1 || reps > 100) return fail(ctx, PV_EINVAL, "reps must be 1..100");
+    const int64_t n = offsets[nbox];
+    if (n > 0 && (!pos || !h || !mass)) return fail(ctx, PV_EINVAL, "NULL particle array");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    // the finest legal grid of every box (auto grid)
+    pv_cells *cells = nullptr;
+    pv_status st = pv_build_cells_batched(ctx, nbox, offsets, pos, h, mass, box, nullptr, &cells);
+    if (st != PV_OK && st != PV_EOVERFLOW) {
+        if (cells) pv_free_cells(ctx, cells);
+        return st;
+    }
+    std::vector<int> finest(3 * nbox);
+    for (int b = 0; b < nbox; ++b)
+        for (int a = 0; a < 3; ++a) finest[3 * b + a] = cells->hbox[b].g[a];
+    float *out = nullptr;
+    if (hipMalloc((void **)&out, sizeof(float) * 4 * (size_t)std::max<int64_t>(n, 1)) != hipSuccess) {
+        pv_free_cells(ctx, cells);
+        return fail(ctx, PV_ENOMEM, "autotune_grid: device allocation failed");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    // candidate grids: fractions of the finest grid (at least 3 cells per axis)
+    static const float fractions[] = {1.0f, 0.85f, 0.7f, 0.6f, 0.5f, 0.42f, 0.35f, 0.3f};
+    std::vector<int> g(3 * nbox), best;
+    float best_ms = INFINITY, finest_ms = INFINITY;
+    int worse = 0;
+    for (float f : fractions) {
+        for (int k = 0; k < 3 * nbox; ++k) g[k] = std::max(3, (int)floorf(f * (float)finest[k]));
+        if (!best.empty() && g == best) continue;
+        auto step = [&]() -> pv_status {
+            pv_status s2 = pv_build_cells_batched(ctx, nbox, offsets, pos, h, mass, box, g.data(),
+                                                  &cells);
+            if (s2 == PV_OK) s2 = pv_sort_cells(ctx, cells);
+            if (s2 == PV_OK)
+                s2 = pv_density(ctx, cells, PV_SORTED_PAIR, out, out + n, out + 2 * n,
+                                (int32_t *)(out + 3 * n));
+            return s2;
+        };
+        st = step();
+        if (st == PV_OK) st = pv_check(ctx);
+        if (st == PV_EOVERFLOW) {   // too coarse: a cell above the limit
+            st = PV_OK;
+            break;
+        }
+        if (st != PV_OK) break;
+        (void)hipEventRecord(e0, ctx->stream);
+        for (int r = 0; r < reps && st == PV_OK; ++r) st = step();
+        (void)hipEventRecord(e1, ctx->stream);
+        if (st == PV_OK) st = pv_check(ctx);
+        if (st != PV_OK) break;
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)reps;
+        if (f == 1.0f) finest_ms = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = g;
+            worse = 0;
+        } else if (++worse == 2) {
+            break;   // two coarser grids in a row were slower
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    pv_free_cells(ctx, cells);
+    if (st != PV_OK) return st;
+    if (best.empty())
+        return fail(ctx, PV_EOVERFLOW, "even the finest grid has a cell above the limit");
+    for (int k = 0; k < 3 * nbox; ++k) grid_out[k] = best[k];
+    if (times_ms) {
+        times_ms[0] = finest_ms;
+        times_ms[1] = best_ms;
+    }
+    ctx->err.clear();
+    return PV_OK;
+}
+
 pv_status pv_lj(pv_ctx *ctx, const pv_cells *cells, float eps, float sigma, float *force,
                 float *energy)
 {

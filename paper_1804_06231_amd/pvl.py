@@ -28,7 +28,7 @@ EXPORTS = (
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
     "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h", "pv_drift",
-    "pv_lj",
+    "pv_lj", "pv_autotune_grid",
 )
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4}
 PV_PARAM_ADJOINT = 16
@@ -83,6 +83,7 @@ def load_library(path: str = LIB_PATH):
         "pv_solve_h": ([P, i32, P, P, P, P, P, C.c_float, C.c_float, i32, P, P], i32),
         "pv_drift": ([P, P, P], i32),
         "pv_lj": ([P, P, C.c_float, C.c_float, P, P], i32),
+        "pv_autotune_grid": ([P, i32, P, P, P, P, P, i32, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -254,6 +255,31 @@ class Context:
         self._sync_stream()
         self._call("pv_density", cells.handle, ALGOS[algo], _ptr(rho), _ptr(wc), _ptr(dh), _ptr(nc))
         return rho, wc, dh, nc
+
+    def autotune_grid(self, pos, h, mass, box=(1.0, 1.0, 1.0), reps: int = 3, offsets=None,
+                      boxes=None):
+        """Fastest cells-per-axis for build + sort + density (pv_autotune_grid):
+        returns (grids, ms at the finest grid, ms at the chosen one); grids is
+        one (gx, gy, gz) per box."""
+        n = int(pos.shape[0])
+        _dev_f32(pos, n, 3, "pos", self.device)
+        _dev_f32(h, n, 0, "h", self.device)
+        _dev_f32(mass, n, 0, "mass", self.device)
+        if offsets is None:
+            offsets, boxes = [0, n], [box]
+        nbox = len(offsets) - 1
+        off = (C.c_int64 * (nbox + 1))(*[int(x) for x in offsets])
+        bx = []
+        for b in boxes:
+            bx.extend([float(b)] * 3 if isinstance(b, (int, float)) else [float(x) for x in b])
+        barr = (C.c_double * (3 * nbox))(*bx)
+        g = (C.c_int * (3 * nbox))()
+        t = (C.c_float * 2)()
+        self._sync_stream()
+        self._call("pv_autotune_grid", nbox, off, _ptr(pos), _ptr(h), _ptr(mass), barr,
+                   int(reps), g, t)
+        grids = [tuple(g[3 * b:3 * b + 3]) for b in range(nbox)]
+        return grids, float(t[0]), float(t[1])
 
     def lj(self, cells: Cells, eps: float, sigma: float, out=None):
         """Lennard-Jones (force (n, 3), energy (n,)) over each particle's

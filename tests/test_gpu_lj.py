@@ -59,3 +59,22 @@ def test_lj_1m_sampled(ctx):
     ref = oracle_for(s).lj(eps, sigma, idx)
     print("lj-1m: max err force/energy", _check(f, e, ref, idx, "lj-1m"), flush=True)
     assert np.all(np.abs(f.sum(0)) < 1e-5 * np.abs(f).sum(0))
+
+
+def test_grid_autotune(ctx):
+    """The grid autotuner returns a legal grid no finer than the finest, at least
+    as fast, and the results on it still match the oracle (any legal grid gives
+    the same pairs)."""
+    s = lj_set(40, 79, jitter=0.2, rc_over_a=2.5)
+    pos, h, m = upload(s)
+    (g,), t_finest, t_best = ctx.autotune_grid(pos, h, m, s.box, reps=2)
+    finest = int(1.0 / (float(h[0]) * 1.825742 * (1 + 4e-6)))
+    print(f"grid autotune: finest {finest}^3 {t_finest:.3f} ms -> {g} {t_best:.3f} ms", flush=True)
+    assert 3 <= g[0] <= finest and t_best <= t_finest
+    cells = ctx.build_cells(pos, h, m, s.box, g)
+    ctx.sort_cells(cells)
+    f, e = ctx.lj(cells, 1.0, s.extra["sigma"])
+    ctx.check()
+    ref = oracle_for(s).lj(1.0, s.extra["sigma"])
+    _check(f.cpu().numpy().astype(np.float64), e.cpu().numpy().astype(np.float64), ref,
+           label="tuned grid")
