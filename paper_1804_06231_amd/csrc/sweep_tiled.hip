@@ -68,6 +68,7 @@ constexpr int kMaxTasks = 27 * (kChunk / 16);  // task slots per item
 constexpr int kMaxRecv = 26 * kChunk;          // compacted receiver lists per item
 constexpr int kSelfAxis = 4;                   // d = (1, 0, 0): cell order is x order
 constexpr int kReachBuckets = 16;              // reach levels of the receiver ordering
+constexpr int kTaskLevels = 16;                // tile-count levels of the task ordering
 
 // Value of lane (l + K) mod 16 of the same 16-lane row (DPP row_ror:K).
 template <int K>
@@ -465,16 +466,29 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             const int r0 = r_lo + blk * 16, r1 = min(r0 + 16, r_hi);
             // the adjoint's pairs reach max(H_i, H_j) <= the cell's largest cut-off
             float hb = ADJ ? hmax_a : 0.0f;
-            if (!ADJ)
-                for (int r = r0; r < r1; ++r) hb = fmaxf(hb, A.Hc[sa + r]);
+            if (!ADJ) {
+                // the loads in flight before the reduction (clamped indices)
+#pragma unroll 1
+                for (int g0 = r0; g0 < r1; g0 += 8) {
+                    float hv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) hv[u] = A.Hc[sa + min(g0 + u, r1 - 1)];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) hb = fmaxf(hb, hv[u]);
+                }
+            }
             const float lo_k = ka[r0] - hb - slack - 2.0f * dx_a;
             const float hi_k = ka[r1 - 1] + hb + slack + 2.0f * dx_a;
-            int lo = 0, hi = na;
-            while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] <= lo_k) lo = m + 1; else hi = m; }
-            const int j0 = lo;
-            lo = 0; hi = na;
-            while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] < hi_k) lo = m + 1; else hi = m; }
-            const int j1 = lo;
+            // both ends of the window searched in lockstep (two loads per step)
+            int lo0 = 0, hi0 = na, lo1 = 0, hi1 = na;
+            while (lo0 < hi0 || lo1 < hi1) {
+                const int m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
+                const float k0 = lo0 < hi0 ? ka[m0] : 0.0f;
+                const float k1 = lo1 < hi1 ? ka[m1] : 0.0f;
+                if (lo0 < hi0) { if (k0 <= lo_k) lo0 = m0 + 1; else hi0 = m0; }
+                if (lo1 < hi1) { if (k1 < hi_k) lo1 = m1 + 1; else hi1 = m1; }
+            }
+            const int j0 = lo0, j1 = lo1;
             t0 = j0 >> 4;
             nt = ((j1 + 15) >> 4) - t0;
         } else {
@@ -494,22 +508,39 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
             const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[dir]);
             const float hmax_b = __uint_as_float(A.cell_hmax[b]);
             const float mg = dx_a + A.cell_dx[b];
-            // block reach: the largest key + H (ahead) or smallest key - H (behind)
+            // block reach: the largest key + H (ahead) or smallest key - H (behind);
+            // the block's receivers are loaded eight at a time (clamped indices,
+            // so every load of a group is issued before the first is needed)
             float T = sign > 0 ? -INFINITY : INFINITY;
-            for (int r = r0; r < r1; ++r) {
-                float k, H;
+#pragma unroll 1
+            for (int g0 = r0; g0 < r1; g0 += 8) {
+                float kv[8], hv[8];
                 if (listed) {
-                    int ia = L.rlist[L.recv_off[dir] + r];
-                    float4 p = A.xyzm[sa + ia];
-                    k = proj_key(p.x, p.y, p.z, s);
-                    H = A.Hc[sa + ia];
+                    const uint16_t *rl = L.rlist + L.recv_off[dir];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int ia = rl[min(g0 + u, r1 - 1)];
+                        const float4 p = A.xyzm[sa + ia];
+                        kv[u] = proj_key(p.x, p.y, p.z, s);
+                        hv[u] = A.Hc[sa + ia];
+                    }
                 } else {
-                    int q = sign > 0 ? na - 1 - r : r;
-                    k = ka[q];
-                    H = A.Hc[sa + il[q]];
+                    int iv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int r = min(g0 + u, r1 - 1);
+                        const int q = sign > 0 ? na - 1 - r : r;
+                        kv[u] = ka[q];
+                        iv[u] = il[q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) hv[u] = A.Hc[sa + iv[u]];
                 }
-                if (ADJ) H = fmaxf(H, hmax_b);
-                T = sign > 0 ? fmaxf(T, k + H) : fminf(T, k - H);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float H = ADJ ? fmaxf(hv[u], hmax_b) : hv[u];
+                    T = sign > 0 ? fmaxf(T, kv[u] + H) : fminf(T, kv[u] - H);
+                }
             }
             int nsrc;
             if (sign > 0) {
@@ -528,18 +559,45 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
         L.tasks[t] = pack_task(dir, blk, nt, t0);
     }
     __syncthreads();
-    // longest tasks first, so the four rows of a wave carry similar loads
-    for (int t = tid; t < ntask; t += blockDim.x) {
-        int rank = t;
-        if (A.task_sort) {
-            const int nt = (int)(L.tasks[t] & 511u);
-            rank = 0;
-            for (int q = 0; q < ntask; ++q) {
-                const int nq = (int)(L.tasks[q] & 511u);
-                rank += (nq > nt) || (nq == nt && q < t);
-            }
+    // longest tasks first, so the four rows of a wave carry similar loads: a
+    // stable counting sort on the tile count (kTaskLevels levels, longer
+    // counts share the top one) made of ballots on one wavefront; ties keep
+    // task order, so the order is deterministic
+    if (!A.task_sort) {
+        for (int t = tid; t < ntask; t += blockDim.x) L.torder[t] = (uint16_t)t;
+    } else if (wave == 0) {
+        int below[kTaskLevels];   // tasks of each level in the chunks so far
+        int start[kTaskLevels];
+#pragma unroll
+        for (int v = 0; v < kTaskLevels; ++v) below[v] = 0;
+        for (int c = 0; c < ntask; c += 64) {
+            const int t = c + lane;
+            const int lv = t < ntask ? min((int)(L.tasks[t] & 511u), kTaskLevels - 1) : -1;
+#pragma unroll
+            for (int v = 0; v < kTaskLevels; ++v) below[v] += __popcll(__ballot(lv == v));
         }
-        L.torder[rank] = (uint16_t)t;
+        int run = 0;
+#pragma unroll
+        for (int v = kTaskLevels - 1; v >= 0; --v) {
+            start[v] = run;
+            run += below[v];
+            below[v] = 0;
+        }
+        for (int c = 0; c < ntask; c += 64) {
+            const int t = c + lane;
+            const int lv = t < ntask ? min((int)(L.tasks[t] & 511u), kTaskLevels - 1) : -1;
+            int pos = 0;
+#pragma unroll
+            for (int v = 0; v < kTaskLevels; ++v) {
+                const uint64_t m = __ballot(lv == v);
+                if (lv == v)
+                    pos = start[v] + below[v] +
+                          (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                below[v] += __popcll(m);
+            }
+            if (t < ntask) L.torder[pos] = (uint16_t)t;
+        }
     }
     for (int t = tid; t < 4 * kChunk; t += blockDim.x)
         (&L.acc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
