@@ -105,7 +105,7 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.skey, 13 * N);
     ALLOC(d.gcell, N);
     ALLOC(d.items, pvl::queue_capacity(N, C));
-    ALLOC(d.qcount, 4);
+    ALLOC(d.qcount, pvl::kQueueCounters);
     ALLOC(d.scan_tmp, pvl::scan_scratch_words(C));
     ALLOC(d.binm, M);
     ALLOC(d.bin_blocks, NB);

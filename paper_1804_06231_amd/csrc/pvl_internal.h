@@ -87,7 +87,7 @@ struct DevCells {
     float *skey = nullptr;        // 13 x n: the keys in that order
     float *gcell = nullptr;       // n: upstream gradient in cell order (adjoint)
     int2 *items = nullptr;        // work queue of (cell, receiver chunk)
-    int *qcount = nullptr;        // [0] large-cell chunks, [1] single-chunk cells, [2] head
+    int *qcount = nullptr;        // kQueueCounters: large-cell chunks, single-chunk cells, head
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
     int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
     int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
@@ -126,7 +126,10 @@ struct SweepTuning {
 };
 
 // Entries of the work queue for n particles in ncell cells.
-int queue_capacity(int64_t n, int64_t ncell);
+int64_t queue_capacity(int64_t n, int64_t ncell);
+// Work-queue counters: large-cell chunks, single-chunk cells, and the head of
+// the dynamic queue.
+constexpr int kQueueCounters = 3;
 
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,

@@ -238,7 +238,6 @@ struct SweepLds {
     int act_cell[26];
     int task_off[28];
     int recv_off[27];
-    int wsum[4];
     int flag;
     int item;
 };
@@ -395,40 +394,42 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
         }
     } else {
         // compact, in interface-first order, the active receivers that belong to
-        // this chunk (in-cell rank in [r_lo, r_hi)); one direction at a time
+        // this chunk (in-cell rank in [r_lo, r_hi)): one wavefront per direction,
+        // ballots over the direction's list (four loads in flight per lane),
+        // into the direction's own slot of chunk entries (a direction keeps at
+        // most the chunk's receivers), so the directions need no barrier or
+        // prefix between them
         listed = true;
-        int roff = 0;
-        for (int d = 0; d < 26; ++d) {
+        for (int d = wave; d < 26; d += (int)(blockDim.x >> 6)) {
             const int act = L.act_cell[d];
             int dx, dy, dz, sign;
             nb_offset(d, dx, dy, dz);
             const int s = dir_canon(dx, dy, dz, &sign);
-            int cnt = 0;
-            for (int base = 0; base < act; base += blockDim.x) {
-                const int q = base + tid;
-                int ia = -1;
-                if (q < act) ia = sidx[(size_t)s * n + sa + (sign > 0 ? na - 1 - q : q)];
-                const bool keep = ia >= r_lo && ia < r_hi;
-                const uint64_t m = __ballot(keep);
-                if (lane == 0) L.wsum[wave] = __popcll(m);
-                __syncthreads();
-                int before = 0, total = 0;
-                for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
-                    before += w < wave ? L.wsum[w] : 0;
-                    total += L.wsum[w];
+            const uint16_t *il = sidx + (size_t)s * n + sa;
+            uint16_t *out = L.rlist + d * A.chunk;
+            int cnt = 0;   // wavefront-uniform
+            for (int base = 0; base < act; base += 4 * 64) {
+                int iv[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = base + u * 64 + lane;
+                    iv[u] = q < act ? (int)il[sign > 0 ? na - 1 - q : q] : -1;
                 }
-                const int pos = before + (int)__builtin_amdgcn_mbcnt_hi(
-                                             (uint32_t)(m >> 32),
-                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                if (keep) L.rlist[roff + cnt + pos] = (uint16_t)ia;
-                cnt += total;
-                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool keep = iv[u] >= r_lo && iv[u] < r_hi;
+                    const uint64_t m = __ballot(keep);
+                    if (keep)
+                        out[cnt + (int)__builtin_amdgcn_mbcnt_hi(
+                                      (uint32_t)(m >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint16_t)iv[u];
+                    cnt += __popcll(m);
+                }
             }
-            if (tid == 0) {
+            if (lane == 0) {
                 L.n_act[d] = cnt;
-                L.recv_off[d] = roff;
+                L.recv_off[d] = d * A.chunk;
             }
-            roff += cnt;
         }
     }
     if (tid == 0) L.n_act[26] = nr;
@@ -787,7 +788,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(MODE == kModeAdjoint ? 4 : 5, 8))) k_sweep_queue(SweepArgs A)
+    __attribute__((amdgpu_waves_per_eu(MODE == kModePlain ? 5 : 4, 8))) k_sweep_queue(SweepArgs A)
 {
     __shared__ SweepLds L;
     if (A.dflags[0]) return;
@@ -823,16 +824,16 @@ __global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, 
     }
 }
 
-int queue_capacity(int64_t n, int64_t ncell) { return (int)(ncell + n / kChunkMin + 1); }
+int64_t queue_capacity(int64_t n, int64_t ncell) { return ncell + n / kChunkMin + 1; }
 
 // Queue set-up and the persistent sweep in the given mode.
 static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                                      SweepArgs A, const SweepTuning &tune, int mode)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
-    const int cap = queue_capacity(n, ncell);
+    const int cap = (int)queue_capacity(n, ncell);
     // qcount[0..1] and the head counter (qcount[2]) start at zero
-    hipError_t e = launch_zero(st, c.qcount, 3);
+    hipError_t e = launch_zero(st, c.qcount, kQueueCounters);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_queue_items, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st,
                        c.cell_start, ncell, cap, tune.chunk, c.items, c.qcount);
