@@ -188,12 +188,22 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
  *                         accumulator tile: a multiple of 16 in 32..256.
  *                         Cells with more particles are split into x-slabs
  *                         of this many receivers.  Default 256.
+ *   PV_PARAM_TAIL_PARTS   the last cells of the work queue run as this many
+ *                         work items each (1, 2 or 4), every item a share of
+ *                         the cell's row tasks, so that the last items are
+ *                         short and the workgroups finish together; the
+ *                         shares are added in a fixed order afterwards.
+ *                         1 (no split) by default.
+ *   PV_PARAM_TAIL_CELLS   how many cells are split (0..2048; 0: as many as
+ *                         the sweep has persistent workgroups).  Default 0.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,
     PV_PARAM_TASK_SORT = 2,
     PV_PARAM_QUEUE_WGS = 3,
     PV_PARAM_CHUNK = 4,
+    PV_PARAM_TAIL_PARTS = 5,
+    PV_PARAM_TAIL_CELLS = 6,
     PV_PARAM_ADJOINT = 16,
     PV_PARAM_PLAIN = 32
 } pv_param;
@@ -205,8 +215,9 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value);
  * n floats in original order) or the plain cell-list sweep (PV_TUNE_PLAIN)
  * on `cells` for every combination of the
  * parameters above (chunk 64/128/256, 1..8 workgroups per compute unit, task
- * order, receiver order), `reps` timed runs each after one warm-up, and keeps
- * the fastest on the context.  times_ms (host, may be NULL) receives the mean
+ * order, receiver order), then the tail split (2 or 4 parts of the last 256,
+ * 512 or 1024 cells) on top of the best, `reps` timed runs each after one
+ * warm-up, and keeps the fastest on the context.  times_ms (host, may be NULL) receives the mean
  * time of the setting in place before the call and of the chosen one.  The
  * kernels write into temporary device buffers that the call allocates and
  * frees; the call synchronises the context's stream and must not be

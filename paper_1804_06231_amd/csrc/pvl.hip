@@ -68,7 +68,8 @@ void free_dev(DevCells &d)
 {
     void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cellid, d.slot, d.stage,
                     d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
-                    d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks, d.cell_dx, d.dx_all};
+                    d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks, d.cell_dx, d.dx_all,
+                    d.partial};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DevCells();
@@ -111,6 +112,7 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.bin_blocks, NB);
     ALLOC(d.cell_dx, C);
     ALLOC(d.dx_all, 1);
+    ALLOC(d.partial, (int64_t)pvl::kTailMaxCells * pvl::kTailMaxParts * pvl::kTailRecv);
 #undef ALLOC
     if (e != hipSuccess) {
         free_dev(c->d);
@@ -537,6 +539,16 @@ pv_status pv_set_param(pv_ctx *ctx, int param, int value)
             return fail(ctx, PV_EINVAL, "chunk must be a multiple of 16 in 32..256");
         t.chunk = value;
         return PV_OK;
+    case PV_PARAM_TAIL_PARTS:
+        if (value != 1 && value != 2 && value != 4)
+            return fail(ctx, PV_EINVAL, "tail_parts must be 1, 2 or 4");
+        t.tail_parts = value;
+        return PV_OK;
+    case PV_PARAM_TAIL_CELLS:
+        if (value < 0 || value > pvl::kTailMaxCells)
+            return fail(ctx, PV_EINVAL, "tail_cells must be in 0..2048");
+        t.tail_cells = value;
+        return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -550,6 +562,8 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value)
     case PV_PARAM_TASK_SORT: *value = t.task_sort; return PV_OK;
     case PV_PARAM_QUEUE_WGS: *value = t.queue_wgs_per_cu; return PV_OK;
     case PV_PARAM_CHUNK: *value = t.chunk; return PV_OK;
+    case PV_PARAM_TAIL_PARTS: *value = t.tail_parts; return PV_OK;
+    case PV_PARAM_TAIL_CELLS: *value = t.tail_cells; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -623,6 +637,25 @@ pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const floa
                         best = t;
                     }
                 }
+    // then the tail split on top of the best setting
+    {
+        const pvl::SweepTuning base = best;
+        static const int parts[] = {2, 4};
+        static const int tails[] = {256, 512, 1024};
+        for (int p : parts)
+            for (int tc : tails) {
+                if (e != hipSuccess) break;
+                pvl::SweepTuning t = base;
+                t.tail_parts = p;
+                t.tail_cells = tc;
+                float ms = 0.0f;
+                e = time_of(t, &ms);
+                if (e == hipSuccess && ms < best_ms) {
+                    best_ms = ms;
+                    best = t;
+                }
+            }
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipFree(scratch);

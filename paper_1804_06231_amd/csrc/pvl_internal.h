@@ -87,7 +87,8 @@ struct DevCells {
     float *skey = nullptr;        // 13 x n: the keys in that order
     float *gcell = nullptr;       // n: upstream gradient in cell order (adjoint)
     int2 *items = nullptr;        // work queue of (cell, receiver chunk)
-    int *qcount = nullptr;        // kQueueCounters: large-cell chunks, single-chunk cells, head
+    float4 *partial = nullptr;    // per-part sums of the split tail cells
+    int *qcount = nullptr;        // kQueueCounters: large-cell chunks, cells, head, tail cells
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
     int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
     int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
@@ -122,14 +123,22 @@ struct SweepTuning {
     int task_sort = 1;
     int queue_wgs_per_cu = 4;   // persistent workgroups per compute unit
     int chunk = 256;            // receivers per work item (multiple of 16, 32..256)
+    int tail_parts = 1;         // the queue's last cells run as this many items (1, 2, 4)
+    int tail_cells = 0;         // how many cells (0: one per persistent workgroup)
     int num_cu = 256;           // compute units of the device
 };
 
+// Tail split of the work queue: at most kTailMaxCells cells, kTailMaxParts
+// parts each, kTailRecv receivers per cell (the largest chunk).
+constexpr int kTailMaxCells = 2048;
+constexpr int kTailMaxParts = 4;
+constexpr int kTailRecv = 256;
+
 // Entries of the work queue for n particles in ncell cells.
 int64_t queue_capacity(int64_t n, int64_t ncell);
-// Work-queue counters: large-cell chunks, single-chunk cells, and the head of
-// the dynamic queue.
-constexpr int kQueueCounters = 3;
+// Work-queue counters: large-cell chunks, single-chunk cells, the head of the
+// dynamic queue, and the split tail cells.
+constexpr int kQueueCounters = 4;
 
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,

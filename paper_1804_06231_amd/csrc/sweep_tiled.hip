@@ -55,6 +55,8 @@
 //       E_i = 1/2 sum_j 4 eps [(sigma/r)^12 - (sigma/r)^6]   over r < H_i.
 #include "device_util.h"
 
+#include <algorithm>
+
 namespace pvl {
 
 constexpr int kModeSorted = 0;
@@ -63,6 +65,7 @@ constexpr int kModeAdjoint = 2;
 constexpr int kModeLJ = 3;
 
 constexpr int kChunk = 256;                    // largest receivers per work item
+static_assert(kChunk == kTailRecv, "tail slots hold one chunk");
 constexpr int kChunkMin = 32;                  // smallest (sizes the queue)
 constexpr int kMaxTasks = 27 * (kChunk / 16);  // task slots per item
 constexpr int kMaxRecv = 26 * kChunk;          // compacted receiver lists per item
@@ -224,6 +227,9 @@ struct SweepArgs {
     const int *qcount;   // [0] nbig, [1] nsmall
     int *head;           // items taken after the first static round
     int cap;
+    int tail_cells;      // single-chunk cells among the last tail_cells cells ...
+    int tail_parts;      // ... run last, as this many items each (1: no split)
+    float4 *partial;     // sums of the split items: [tail cell][part][receiver]
     int reach_order;
     int task_sort;
     int chunk;           // receivers per work item: a multiple of 16 in [kChunkMin, kChunk]
@@ -242,8 +248,48 @@ struct SweepLds {
     int item;
 };
 
+// Outputs of receiver p (cell order) from its sums over all sources: the
+// density with its self term and normalisation, the adjoint's gradients or
+// the Lennard-Jones force and energy, written at the particle's input index.
 template <int MODE>
-__device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
+__device__ __forceinline__ void finalize_receiver(const SweepArgs &A, int p, float sr, float sw,
+                                                  float sd, float sc)
+{
+    const float H = A.Hc[p];
+    const float mi = A.xyzm[p].w;
+    const float invH = 1.0f / H;
+    const float norm = (8.0f / kPi) * invH * invH * invH;
+    const int o = A.orig[p];
+    if constexpr (MODE == kModeAdjoint) {
+        // (sr, sw, sd) is dL/dx; sc is the sum behind drho_dh
+        if (A.grad_pos) {
+            A.grad_pos[3 * (int64_t)o + 0] = sr;
+            A.grad_pos[3 * (int64_t)o + 1] = sw;
+            A.grad_pos[3 * (int64_t)o + 2] = sd;
+        }
+        if (A.grad_h) A.grad_h[o] = A.gcell[p] * (-norm * (kGamma * invH) * (sc + 3.0f * mi));
+    } else if constexpr (MODE == kModeLJ) {
+        // (sr, sw, sd) is the force, sc the energy
+        if (A.force) {
+            A.force[3 * (int64_t)o + 0] = sr;
+            A.force[3 * (int64_t)o + 1] = sw;
+            A.force[3 * (int64_t)o + 2] = sd;
+        }
+        if (A.energy) A.energy[o] = sc;
+    } else {
+        if (A.rho) A.rho[o] = norm * (sr + mi);                          // self: w(0) = 1
+        if (A.wcount) A.wcount[o] = norm * (sw + 1.0f);
+        if (A.drho_dh) A.drho_dh[o] = -norm * (kGamma * invH) * (sd + 3.0f * mi);  // 1/h = gamma/H
+        if (A.ncount) A.ncount[o] = (int32_t)sc;
+    }
+}
+
+// One work item: receivers [chunk * A.chunk, ...) of cell a.  An item split
+// into nparts > 1 parts (tail slot `slot`) runs every nparts-th group of
+// tasks and leaves its sums in A.partial for k_tail_combine.
+template <int MODE>
+__device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, int part,
+                           int nparts, int slot)
 {
     constexpr bool PLAIN = MODE == kModePlain;
     constexpr bool ADJ = MODE == kModeAdjoint;
@@ -604,10 +650,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
         (&L.acc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 
-    // tasks in groups of 4 (one per row); group g runs on wave g % 4
+    // tasks in groups of 4 (one per row); the part's groups (every nparts-th)
+    // are dealt to the waves in turn
     const int row = lane >> 4;
     const int l16 = lane & 15;
-    for (int g = wave; g * 4 < ntask; g += 4) {
+    for (int gp = wave; (part + nparts * gp) * 4 < ntask; gp += 4) {
+        const int g = part + nparts * gp;
         const int t = g * 4 + row;
         const bool row_valid = t < ntask;
         const uint32_t tw = row_valid ? L.tasks[L.torder[t]] : 0u;
@@ -753,36 +801,10 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk)
         const float sw = ((s0.y + s1.y) + s2.y) + s3.y;
         const float sd = ((s0.z + s1.z) + s2.z) + s3.z;
         const float sc = ((s0.w + s1.w) + s2.w) + s3.w;
-        const int p = sa + r_lo + i;
-        const float H = A.Hc[p];
-        const float mi = A.xyzm[p].w;
-        const float invH = 1.0f / H;
-        const float norm = (8.0f / kPi) * invH * invH * invH;
-        const int o = A.orig[p];
-        if constexpr (ADJ) {
-            // (sr, sw, sd) is dL/dx; sc is the sum behind drho_dh
-            if (A.grad_pos) {
-                A.grad_pos[3 * (int64_t)o + 0] = sr;
-                A.grad_pos[3 * (int64_t)o + 1] = sw;
-                A.grad_pos[3 * (int64_t)o + 2] = sd;
-            }
-            if (A.grad_h) A.grad_h[o] = A.gcell[p] * (-norm * (kGamma * invH) * (sc + 3.0f * mi));
-            continue;
-        }
-        if constexpr (LJ) {
-            // (sr, sw, sd) is the force, sc the energy
-            if (A.force) {
-                A.force[3 * (int64_t)o + 0] = sr;
-                A.force[3 * (int64_t)o + 1] = sw;
-                A.force[3 * (int64_t)o + 2] = sd;
-            }
-            if (A.energy) A.energy[o] = sc;
-            continue;
-        }
-        if (A.rho) A.rho[o] = norm * (sr + mi);                          // self: w(0) = 1
-        if (A.wcount) A.wcount[o] = norm * (sw + 1.0f);
-        if (A.drho_dh) A.drho_dh[o] = -norm * (kGamma * invH) * (sd + 3.0f * mi);  // 1/h = gamma/H
-        if (A.ncount) A.ncount[o] = (int32_t)sc;
+        if (nparts > 1)
+            A.partial[((size_t)slot * nparts + part) * kChunk + i] = make_float4(sr, sw, sd, sc);
+        else
+            finalize_receiver<MODE>(A, sa + r_lo + i, sr, sw, sd, sc);
     }
 }
 
@@ -793,11 +815,23 @@ __global__ void __launch_bounds__(kBlock)
     __shared__ SweepLds L;
     if (A.dflags[0]) return;
     const int nbig = A.qcount[0], nsmall = A.qcount[1];
-    const int nitems = nbig + nsmall;
+    // the tail cells (a fixed set: single-chunk cells among the last
+    // tail_cells cells) run after all others, as tail_parts items each, so
+    // that the final items are short and the workgroups finish together
+    const int ntail = A.qcount[3];
+    const int nwhole = nbig + nsmall;
+    const int nitems = nwhole + ntail * A.tail_parts;
     int item = blockIdx.x;
     while (item < nitems) {
-        const int2 w = item < nbig ? A.items[item] : A.items[A.cap - nsmall + (item - nbig)];
-        sweep_item<MODE>(A, L, w.x, w.y);
+        if (item < nwhole) {
+            const int2 w = item < nbig ? A.items[item] : A.items[A.cap - nsmall + (item - nbig)];
+            sweep_item<MODE>(A, L, w.x, w.y, 0, 1, 0);
+        } else {
+            const int j = item - nwhole;
+            const int slot = j / A.tail_parts;
+            const int2 w = A.items[A.cap + slot];
+            sweep_item<MODE>(A, L, w.x, 0, j - slot * A.tail_parts, A.tail_parts, slot);
+        }
         __syncthreads();
         if (threadIdx.x == 0) L.item = (int)gridDim.x + atomicAdd(A.head, 1);
         __syncthreads();
@@ -805,10 +839,38 @@ __global__ void __launch_bounds__(kBlock)
     }
 }
 
+// Receivers of the split tail cells: the parts' sums added in part order (so
+// the result does not depend on which part finished first), then finalised.
+// One workgroup per tail cell.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_tail_combine(SweepArgs A)
+{
+    const int ntail = A.qcount[3];
+    const int slot = blockIdx.x;
+    if (slot >= ntail) return;
+    const int a = A.items[A.cap + slot].x;
+    const int sa = A.start[a];
+    const int na = A.start[a + 1] - sa;
+    for (int i = threadIdx.x; i < na; i += blockDim.x) {
+        const float4 *pp = A.partial + (size_t)slot * A.tail_parts * kChunk + i;
+        float4 t = pp[0];
+        for (int q = 1; q < A.tail_parts; ++q) {
+            const float4 u = pp[(size_t)q * kChunk];
+            t.x += u.x;
+            t.y += u.y;
+            t.z += u.z;
+            t.w += u.w;
+        }
+        finalize_receiver<MODE>(A, sa + i, t.x, t.y, t.z, t.w);
+    }
+}
+
 // Work items: the chunks of cells larger than one chunk at the front, in any
-// order; single-chunk cells at the back, counted from the end.
+// order; single-chunk cells at the back, counted from the end; the tail cells
+// (single-chunk cells with index >= tail_from) after cap.
 __global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, int cap,
-                              int chunk, int2 *__restrict__ items, int *__restrict__ qcount)
+                              int chunk, int64_t tail_from, int2 *__restrict__ items,
+                              int *__restrict__ qcount)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= ncell) return;
@@ -818,25 +880,39 @@ __global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, 
         const int nch = (na + chunk - 1) / chunk;
         const int p = atomicAdd(&qcount[0], nch);
         for (int k = 0; k < nch; ++k) items[p + k] = make_int2((int)c, k);
+    } else if (c >= tail_from) {
+        const int p = atomicAdd(&qcount[3], 1);
+        items[cap + p] = make_int2((int)c, 0);
     } else {
         const int p = atomicAdd(&qcount[1], 1);
         items[cap - 1 - p] = make_int2((int)c, 0);
     }
 }
 
-int64_t queue_capacity(int64_t n, int64_t ncell) { return ncell + n / kChunkMin + 1; }
+// Entries before the tail region; the tail region holds kTailMaxCells more.
+static int64_t queue_main(int64_t n, int64_t ncell) { return ncell + n / kChunkMin + 1; }
+int64_t queue_capacity(int64_t n, int64_t ncell) { return queue_main(n, ncell) + kTailMaxCells; }
 
 // Queue set-up and the persistent sweep in the given mode.
 static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                                      SweepArgs A, const SweepTuning &tune, int mode)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
-    const int cap = (int)queue_capacity(n, ncell);
-    // qcount[0..1] and the head counter (qcount[2]) start at zero
+    const int cap = (int)queue_main(n, ncell);
+    // persistent workgroups: a few per compute unit, never more than the cells
+    int64_t grid = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
+    if (grid > ncell) grid = ncell;
+    if (grid < 1) grid = 1;
+    A.tail_parts = tune.tail_parts;
+    A.tail_cells = tune.tail_parts == 1 ? 0
+                   : tune.tail_cells > 0 ? tune.tail_cells
+                                         : (int)std::min<int64_t>(grid, kTailMaxCells);
+    // the counters (chunks, cells, head, tail cells) start at zero
     hipError_t e = launch_zero(st, c.qcount, kQueueCounters);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_queue_items, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st,
-                       c.cell_start, ncell, cap, tune.chunk, c.items, c.qcount);
+                       c.cell_start, ncell, cap, tune.chunk, ncell - A.tail_cells, c.items,
+                       c.qcount);
     A.box = c.box;
     A.cell_box = c.cell_box;
     A.start = c.cell_start;
@@ -853,13 +929,10 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.qcount = c.qcount;
     A.head = c.qcount + 2;
     A.cap = cap;
+    A.partial = c.partial;
     A.reach_order = tune.reach_order;
     A.task_sort = tune.task_sort;
     A.chunk = tune.chunk;
-    // persistent workgroups: a few per compute unit, never more than the cells
-    int64_t grid = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
-    if (grid > ncell) grid = ncell;
-    if (grid < 1) grid = 1;
     if (mode == kModePlain)
         hipLaunchKernelGGL(k_sweep_queue<kModePlain>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     else if (mode == kModeAdjoint)
@@ -868,6 +941,17 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
         hipLaunchKernelGGL(k_sweep_queue<kModeLJ>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     else
         hipLaunchKernelGGL(k_sweep_queue<kModeSorted>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    if (A.tail_cells > 0) {
+        const dim3 tg((unsigned)A.tail_cells);
+        if (mode == kModePlain)
+            hipLaunchKernelGGL(k_tail_combine<kModePlain>, tg, dim3(kBlock), 0, st, A);
+        else if (mode == kModeAdjoint)
+            hipLaunchKernelGGL(k_tail_combine<kModeAdjoint>, tg, dim3(kBlock), 0, st, A);
+        else if (mode == kModeLJ)
+            hipLaunchKernelGGL(k_tail_combine<kModeLJ>, tg, dim3(kBlock), 0, st, A);
+        else
+            hipLaunchKernelGGL(k_tail_combine<kModeSorted>, tg, dim3(kBlock), 0, st, A);
+    }
     return hipGetLastError();
 }
 

@@ -30,7 +30,8 @@ EXPORTS = (
     "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h", "pv_drift",
     "pv_lj", "pv_autotune_grid",
 )
-PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4}
+PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4, "tail_parts": 5,
+          "tail_cells": 6}
 PV_PARAM_ADJOINT = 16
 PV_PARAM_PLAIN = 32
 TUNE_TARGETS = {"density": 0, "adjoint": 1, "plain": 2}

@@ -278,6 +278,39 @@ def test_tuning_parameters_keep_results(ctx, clustered_ref, chunk, wgs, task_sor
             ctx.set_param("reach_order", 0, sw)
 
 
+@pytest.mark.parametrize("parts,cells", [(2, 0), (4, 37), (2, 2048), (4, 0)])
+def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
+    """The queue's last cells split into parts (each a share of the cell's row
+    tasks, added in part order by a second kernel) give the oracle's results
+    in every sweep, bit-identically from run to run."""
+    s, ref, G, gref = clustered_ref
+    sweeps = ("density", "plain", "adjoint")
+    for sw in sweeps:
+        ctx.set_param("tail_parts", parts, sw)
+        ctx.set_param("tail_cells", cells, sw)
+    try:
+        for algo in ("plain", "sorted"):
+            _flush(f"tail split parts={parts} cells={cells} {algo}")
+            c1, out = run_density(ctx, s, algo)
+            compare_density(out, ref, label=f"tail {parts}x{cells} {algo}")
+            _, out2 = run_density(ctx, s, algo, cells=c1)
+            for x, y in zip(out, out2):
+                assert np.array_equal(x, y)
+        g = torch.from_numpy(G).to(dev())     # c1: the sorted cells
+        gp, gh = ctx.density_backward(c1, g)
+        gp2, gh2 = ctx.density_backward(c1, g)
+        ctx.check()
+        gp, gh = gp.cpu().numpy(), gh.cpu().numpy()
+        assert np.array_equal(gp, gp2.cpu().numpy()) and np.array_equal(gh, gh2.cpu().numpy())
+        ex = np.max(np.abs(gp - gref["gx"]) / np.maximum(gref["gx_abs"], 1e-300))
+        eh = np.max(np.abs(gh - gref["gh"]) / np.maximum(gref["gh_abs"], 1e-300))
+        assert ex < 1e-5 and eh < 1e-5, (ex, eh)
+    finally:
+        for sw in sweeps:
+            ctx.set_param("tail_parts", 1, sw)
+            ctx.set_param("tail_cells", 0, sw)
+
+
 def test_autotune(ctx, clustered_ref):
     """The autotuner keeps a setting at least as fast as the one in place, and
     the tuned sweeps still give the oracle's results."""
