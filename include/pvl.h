@@ -192,10 +192,12 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
  *                         work items each (1, 2 or 4), every item a share of
  *                         the cell's row tasks, so that the last items are
  *                         short and the workgroups finish together; the
- *                         shares are added in a fixed order afterwards.
- *                         1 (no split) by default.
- *   PV_PARAM_TAIL_CELLS   how many cells are split (0..2048; 0: as many as
- *                         the sweep has persistent workgroups).  Default 0.
+ *                         shares are added in a fixed order afterwards
+ *                         (1: no split).  Default 2.
+ *   PV_PARAM_TAIL_CELLS   how many cells are split: the single-chunk cells
+ *                         among the last this many cells of the grid
+ *                         (0..2048; 0: as many as the sweep has persistent
+ *                         workgroups).  Default 256.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,

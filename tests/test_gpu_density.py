@@ -278,7 +278,7 @@ def test_tuning_parameters_keep_results(ctx, clustered_ref, chunk, wgs, task_sor
             ctx.set_param("reach_order", 0, sw)
 
 
-@pytest.mark.parametrize("parts,cells", [(2, 0), (4, 37), (2, 2048), (4, 0)])
+@pytest.mark.parametrize("parts,cells", [(1, 0), (2, 0), (4, 37), (2, 2048), (4, 0)])
 def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
     """The queue's last cells split into parts (each a share of the cell's row
     tasks, added in part order by a second kernel) give the oracle's results
@@ -307,8 +307,8 @@ def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
         assert ex < 1e-5 and eh < 1e-5, (ex, eh)
     finally:
         for sw in sweeps:
-            ctx.set_param("tail_parts", 1, sw)
-            ctx.set_param("tail_cells", 0, sw)
+            ctx.set_param("tail_parts", 2, sw)
+            ctx.set_param("tail_cells", 256, sw)
 
 
 def test_autotune(ctx, clustered_ref):
