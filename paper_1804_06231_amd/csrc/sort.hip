@@ -38,11 +38,12 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
 
 // Cells of at most MAXC particles, one particle per thread (blockDim = MAXC),
 // all 13 axes at once with the axis loops unrolled so that their LDS traffic
-// overlaps.  NB buckets per axis.  Only the positions, the histograms and the
-// bucket-order lists live in LDS (about 16 KB for MAXC = 256), so several
-// cells share a compute unit; keys are recomputed from the positions where a
-// bucket mate's key is needed, bit-identically (same fused operations).  Each
-// particle writes its own entry of the sorted lists at its rank.
+// overlaps.  NB buckets per axis.  The histograms and the bucket-order lists
+// of in-cell ranks and keys live in LDS (about 25 KB for MAXC = 256), so
+// several cells share a compute unit; a particle's rank counts its bucket
+// mates with a smaller (key, in-cell rank), read from the bucket-order lists
+// with one LDS load each.  Each particle writes its own entry of the sorted
+// lists at its rank.
 template <int MAXC, int NB>
 __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict__ box,
                                                       const int32_t *__restrict__ cell_box,
@@ -51,9 +52,9 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
                                                       uint16_t *__restrict__ sidx,
                                                       float *__restrict__ skey, int min_cnt)
 {
-    __shared__ float4 pos[MAXC];
     __shared__ uint32_t hist[13][NB];
     __shared__ uint16_t border[13][MAXC];
+    __shared__ float bkey[13][MAXC];
     __shared__ float ax_kmin[13], ax_scale[13];
     const int c = blockIdx.x;
     const int s0 = start[c];
@@ -74,7 +75,6 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
     const int r = threadIdx.x;
     const bool on = r < cnt;
     const float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
-    pos[r] = p;
     __syncthreads();
     float k[13];
     int b[13];
@@ -122,6 +122,7 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
         for (int g = 0; g < 13; ++g) {
             q0[g] = (int)hist[g][b[g]];
             border[g][q0[g] + (int)sl[g]] = (uint16_t)r;
+            bkey[g][q0[g] + (int)sl[g]] = k[g];
         }
     }
     __syncthreads();
@@ -132,8 +133,7 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
             int rank = q0[g];
             for (int q = q0[g]; q < q1; ++q) {
                 const int r2 = border[g][q];
-                const float4 p2 = pos[r2];
-                const float k2 = proj_key(p2.x, p2.y, p2.z, g);
+                const float k2 = bkey[g][q];
                 rank += (k2 < k[g]) || (k2 == k[g] && r2 < r);
             }
             const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
