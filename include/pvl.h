@@ -196,8 +196,10 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
  *                         (1: no split).  Default 2.
  *   PV_PARAM_TAIL_CELLS   how many cells are split: the single-chunk cells
  *                         among the last this many cells of the grid
- *                         (0..2048; 0: as many as the sweep has persistent
- *                         workgroups).  Default 256.
+ *                         (1..2048), or 0: a quarter of the sweep's
+ *                         persistent workgroups when there are at least
+ *                         twice as many cells as workgroups, else none.
+ *                         Default 0.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,

@@ -124,7 +124,7 @@ struct SweepTuning {
     int queue_wgs_per_cu = 4;   // persistent workgroups per compute unit
     int chunk = 256;            // receivers per work item (multiple of 16, 32..256)
     int tail_parts = 2;         // the queue's last cells run as this many items (1, 2, 4)
-    int tail_cells = 256;       // how many cells (0: one per persistent workgroup)
+    int tail_cells = 0;         // how many cells (0: automatic)
     int num_cu = 256;           // compute units of the device
 };
 

@@ -904,9 +904,12 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     if (grid > ncell) grid = ncell;
     if (grid < 1) grid = 1;
     A.tail_parts = tune.tail_parts;
+    // auto: a quarter of the workgroups' worth of cells, when the queue holds
+    // at least two cells per workgroup (with fewer there is no tail to trim)
     A.tail_cells = tune.tail_parts == 1 ? 0
                    : tune.tail_cells > 0 ? tune.tail_cells
-                                         : (int)std::min<int64_t>(grid, kTailMaxCells);
+                   : ncell >= 2 * grid  ? (int)std::min<int64_t>(grid / 4, kTailMaxCells)
+                                        : 0;
     // the counters (chunks, cells, head, tail cells) start at zero
     hipError_t e = launch_zero(st, c.qcount, kQueueCounters);
     if (e != hipSuccess) return e;

@@ -308,7 +308,7 @@ def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
     finally:
         for sw in sweeps:
             ctx.set_param("tail_parts", 2, sw)
-            ctx.set_param("tail_cells", 256, sw)
+            ctx.set_param("tail_cells", 0, sw)
 
 
 def test_autotune(ctx, clustered_ref):
