@@ -96,17 +96,19 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH, Ti
 {
     float u = __builtin_amdgcn_sqrtf(r2) * invH;   // v_sqrt_f32, 1 ulp
     float u2 = u * u;
-    // inner piece (u < 1/2): w = 1 - 6u^2 + 6u^3, 3w + u w' = 3 - 30u^2 + 36u^3.
-    // The outer piece differs from it by t^3 and 3 t^2 (1 - 4u) with
-    // t = 1 - 2u, so with t = min(0, 1 - 2u) one expression covers both:
-    // w = 2 (1-u)^3 and 3w + u w' = 6 (1-u)^2 (1 - 2u) for u >= 1/2.
+    // inner piece (u < 1/2): w = 1 - 6u^2 + 6u^3, u w' = 18u^3 - 12u^2.
+    // The outer piece differs from it by t^3 in w and by -6 u t^2 in u w'
+    // with t = 1 - 2u, so with t = min(0, 1 - 2u) one expression covers both:
+    // w = 2 (1-u)^3 and u w' = -6 u (1-u)^2 for u >= 1/2.  The sum of
+    // m_j (3w + u w') behind drho_dh is 3 (the density sum) + the sum of
+    // m_j u w', so only the latter is accumulated.
     float t = fminf(fmaf(-2.0f, u, 1.0f), 0.0f);
     float t2 = t * t;
-    float w = fmaf(u2, fmaf(6.0f, u, -6.0f), 1.0f) + t2 * t;
-    float d3 = fmaf(3.0f * t2, fmaf(-4.0f, u, 1.0f), fmaf(u2, fmaf(36.0f, u, -30.0f), 3.0f));
+    float w = fmaf(t2, t, fmaf(u2, fmaf(6.0f, u, -6.0f), 1.0f));
+    float uw = fmaf(-6.0f * u, t2, u2 * fmaf(18.0f, u, -12.0f));
     a.rho = fmaf(mj, w, a.rho);
     a.wc += w;
-    a.dh = fmaf(mj, d3, a.dh);
+    a.dh = fmaf(mj, uw, a.dh);
     a.cnt += 1.0f;
 }
 
@@ -279,7 +281,8 @@ __device__ __forceinline__ void finalize_receiver(const SweepArgs &A, int p, flo
     } else {
         if (A.rho) A.rho[o] = norm * (sr + mi);                          // self: w(0) = 1
         if (A.wcount) A.wcount[o] = norm * (sw + 1.0f);
-        if (A.drho_dh) A.drho_dh[o] = -norm * (kGamma * invH) * (sd + 3.0f * mi);  // 1/h = gamma/H
+        // sum of m_j (3w + u w') over the neighbours and the self term (3 m_i)
+        if (A.drho_dh) A.drho_dh[o] = -norm * (kGamma * invH) * fmaf(3.0f, sr + mi, sd);
         if (A.ncount) A.ncount[o] = (int32_t)sc;
     }
 }
