@@ -500,11 +500,20 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     }
 }
 
+// Owning box of every cell; also clears the per-build state: the cells'
+// accumulated displacement bounds, the structure's largest one and the
+// largest occupancy (dflags[1]) that the binning raises.
 __global__ void k_cell_box(const BoxDesc *__restrict__ box, int nbox, int64_t ncell,
-                           int32_t *__restrict__ cell_box)
+                           int32_t *__restrict__ cell_box, float *__restrict__ cell_dx,
+                           uint32_t *__restrict__ dx_all, int *__restrict__ dflags)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) {
+        *dx_all = 0u;
+        dflags[1] = 0;
+    }
     if (c >= ncell) return;
+    cell_dx[c] = 0.0f;
     int lo = 0, hi = nbox - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -606,7 +615,7 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
                       int *dflags)
 {
     hipLaunchKernelGGL(k_cell_box, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box, nbox,
-                       ncell, c.cell_box);
+                       ncell, c.cell_box, c.cell_dx, c.dx_all, dflags);
     hipLaunchKernelGGL(k_bin_local, dim3((unsigned)plan.nblocks), dim3(kBinThreads), 0, st, c.box,
                        c.bin_blocks, pos, h, c.cellid, c.slot, c.binm, dflags);
     hipLaunchKernelGGL(k_bin_columns, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box,

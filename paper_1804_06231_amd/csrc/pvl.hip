@@ -333,11 +333,9 @@ pv_status pv_build_cells_batched(pv_ctx *ctx, int nbox, const int64_t *offsets,
     c->sorted = false;
     if ((st = upload_boxes(ctx, c)) != PV_OK) { if (fresh) pv_free_cells(ctx, c); return st; }
     c->drifted = false;
-    hipError_t e = pvl::launch_zero(ctx->stream, ctx->dflags + 1, 1);
-    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, c->d.cell_dx, ncell);
-    if (e == hipSuccess) e = pvl::launch_zero(ctx->stream, c->d.dx_all, 1);
-    if (e == hipSuccess)
-        e = pvl::launch_bin(ctx->stream, c->d, c->plan, nbox, n, ncell, pos, h, mass, ctx->dflags);
+    // (the binning also clears the displacement bounds and the occupancy word)
+    hipError_t e = pvl::launch_bin(ctx->stream, c->d, c->plan, nbox, n, ncell, pos, h, mass,
+                                   ctx->dflags);
     if (e != hipSuccess) {
         if (fresh) pv_free_cells(ctx, c);
         return fail(ctx, PV_EHIP, std::string("binning launch: ") + hipGetErrorString(e));
