@@ -128,12 +128,16 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
     // the inner one minus 6 t^2 with t = min(0, 1 - 2u); w as in the forward
     float tk = fminf(fmaf(-2.0f, uk, 1.0f), 0.0f);
     float tj = fminf(fmaf(-2.0f, uj, 1.0f), 0.0f);
-    float dwk = fmaf(-6.0f * tk, tk, uk * fmaf(18.0f, uk, -12.0f));
-    float wk = fmaf(uk * uk, fmaf(6.0f, uk, -6.0f), 1.0f) + tk * tk * tk;
-    float dwj = fmaf(-6.0f * tj, tj, uj * fmaf(18.0f, uj, -12.0f));
-    bool ink = r2 < Hk2, inj = r2 < Hj2;
-    float coef = (ink ? ck * mj * dwk : 0.0f) + (inj ? cj * mk * dwj : 0.0f);
-    a.dh += ink ? mj * fmaf(uk, dwk, 3.0f * wk) : 0.0f;
+    float tk2 = tk * tk, tj2 = tj * tj;
+    float dwk = fmaf(-6.0f, tk2, uk * fmaf(18.0f, uk, -12.0f));
+    float wk = fmaf(tk2, tk, fmaf(uk * uk, fmaf(6.0f, uk, -6.0f), 1.0f));
+    float dwj = fmaf(-6.0f, tj2, uj * fmaf(18.0f, uj, -12.0f));
+    // the receiver's own cut-off decides its term and its drho_dh sum, the
+    // source's cut-off the source's term
+    const float mjk = r2 < Hk2 ? mj : 0.0f;
+    const float cmj = r2 < Hj2 ? cj * mk : 0.0f;
+    float coef = fmaf(ck * mjk, dwk, cmj * dwj);
+    a.dh = fmaf(mjk, fmaf(uk, dwk, 3.0f * wk), a.dh);
     // (x_k - x_j) / r = -d / r
     float c = -coef * invr;
     a.gx = fmaf(c, dx, a.gx);
@@ -241,7 +245,7 @@ struct SweepLds {
     float4 acc[4][kChunk];       // per-wave receiver sums; aliased during set-up
     uint16_t rlist[kMaxRecv];    // receivers per direction (compacted or reach-ordered)
     uint32_t tasks[kMaxTasks];
-    uint16_t torder[kMaxTasks];
+    uint16_t torder[kMaxTasks];  // also the direction of each task (bytes) until ordered
     int n_act[27];
     int act_cell[26];
     int task_off[28];
@@ -482,22 +486,30 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
         }
     }
     if (tid == 0) L.n_act[26] = nr;
+    uint8_t *tdir = reinterpret_cast<uint8_t *>(L.torder);
     __syncthreads();
-    if (tid == 0) {
-        int off = 0;
-        for (int d = 0; d < 27; ++d) {
-            L.task_off[d] = off;
-            off += (L.n_act[d] + 15) >> 4;
+    // tasks (blocks of 16 receivers) per direction, their offsets by a scan
+    // over the first wavefront's lanes, and the direction of every task
+    if (wave == 0) {
+        const int nt_d = lane < 27 ? (L.n_act[lane] + 15) >> 4 : 0;
+        int inc = nt_d;
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const int v = __shfl_up(inc, o);
+            if (lane >= o) inc += v;
         }
-        L.task_off[27] = off;
+        if (lane < 27) {
+            L.task_off[lane + 1] = inc;
+            for (int t = inc - nt_d; t < inc; ++t) tdir[t] = (uint8_t)lane;
+        }
+        if (lane == 0) L.task_off[0] = 0;
     }
     __syncthreads();
     const int ntask = L.task_off[27];
 
     // source tiles of every task: the paper's bound for the block of receivers
     for (int t = tid; t < ntask; t += blockDim.x) {
-        int dir = 0;
-        while (L.task_off[dir + 1] <= t) ++dir;
+        const int dir = tdir[t];
         const int blk = t - L.task_off[dir];
         int nt, t0 = 0;
         if (PLAIN) {
