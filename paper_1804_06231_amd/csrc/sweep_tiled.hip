@@ -92,10 +92,10 @@ struct GradAcc {
     float dh;           // sum over r < H_k of m_j (3 w + u w')
 };
 
-__device__ __forceinline__ void tile_interact(float r2, float mj, float invH, TileAcc &a)
+__device__ __forceinline__ void tile_interact(float r2, float mj, float invH2, TileAcc &a)
 {
-    float u = __builtin_amdgcn_sqrtf(r2) * invH;   // v_sqrt_f32, 1 ulp
-    float u2 = u * u;
+    float u2 = r2 * invH2;
+    float u = __builtin_amdgcn_sqrtf(u2);   // v_sqrt_f32, 1 ulp
     // inner piece (u < 1/2): w = 1 - 6u^2 + 6u^3, u w' = 18u^3 - 12u^2.
     // The outer piece differs from it by t^3 in w and by -6 u t^2 in u w'
     // with t = 1 - 2u, so with t = min(0, 1 - 2u) one expression covers both:
@@ -191,7 +191,7 @@ __device__ __forceinline__ void lj_interact(float dx, float dy, float dz, float 
         float dz = ror16<K>(sz) - tz;                                     \
         float mj = ror16<K>(sm);                                          \
         float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                   \
-        if (r2 < H2) tile_interact(r2, mj, invH, acc);                    \
+        if (r2 < H2) tile_interact(r2, mj, invH2, acc);                   \
     }
 
 // Task word: bits 0-8 source tiles, 9-13 receiver block, 14-18 direction
@@ -701,6 +701,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
         const float Hi = recv_ok ? A.Hc[sa + ia] : 0.0f;
         const float H2 = Hi * Hi;
         const float invH = recv_ok ? 1.0f / Hi : 0.0f;
+        const float invH2 = invH * invH;
         // pair frame: receiver moved for +1 offsets, source for -1 offsets
         const float tx = dx > 0 ? pi.x - shx : pi.x;
         const float ty = dy > 0 ? pi.y - shy : pi.y;
