@@ -299,6 +299,27 @@ __global__ void k_scatter(const BoxDesc *__restrict__ box, int nbox, int64_t n, 
     stage[2 * q + 1] = make_float4(mass[p], __int_as_float((int)p), 0.f, 0.f);
 }
 
+// Common mass of a cell from the workgroup's smallest and largest masses
+// (red: one pair per wavefront): the mass itself when they agree, NaN when
+// they differ (see DevCells::cell_m).
+__device__ __forceinline__ void reduce_cell_mass(float mn, float mx, float2 *red, int nwave,
+                                                 float *out)
+{
+    for (int off = 32; off > 0; off >>= 1) {
+        mn = fminf(mn, __shfl_xor(mn, off));
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = make_float2(mn, mx);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < nwave; ++w) {
+            mn = fminf(mn, red[w].x);
+            mx = fmaxf(mx, red[w].y);
+        }
+        *out = mn == mx ? mn : __builtin_nanf("");
+    }
+}
+
 // One workgroup per cell: order the cell's particles by (cell-relative x,
 // original index) with a bucket sort in LDS (buckets are equal x ranges of
 // the cell; the exact rank inside a bucket compares bucket mates), shift the
@@ -311,19 +332,23 @@ __global__ void __launch_bounds__(MAXC) k_cell_finish_small(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
-    uint32_t *__restrict__ cell_hmax, int min_cnt)
+    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int min_cnt)
 {
     __shared__ float key[MAXC];
     __shared__ int32_t okey[MAXC];
     __shared__ uint16_t border[MAXC];
     __shared__ uint32_t hist[NB];
     __shared__ uint32_t hred[MAXC / 64];
+    __shared__ float2 mred[MAXC / 64];
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
     if (cnt < min_cnt || cnt > MAXC) return;
     if (cnt == 0) {
-        if (threadIdx.x == 0) cell_hmax[c] = 0u;
+        if (threadIdx.x == 0) {
+            cell_hmax[c] = 0u;
+            cell_m[c] = INFINITY;   // empty
+        }
         return;
     }
     const BoxDesc &B = box[cell_box[c]];
@@ -395,27 +420,34 @@ __global__ void __launch_bounds__(MAXC) k_cell_finish_small(
         for (int w = 0; w < MAXC / 64; ++w) mx = max(mx, hred[w]);
         cell_hmax[c] = mx;
     }
+    reduce_cell_mass(on ? m.x : INFINITY, on ? m.x : -INFINITY, mred, MAXC / 64, cell_m + c);
 }
 
 constexpr int kFinishMaxBuckets = 1024;
+
+
 
 __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
-    uint32_t *__restrict__ cell_hmax, int min_cnt)
+    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int min_cnt)
 {
     __shared__ float key[PV_MAX_CELL];
     __shared__ uint16_t slot[PV_MAX_CELL];
     __shared__ uint16_t border[PV_MAX_CELL];
     __shared__ uint32_t hist[kFinishMaxBuckets];
     __shared__ uint32_t hred[kBlock / 64];
+    __shared__ float2 mred[kBlock / 64];
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
     if (cnt < min_cnt) return;
     if (cnt > PV_MAX_CELL) {
-        if (threadIdx.x == 0) cell_hmax[c] = 0u;
+        if (threadIdx.x == 0) {
+            cell_hmax[c] = 0u;
+            cell_m[c] = __builtin_nanf("");
+        }
         return;
     }
     const BoxDesc &B = box[cell_box[c]];
@@ -467,6 +499,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
         border[hist[bucket(key[r])] + slot[r]] = (uint16_t)r;
     __syncthreads();
     uint32_t hm = 0u;
+    float mmin = INFINITY, mmax = -INFINITY;
     for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
         const float k = key[r];
         const int b = bucket(k);
@@ -488,6 +521,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
         Hout[s0 + rank] = a.w;
         orig[s0 + rank] = my_orig;
         hm = max(hm, __float_as_uint(a.w));
+        mmin = fminf(mmin, m.x);
+        mmax = fmaxf(mmax, m.x);
     }
     // largest cut-off of the cell (positive floats order as their bits)
     for (int off = 32; off > 0; off >>= 1) hm = max(hm, (uint32_t)__shfl_xor((int)hm, off));
@@ -498,6 +533,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = max(mx, hred[w]);
         cell_hmax[c] = mx;
     }
+    reduce_cell_mass(mmin, mmax, mred, (int)(blockDim.x >> 6), cell_m + c);
 }
 
 // Owning box of every cell; also clears the per-build state: the cells'
@@ -628,12 +664,14 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
     }
     // size classes: at most 64 particles (and empty cells), 65..256, more
     hipLaunchKernelGGL((k_cell_finish_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax, 0);
+                       c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax,
+                       c.cell_m, 0);
     hipLaunchKernelGGL((k_cell_finish_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0,
                        st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
-                       c.cell_hmax, 65);
+                       c.cell_hmax, c.cell_m, 65);
     hipLaunchKernelGGL(k_cell_finish_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax, 257);
+                       c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax,
+                       c.cell_m, 257);
     return hipGetLastError();
 }
 

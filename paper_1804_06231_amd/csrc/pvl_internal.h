@@ -92,6 +92,8 @@ struct DevCells {
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
     int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
     int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
+    float *cell_m = nullptr;      // ncell: the mass shared by all particles of the cell,
+                                  // NaN if they differ, +inf if the cell is empty
     float *cell_dx = nullptr;     // ncell: accumulated largest displacement since the build
     uint32_t *dx_all = nullptr;   // largest cell_dx of the structure (fp32 bits)
     int4 *bin_blocks = nullptr;   // binning chunks: (box, chunk in box, first, end particle)

@@ -112,6 +112,21 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH2, T
     a.cnt += 1.0f;
 }
 
+// tile_interact with unit masses and without the density sum (the caller
+// scales the sums by the common mass).
+__device__ __forceinline__ void tile_interact_unit(float r2, float invH2, TileAcc &a)
+{
+    float u2 = r2 * invH2;
+    float u = __builtin_amdgcn_sqrtf(u2);   // v_sqrt_f32, 1 ulp
+    float t = fminf(fmaf(-2.0f, u, 1.0f), 0.0f);
+    float t2 = t * t;
+    float w = fmaf(t2, t, fmaf(u2, fmaf(6.0f, u, -6.0f), 1.0f));
+    float uw = fmaf(-6.0f * u, t2, u2 * fmaf(18.0f, u, -12.0f));
+    a.wc += w;
+    a.dh += uw;
+    a.cnt += 1.0f;
+}
+
 // Both terms of the adjoint for a source j within max(H_k, H_j) of receiver
 // k (d = x_j - x_k, r2 = |d|^2 > 0).  Receiver constants: H_k^2, 1/H_k,
 // ck = G_k 8 / (pi H_k^4), m_k; source: m_j, 1/H_j, cj = G_j 8 / (pi H_j^4),
@@ -194,6 +209,16 @@ __device__ __forceinline__ void lj_interact(float dx, float dy, float dz, float 
         if (r2 < H2) tile_interact(r2, mj, invH2, acc);                   \
     }
 
+// The same step when all masses are equal (no source mass, no density sum).
+#define PVL_TILE_STEP_U(K)                                                \
+    {                                                                     \
+        float dx = ror16<K>(sx) - tx;                                     \
+        float dy = ror16<K>(sy) - ty;                                     \
+        float dz = ror16<K>(sz) - tz;                                     \
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                   \
+        if (r2 < H2) tile_interact_unit(r2, invH2, acc);                  \
+    }
+
 // Task word: bits 0-8 source tiles, 9-13 receiver block, 14-18 direction
 // (0..25 neighbour, 26 = own cell), 19-27 first source tile.
 __device__ __forceinline__ uint32_t pack_task(int dir, int blk, int nt, int t0)
@@ -227,6 +252,7 @@ struct SweepArgs {
     float lj_eps, lj_sigma2;     // Lennard-Jones parameters
     float *force, *energy;       // Lennard-Jones outputs (input order)
     int *dflags;
+    const float *cell_m;         // common mass per cell (NaN: mixed, +inf: empty)
     const float *cell_dx;        // accumulated displacement bound per cell (pv_drift)
     const uint32_t *dx_all;      // its largest value (fp32 bits)
     const int2 *items;   // queue: [0, nbig) large-cell chunks, [cap - nsmall, cap) cells
@@ -252,6 +278,7 @@ struct SweepLds {
     int recv_off[27];
     int flag;
     int item;
+    float mass;          // the item's common mass (NaN: masses differ)
 };
 
 // Outputs of receiver p (cell order) from its sums over all sources: the
@@ -327,12 +354,14 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
     const float *skey = A.skey;
 
     // receivers of each direction that can have a candidate (first_a), whole cell
+    float mb = INFINITY;   // the neighbour's common mass (see DevCells::cell_m)
     if (tid < 26) {
         int dx, dy, dz;
         nb_offset(tid, dx, dy, dz);
         float sx, sy, sz;
         int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
         int sb = A.start[b], nb = A.start[b + 1] - sb;
+        if (!ADJ && !LJ) mb = A.cell_m[b];
         int act = 0;
         if (PLAIN) {
             act = nb > 0 ? na : 0;
@@ -362,6 +391,18 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             }
         }
         L.act_cell[tid] = act;
+    }
+    // equal masses: when this cell and every non-empty neighbour share one
+    // mass m, the density sums are m times the unit-mass sums, and the steps
+    // need neither the sources' masses nor a separate density sum
+    if constexpr (!ADJ && !LJ) {
+        if (wave == 0) {
+            const float ma = A.cell_m[a];
+            const bool ok = lane >= 26 || mb == ma || mb == INFINITY;
+            const uint64_t bad = __ballot(!ok);
+            if (lane == 0)
+                L.mass = (bad == 0 && ma == ma && ma != INFINITY) ? ma : __builtin_nanf("");
+        }
     }
     __syncthreads();
 
@@ -771,6 +812,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
         } else {
             TileAcc acc = {0.f, 0.f, 0.f, 0.f};
             const float sig2 = A.lj_sigma2, eps = A.lj_eps;
+            const bool unit = !LJ && L.mass == L.mass;
             auto load_src = [&](int p) {
                 return p >= 0 ? A.xyzm[sb + p] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
             };
@@ -790,6 +832,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
                         PVL_LJ_STEP(5) PVL_LJ_STEP(6) PVL_LJ_STEP(7) PVL_LJ_STEP(8)
                         PVL_LJ_STEP(9) PVL_LJ_STEP(10) PVL_LJ_STEP(11) PVL_LJ_STEP(12)
                         PVL_LJ_STEP(13) PVL_LJ_STEP(14) PVL_LJ_STEP(15)
+                    } else if (unit) {
+                        if (tile != diag) PVL_TILE_STEP_U(0)
+                        PVL_TILE_STEP_U(1) PVL_TILE_STEP_U(2) PVL_TILE_STEP_U(3) PVL_TILE_STEP_U(4)
+                        PVL_TILE_STEP_U(5) PVL_TILE_STEP_U(6) PVL_TILE_STEP_U(7) PVL_TILE_STEP_U(8)
+                        PVL_TILE_STEP_U(9) PVL_TILE_STEP_U(10) PVL_TILE_STEP_U(11) PVL_TILE_STEP_U(12)
+                        PVL_TILE_STEP_U(13) PVL_TILE_STEP_U(14) PVL_TILE_STEP_U(15)
                     } else {
                         if (tile != diag) PVL_TILE_STEP(0)
                         PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
@@ -813,10 +861,15 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
 
     for (int i = tid; i < nr; i += blockDim.x) {
         const float4 s0 = L.acc[0][i], s1 = L.acc[1][i], s2 = L.acc[2][i], s3 = L.acc[3][i];
-        const float sr = ((s0.x + s1.x) + s2.x) + s3.x;
+        float sr = ((s0.x + s1.x) + s2.x) + s3.x;
         const float sw = ((s0.y + s1.y) + s2.y) + s3.y;
-        const float sd = ((s0.z + s1.z) + s2.z) + s3.z;
+        float sd = ((s0.z + s1.z) + s2.z) + s3.z;
         const float sc = ((s0.w + s1.w) + s2.w) + s3.w;
+        if (!ADJ && !LJ && L.mass == L.mass) {
+            // equal masses: the sums were taken with unit masses
+            sr = L.mass * sw;
+            sd = L.mass * sd;
+        }
         if (nparts > 1)
             A.partial[((size_t)slot * nparts + part) * kChunk + i] = make_float4(sr, sw, sd, sc);
         else
@@ -942,6 +995,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.sidx = c.sidx;
     A.skey = c.skey;
     A.n = n;
+    A.cell_m = c.cell_m;
     A.cell_dx = c.cell_dx;
     A.dx_all = c.dx_all;
     A.items = c.items;

@@ -120,6 +120,25 @@ def test_empty_and_tiny(ctx):
     assert list(out[3]) == [1, 1]
 
 
+@pytest.mark.parametrize("algo", ["sorted", "plain"])
+def test_equal_and_mixed_masses(ctx, algo):
+    """Work items whose cell and neighbours share one mass take the unit-mass
+    steps; items next to a different mass take the general ones.  Both, and
+    the seams between them, give the oracle's results."""
+    base = uniform_set(20000, 41, hmode="lognormal")
+    x = base.pos[:, 0]
+    variants = {
+        "equal": np.full(base.n, 1.0 / base.n, np.float32),
+        "two-regions": np.where(x < 0.3, 2.0 / base.n, 1.0 / base.n).astype(np.float32),
+        "one-odd": np.where(np.arange(base.n) == 777, 3.0 / base.n, 1.0 / base.n).astype(np.float32),
+    }
+    for name, m in variants.items():
+        _flush(f"masses {name} {algo}")
+        s = ParticleSet(base.pos, base.h, m, base.box, 41, name)
+        _, out = run_density(ctx, s, algo)
+        compare_density(out, oracle_for(s).density(), label=f"masses-{name}-{algo}")
+
+
 def test_heavy_cell_near_max_occupancy(ctx):
     """Most particles packed in one cell (occupancy ~4000, the largest the
     per-cell sort supports) next to nearly empty cells."""
