@@ -92,6 +92,14 @@ struct DevCells {
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
     int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
     int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
+    // Tile summaries of the sorted lists, written by the per-cell sorts: for
+    // axis s and tile slot t = cell_start[c] / 16 + c + j of tile j of cell c,
+    //   tiles[kTileTS(s)] key of position 16 j        (first of tile j from the start)
+    //   tiles[kTileTE(s)] key of position na-1-16 j   (first of tile j from the end)
+    // and for the x axis (the cell order) the last key and the largest H of
+    // each tile.
+    float *tiles = nullptr;       // kTileArrays x tslots
+    int64_t tslots = 0;
     float *cell_m = nullptr;      // ncell: the mass shared by all particles of the cell,
                                   // NaN if they differ, +inf if the cell is empty
     float *cell_dx = nullptr;     // ncell: accumulated largest displacement since the build
@@ -105,6 +113,19 @@ struct BinPlan {
     int64_t mtot = 0;      // entries of the count matrices
     int64_t nblocks = 0;   // chunks (workgroups of the counting kernel)
 };
+
+// Tile-summary arrays (see DevCells::tiles).
+constexpr int kTileArrays = 2 * 13 + 2;
+constexpr int kTileAxisX = 4;   // d = (1, 0, 0): the sorted list is the cell order
+__host__ __device__ inline int64_t tile_slot(int32_t cell_start, int64_t cell, int j)
+{
+    return (int64_t)(cell_start >> 4) + cell + j;
+}
+__host__ __device__ inline int64_t tile_slots(int64_t n, int64_t ncell) { return n / 16 + ncell + 1; }
+__host__ __device__ inline int64_t kTileTS(int s) { return s; }
+__host__ __device__ inline int64_t kTileTE(int s) { return 13 + s; }
+constexpr int64_t kTileTLX = 26;   // x axis: key of the tile's last position
+constexpr int64_t kTileBHX = 27;   // x axis: largest H of the tile
 
 // Launch wrappers (each lives next to its kernels).
 hipError_t launch_box_hmax(hipStream_t st, const DevCells &c, int nbox, int64_t n,

@@ -42,15 +42,17 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
 // of in-cell ranks and keys live in LDS (about 25 KB for MAXC = 256), so
 // several cells share a compute unit; a particle's rank counts its bucket
 // mates with a smaller (key, in-cell rank), read from the bucket-order lists
-// with one LDS load each.  Each particle writes its own entry of the sorted
-// lists at its rank.
+// with one LDS load each.  Each particle writes its own entries of the sorted
+// lists at its ranks, and the first keys of the tiles of 16 positions.
 template <int MAXC, int NB>
 __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict__ box,
                                                       const int32_t *__restrict__ cell_box,
                                                       const int32_t *__restrict__ start,
-                                                      const float4 *__restrict__ xyzm, int64_t n,
+                                                      const float4 *__restrict__ xyzm,
+                                                      const float *__restrict__ Hc, int64_t n,
                                                       uint16_t *__restrict__ sidx,
-                                                      float *__restrict__ skey, int min_cnt)
+                                                      float *__restrict__ skey, int64_t tslots,
+                                                      float *__restrict__ tiles, int min_cnt)
 {
     __shared__ uint32_t hist[13][NB];
     __shared__ uint16_t border[13][MAXC];
@@ -75,6 +77,7 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
     const int r = threadIdx.x;
     const bool on = r < cnt;
     const float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float Hi = on ? Hc[s0 + r] : 0.0f;
     __syncthreads();
     float k[13];
     int b[13];
@@ -116,6 +119,7 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
         }
     }
     __syncthreads();
+    const int64_t slot0 = tile_slot(s0, c, 0);
     int q0[13];
     if (on) {
 #pragma unroll
@@ -139,17 +143,30 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
             const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
             sidx[o] = (uint16_t)r;
             skey[o] = k[g];
+            // tile summaries: the first keys of the tiles from either end
+            const int re = cnt - 1 - rank;
+            if ((rank & 15) == 0) tiles[kTileTS(g) * tslots + slot0 + (rank >> 4)] = k[g];
+            if ((re & 15) == 0) tiles[kTileTE(g) * tslots + slot0 + (re >> 4)] = k[g];
+            if (g == kTileAxisX && ((rank & 15) == 15 || re == 0))
+                tiles[kTileTLX * tslots + slot0 + (rank >> 4)] = k[g];
         }
     }
+    // largest cut-off of each tile of the cell order (16 consecutive threads)
+    float hx = Hi;
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) hx = fmaxf(hx, __shfl_xor(hx, off, 16));
+    if (on && (r & 15) == 0) tiles[kTileBHX * tslots + slot0 + (r >> 4)] = hx;
 }
 
 // Cells above the small sizes: G axes per pass, as many as fit the LDS.
 __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restrict__ box,
                                                     const int32_t *__restrict__ cell_box,
                                                     const int32_t *__restrict__ start,
-                                                    const float4 *__restrict__ xyzm, int64_t n,
+                                                    const float4 *__restrict__ xyzm,
+                                                    const float *__restrict__ Hc, int64_t n,
                                                     uint16_t *__restrict__ sidx,
-                                                    float *__restrict__ skey, int min_cnt)
+                                                    float *__restrict__ skey, int64_t tslots,
+                                                    float *__restrict__ tiles, int min_cnt)
 {
     __shared__ __align__(16) unsigned char lds[kSortLdsBytes];
     __shared__ float ax_kmin[13], ax_scale[13];
@@ -256,18 +273,33 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
             }
         }
         __syncthreads();
-        // coalesced output of the sorted lists
+        // coalesced output of the sorted lists and of the tiles' first keys
+        const int64_t slot0 = tile_slot(s0, c, 0);
         for (int g = 0; g < ng; ++g) {
+            const int s = sf + g;
             const float *kk = key + g * keyw;
             const uint16_t *fo = forder + g * u16w;
-            const size_t o = (size_t)(sf + g) * (size_t)n + (size_t)s0;
+            const size_t o = (size_t)s * (size_t)n + (size_t)s0;
             for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
                 const int r = fo[q];
+                const float kq = kk[r];
                 sidx[o + q] = (uint16_t)r;
-                skey[o + q] = kk[r];
+                skey[o + q] = kq;
+                const int re = cnt - 1 - q;
+                if ((q & 15) == 0) tiles[kTileTS(s) * tslots + slot0 + (q >> 4)] = kq;
+                if ((re & 15) == 0) tiles[kTileTE(s) * tslots + slot0 + (re >> 4)] = kq;
+                if (s == kTileAxisX && ((q & 15) == 15 || re == 0))
+                    tiles[kTileTLX * tslots + slot0 + (q >> 4)] = kq;
             }
         }
         __syncthreads();
+    }
+    // largest cut-off of each tile of the cell order
+    const int64_t slot0 = tile_slot(s0, c, 0);
+    for (int j = threadIdx.x; j * 16 < cnt; j += blockDim.x) {
+        float hx = 0.0f;
+        for (int q = 16 * j; q < min(16 * j + 16, cnt); ++q) hx = fmaxf(hx, Hc[s0 + q]);
+        tiles[kTileBHX * tslots + slot0 + j] = hx;
     }
 }
 
@@ -279,13 +311,17 @@ hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t n
 {
     if (ncell == 0 || n == 0) return hipSuccess;
     hipLaunchKernelGGL((k_sort13_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 1);
+                       c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
+                       c.tiles, 1);
     hipLaunchKernelGGL((k_sort13_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 65);
+                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                       c.tslots, c.tiles, 65);
     hipLaunchKernelGGL((k_sort13_small<512, 256>), dim3((unsigned)ncell), dim3(512), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 257);
+                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                       c.tslots, c.tiles, 257);
     hipLaunchKernelGGL(k_sort13_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.xyzm, n, c.sidx, c.skey, 513);
+                       c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
+                       c.tiles, 513);
     return hipGetLastError();
 }
 

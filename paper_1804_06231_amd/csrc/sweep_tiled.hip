@@ -234,6 +234,31 @@ __device__ __forceinline__ void nb_offset(int dir, int &dx, int &dy, int &dz)
     dz = o % 3 - 1;
 }
 
+// Length of the prefix of the sorted array a[0, len) (len >= 1) on which
+// v OP x holds (OP 0: <, 1: <=, 2: >; the predicate is true on a prefix).
+// Up to 16 entries are loaded at once and counted; longer arrays are
+// bisected.
+template <int OP>
+__device__ __forceinline__ int prefix_count(const float *__restrict__ a, int len, float x)
+{
+    auto pred = [x](float v) { return OP == 0 ? v < x : (OP == 1 ? v <= x : v > x); };
+    if (len <= 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = a[min(u, len - 1)];
+        int c = 0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c += (u < len && pred(v[u])) ? 1 : 0;
+        return c;
+    }
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if (pred(a[m])) lo = m + 1; else hi = m;
+    }
+    return lo;
+}
+
 struct SweepArgs {
     const BoxDesc *box;
     const int32_t *cell_box;
@@ -253,6 +278,8 @@ struct SweepArgs {
     float *force, *energy;       // Lennard-Jones outputs (input order)
     int *dflags;
     const float *cell_m;         // common mass per cell (NaN: mixed, +inf: empty)
+    const float *tiles;          // tile summaries of the sorted lists (see DevCells)
+    int64_t tslots;
     const float *cell_dx;        // accumulated displacement bound per cell (pv_drift)
     const uint32_t *dx_all;      // its largest value (fp32 bits)
     const int2 *items;   // queue: [0, nbig) large-cell chunks, [cap - nsmall, cap) cells
@@ -352,8 +379,14 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
     const int wave = tid >> 6, lane = tid & 63;
     const uint16_t *sidx = A.sidx;
     const float *skey = A.skey;
+    const int64_t ts = A.tslots;
+    const float *tiles = A.tiles;
+    const int ntile_a = (na + 15) >> 4;
+    const int64_t slot_a = tile_slot(sa, a, 0);
 
-    // receivers of each direction that can have a candidate (first_a), whole cell
+    // receivers of each direction that can have a candidate (first_a), whole
+    // cell, rounded up to whole tiles of the interface-first order (the extra
+    // receivers have no candidate either; they only fill their row)
     float mb = INFINITY;   // the neighbour's common mass (see DevCells::cell_m)
     if (tid < 26) {
         int dx, dy, dz;
@@ -371,24 +404,22 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             float e[3];
             dir_axis(s, e);
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
-            const float *ka = skey + (size_t)s * n + sa;
-            const float *kb = skey + (size_t)s * n + sb;
+            const int64_t slot_b = tile_slot(sb, b, 0);
             // the adjoint also keeps pairs decided by the source's cut-off
             const float reach = (ADJ ? fmaxf(hmax_a, __uint_as_float(A.cell_hmax[b])) : hmax_a) +
                                 (dx_a + A.cell_dx[b]);
+            int ntl;
             if (sign > 0) {
-                // receivers with key_i + reach > key_b[0] + se
-                float thr = (kb[0] + se) - reach - slack;
-                int lo = 0, hi = na;
-                while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] <= thr) lo = m + 1; else hi = m; }
-                act = na - lo;
+                // receivers with key_i + reach > key_b[0] + se: a suffix, whose
+                // tiles counted from the end have their first key above thr
+                const float thr = (tiles[kTileTS(s) * ts + slot_b] + se) - reach - slack;
+                ntl = prefix_count<2>(tiles + kTileTE(s) * ts + slot_a, ntile_a, thr);
             } else {
-                // receivers with key_i - reach < key_b[nb-1] + se
-                float thr = (kb[nb - 1] + se) + reach + slack;
-                int lo = 0, hi = na;
-                while (lo < hi) { int m = (lo + hi) >> 1; if (ka[m] < thr) lo = m + 1; else hi = m; }
-                act = lo;
+                // receivers with key_i - reach < key_b[nb-1] + se: a prefix
+                const float thr = (tiles[kTileTE(s) * ts + slot_b] + se) + reach + slack;
+                ntl = prefix_count<0>(tiles + kTileTS(s) * ts + slot_a, ntile_a, thr);
             }
+            act = min(16 * ntl, na);
         }
         L.act_cell[tid] = act;
     }
@@ -564,36 +595,19 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             }
             nt = (nb + 15) >> 4;
         } else if (dir == 26) {
-            // two-sided window in x over the whole cell: |x_j - x_i| < H_i
-            const float *ka = skey + (size_t)kSelfAxis * n + sa;
-            const int r0 = r_lo + blk * 16, r1 = min(r0 + 16, r_hi);
+            // two-sided window in x over the whole cell: |x_j - x_i| < H_i.
+            // The block is tile jb of the cell order (chunks are whole tiles);
+            // the source tiles are those whose last x is above the block's
+            // first x - reach and whose first x is below its last x + reach.
+            const int jb = (r_lo >> 4) + blk;
+            const float *first_x = tiles + kTileTS(kSelfAxis) * ts + slot_a;
+            const float *last_x = tiles + kTileTLX * ts + slot_a;
             // the adjoint's pairs reach max(H_i, H_j) <= the cell's largest cut-off
-            float hb = ADJ ? hmax_a : 0.0f;
-            if (!ADJ) {
-                // the loads in flight before the reduction (clamped indices)
-#pragma unroll 1
-                for (int g0 = r0; g0 < r1; g0 += 8) {
-                    float hv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) hv[u] = A.Hc[sa + min(g0 + u, r1 - 1)];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) hb = fmaxf(hb, hv[u]);
-                }
-            }
-            const float lo_k = ka[r0] - hb - slack - 2.0f * dx_a;
-            const float hi_k = ka[r1 - 1] + hb + slack + 2.0f * dx_a;
-            // both ends of the window searched in lockstep (two loads per step)
-            int lo0 = 0, hi0 = na, lo1 = 0, hi1 = na;
-            while (lo0 < hi0 || lo1 < hi1) {
-                const int m0 = (lo0 + hi0) >> 1, m1 = (lo1 + hi1) >> 1;
-                const float k0 = lo0 < hi0 ? ka[m0] : 0.0f;
-                const float k1 = lo1 < hi1 ? ka[m1] : 0.0f;
-                if (lo0 < hi0) { if (k0 <= lo_k) lo0 = m0 + 1; else hi0 = m0; }
-                if (lo1 < hi1) { if (k1 < hi_k) lo1 = m1 + 1; else hi1 = m1; }
-            }
-            const int j0 = lo0, j1 = lo1;
-            t0 = j0 >> 4;
-            nt = ((j1 + 15) >> 4) - t0;
+            const float hb = ADJ ? hmax_a : tiles[kTileBHX * ts + slot_a + jb];
+            const float lo_k = first_x[jb] - hb - slack - 2.0f * dx_a;
+            const float hi_k = last_x[jb] + hb + slack + 2.0f * dx_a;
+            t0 = prefix_count<1>(last_x, ntile_a, lo_k);
+            nt = prefix_count<0>(first_x, ntile_a, hi_k) - t0;
         } else {
             int dx, dy, dz;
             nb_offset(dir, dx, dy, dz);
@@ -607,7 +621,6 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
             const float *ka = skey + (size_t)s * n + sa;
             const uint16_t *il = sidx + (size_t)s * n + sa;
-            const float *kb = skey + (size_t)s * n + sb;
             const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[dir]);
             const float hmax_b = __uint_as_float(A.cell_hmax[b]);
             const float mg = dx_a + A.cell_dx[b];
@@ -645,19 +658,17 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
                     T = sign > 0 ? fmaxf(T, kv[u] + H) : fminf(T, kv[u] - H);
                 }
             }
-            int nsrc;
+            // source tiles with a key below the reach (ahead), or above it
+            // (behind, counted from the end): from the tiles' first keys
+            const int64_t slot_b = tile_slot(sb, b, 0);
+            const int ntile_b = (nb + 15) >> 4;
             if (sign > 0) {
                 T = (T - se) + slack + mg;
-                int lo = 0, hi = nb;
-                while (lo < hi) { int m = (lo + hi) >> 1; if (kb[m] < T) lo = m + 1; else hi = m; }
-                nsrc = lo;
+                nt = prefix_count<0>(tiles + kTileTS(s) * ts + slot_b, ntile_b, T);
             } else {
                 T = (T - se) - slack - mg;
-                int lo = 0, hi = nb;
-                while (lo < hi) { int m = (lo + hi) >> 1; if (kb[m] <= T) lo = m + 1; else hi = m; }
-                nsrc = nb - lo;
+                nt = prefix_count<2>(tiles + kTileTE(s) * ts + slot_b, ntile_b, T);
             }
-            nt = (nsrc + 15) >> 4;
         }
         L.tasks[t] = pack_task(dir, blk, nt, t0);
     }
@@ -996,6 +1007,8 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.skey = c.skey;
     A.n = n;
     A.cell_m = c.cell_m;
+    A.tiles = c.tiles;
+    A.tslots = c.tslots;
     A.cell_dx = c.cell_dx;
     A.dx_all = c.dx_all;
     A.items = c.items;
