@@ -6,9 +6,11 @@ A step is one pass of the whole hot path over the resident particle set:
 build_cells (binning into cells, explicit grid) + sort_cells (13 per-axis
 sorts) + density (sorted-pair sweep with in-place finalisation).  The plain
 cell-list comparator (build_cells + density with the 27-cell brute force) is
-timed the same way.  Both steps are timed as issued call by call and as a
-captured HIP graph (the reported figure); the sweep parameters are autotuned
-first.  Inputs are seeded synthetic particle sets already in HBM.
+timed the same way.  Both steps are timed as issued call by call on the
+stream and as a captured HIP graph (one launch per step), with the same event
+timing; the reported figure is the faster of the two (both are recorded, with
+which one was reported).  The sweep parameters are autotuned first.  Inputs
+are seeded synthetic particle sets already in HBM.
 
 Prints one JSON line: pair-interactions/s of the sorted-pair path (value), the
 plain comparator, ns/particle, the sweep kernel's roofline and the fp64 CPU
@@ -175,7 +177,7 @@ def main():
         ctx.density(cells, "plain", out_p)
 
     print("[bench] timing sorted-pair path", file=sys.stderr, flush=True)
-    ms_sorted_eager, _ = _time_loop(step_sorted, a.steps, a.warmup, torch)
+    ms_sorted_eager, wall_eager = _time_loop(step_sorted, a.steps, a.warmup, torch)
     print("[bench] timing plain cell-list path", file=sys.stderr, flush=True)
     ms_plain_eager, _ = _time_loop(step_plain, a.steps, a.warmup, torch)
     ctx.check()
@@ -203,10 +205,17 @@ def main():
         print("[bench] h-iteration, list reuse, Lennard-Jones", file=sys.stderr, flush=True)
         hsolve = _bench_hsolve(ctx, s, pos, m, torch)
         reuse = _bench_reuse(a, ctx, s, pos, h, m, grid, out_s, torch)
-        reuse["speedup_vs_rebuild"] = ms_sorted / reuse["ms_per_step"]
         lj = _bench_lj(a, ctx, torch)
 
     n = s.n
+    # the faster of the two launch forms of the same step
+    ms_sorted_graph, ms_plain_graph = ms_sorted, ms_plain
+    timed = "graph" if ms_sorted_graph <= ms_sorted_eager else "stream"
+    wall = wall_sorted if timed == "graph" else wall_eager
+    ms_sorted = min(ms_sorted_graph, ms_sorted_eager)
+    ms_plain = min(ms_plain_graph, ms_plain_eager)
+    if reuse is not None:
+        reuse["speedup_vs_rebuild"] = ms_sorted / reuse["ms_per_step"]
     value = pairs / (ms_sorted * 1e-3)
     alg_ops = OPS_PER_CANDIDATE * cand_sorted + OPS_PER_INTERACTION * inr
     achieved = alg_ops / (ms_sweep * 1e-3) / 1e12
@@ -235,9 +244,12 @@ def main():
                    if "lognormal" in s.name else "see workload"},
         "ns_per_particle": ms_sorted * 1e6 / n,
         "pairs_in_range": pairs,
+        "timed": timed,
+        "graph_ms_per_step": ms_sorted_graph,
         "eager_ms_per_step": ms_sorted_eager,
         "plain_cell_list": {"ms_per_step": ms_plain, "value": pairs / (ms_plain * 1e-3),
                             "ns_per_particle": ms_plain * 1e6 / n,
+                            "graph_ms_per_step": ms_plain_graph,
                             "eager_ms_per_step": ms_plain_eager, "sweep_ms": ms_sweep_plain},
         "speedup_sorted_vs_plain": ms_plain / ms_sorted,
         "stages_ms": {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep,
@@ -249,7 +261,7 @@ def main():
         "h_iteration": hsolve,
         "verlet_reuse": reuse,
         "lennard_jones": lj,
-        "wall_ms_per_step": wall_sorted,
+        "wall_ms_per_step": wall,
         "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
                      "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
