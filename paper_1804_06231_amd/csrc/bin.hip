@@ -662,13 +662,18 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
                            plan.chunk, pos, h, mass, c.cellid, c.slot, c.binm, c.cell_start,
                            c.stage);
     }
-    // size classes: at most 64 particles (and empty cells), 65..256, more
-    hipLaunchKernelGGL((k_cell_finish_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax,
-                       c.cell_m, 0);
+    // size classes: at most 64 particles (and empty cells), 65..256, more;
+    // when cells hold 128 or more on average the first two are one launch
+    // (small cells are then rare, and an empty class still costs a launch
+    // over all cells)
+    const bool dense = n >= kDenseCells * ncell;
+    if (!dense)
+        hipLaunchKernelGGL((k_cell_finish_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
+                           c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
+                           c.cell_hmax, c.cell_m, 0);
     hipLaunchKernelGGL((k_cell_finish_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0,
                        st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
-                       c.cell_hmax, c.cell_m, 65);
+                       c.cell_hmax, c.cell_m, dense ? 0 : 65);
     hipLaunchKernelGGL(k_cell_finish_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                        c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax,
                        c.cell_m, 257);

@@ -114,6 +114,10 @@ struct BinPlan {
     int64_t nblocks = 0;   // chunks (workgroups of the counting kernel)
 };
 
+// Mean cell occupancy from which the per-cell kernels fold their rare size
+// classes into their neighbours' launches.
+constexpr int64_t kDenseCells = 128;
+
 // Tile-summary arrays (see DevCells::tiles).
 constexpr int kTileArrays = 2 * 13 + 2;
 constexpr int kTileAxisX = 4;   // d = (1, 0, 0): the sorted list is the cell order

@@ -310,12 +310,17 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_sort13_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
-                       c.tiles, 1);
+    // with 128 or more particles per cell on average, cells of at most 64 are
+    // rare: the 256 class takes them, one launch over all cells fewer (the
+    // 257..512 class stays: the looping kernel is slower on such cells)
+    const bool dense = n >= kDenseCells * ncell;
+    if (!dense)
+        hipLaunchKernelGGL((k_sort13_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
+                           c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                           c.tslots, c.tiles, 1);
     hipLaunchKernelGGL((k_sort13_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
-                       c.tslots, c.tiles, 65);
+                       c.tslots, c.tiles, dense ? 1 : 65);
     hipLaunchKernelGGL((k_sort13_small<512, 256>), dim3((unsigned)ncell), dim3(512), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
                        c.tslots, c.tiles, 257);
