@@ -33,11 +33,19 @@
 // every direction are compacted out of the cell's sorted lists in order.
 // Persistent workgroups take items from a device queue that lists the chunks
 // of large cells first, so uneven occupancy and many boxes of different sizes
-// share one launch.  Each wave adds its rows' sums, once per task, into its
-// own LDS array; the four arrays are summed in a fixed order at the end, so
-// the result does not depend on timing or on which workgroup took the item.
+// share one launch; the last cells of the queue may run as 2 or 4 items that
+// share out the cell's row tasks, whose sums a second kernel adds in part
+// order (so the workgroups finish together).  Each wave adds its rows' sums,
+// once per task, into its own LDS array; the four arrays are summed in a fixed
+// order at the end, so the result does not depend on timing or on which
+// workgroup took the item.
 //
-// Three sweeps share this code (the MODE template argument):
+// The set-up's searches (first_a, the own cell's window, the source tiles of
+// a block) count tiles from the first keys of every 16 sorted positions that
+// the per-cell sort leaves beside the lists.  Where a cell and its non-empty
+// neighbours share one mass the density steps run with unit masses.
+//
+// Four sweeps share this code (the MODE template argument):
 //   * kModeSorted: the density with the pruned bounds above;
 //   * kModePlain: the plain cell-list comparator on the same tiles: every
 //     receiver meets every particle of the 27 cells, in cell order, with no
