@@ -431,7 +431,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
-    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int min_cnt)
+    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int32_t *__restrict__ big,
+    int min_cnt)
 {
     __shared__ float key[PV_MAX_CELL];
     __shared__ uint16_t slot[PV_MAX_CELL];
@@ -450,6 +451,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
         }
         return;
     }
+    if (cnt > kSortSmallMax && threadIdx.x == 0) big[1 + atomicAdd(&big[0], 1)] = c;
     const BoxDesc &B = box[cell_box[c]];
     const int local = c - B.cell_off;
     const int cz = local % B.g[2];
@@ -541,12 +543,14 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
 // largest occupancy (dflags[1]) that the binning raises.
 __global__ void k_cell_box(const BoxDesc *__restrict__ box, int nbox, int64_t ncell,
                            int32_t *__restrict__ cell_box, float *__restrict__ cell_dx,
-                           uint32_t *__restrict__ dx_all, int *__restrict__ dflags)
+                           uint32_t *__restrict__ dx_all, int *__restrict__ dflags,
+                           int32_t *__restrict__ big)
 {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c == 0) {
         *dx_all = 0u;
         dflags[1] = 0;
+        big[0] = 0;
     }
     if (c >= ncell) return;
     cell_dx[c] = 0.0f;
@@ -651,7 +655,7 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
                       int *dflags)
 {
     hipLaunchKernelGGL(k_cell_box, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box, nbox,
-                       ncell, c.cell_box, c.cell_dx, c.dx_all, dflags);
+                       ncell, c.cell_box, c.cell_dx, c.dx_all, dflags, c.big);
     hipLaunchKernelGGL(k_bin_local, dim3((unsigned)plan.nblocks), dim3(kBinThreads), 0, st, c.box,
                        c.bin_blocks, pos, h, c.cellid, c.slot, c.binm, dflags);
     hipLaunchKernelGGL(k_bin_columns, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box,
@@ -676,7 +680,7 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
                        c.cell_hmax, c.cell_m, dense ? 0 : 65);
     hipLaunchKernelGGL(k_cell_finish_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                        c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax,
-                       c.cell_m, 257);
+                       c.cell_m, c.big, 257);
     return hipGetLastError();
 }
 

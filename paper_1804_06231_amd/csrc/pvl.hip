@@ -69,7 +69,7 @@ void free_dev(DevCells &d)
     void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cellid, d.slot, d.stage,
                     d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
                     d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks, d.cell_dx, d.dx_all,
-                    d.partial, d.cell_m, d.tiles};
+                    d.partial, d.cell_m, d.tiles, d.big};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DevCells();
@@ -112,6 +112,7 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.bin_blocks, NB);
     ALLOC(d.cell_dx, C);
     ALLOC(d.cell_m, C);
+    ALLOC(d.big, C + 1);
     d.tslots = pvl::tile_slots(N, C);
     ALLOC(d.tiles, pvl::kTileArrays * d.tslots);
     ALLOC(d.dx_all, 1);

@@ -92,6 +92,8 @@ struct DevCells {
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
     int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
     int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
+    int32_t *big = nullptr;       // ncell + 1: [0] count, then the cells above kSortSmallMax
+                                  // particles (written by the cell finish, any order)
     // Tile summaries of the sorted lists, written by the per-cell sorts: for
     // axis s and tile slot t = cell_start[c] / 16 + c + j of tile j of cell c,
     //   tiles[kTileTS(s)] key of position 16 j        (first of tile j from the start)
@@ -113,6 +115,10 @@ struct BinPlan {
     int64_t mtot = 0;      // entries of the count matrices
     int64_t nblocks = 0;   // chunks (workgroups of the counting kernel)
 };
+
+// Largest cell sorted with one particle per thread; larger cells are listed
+// and sorted one axis per workgroup.
+constexpr int kSortSmallMax = 512;
 
 // Mean cell occupancy from which the per-cell kernels fold their rare size
 // classes into their neighbours' launches.

@@ -17,9 +17,12 @@
 // Output per axis: the in-cell ranks (uint16) in key order and the keys (fp32).
 #include "device_util.h"
 
+#include <algorithm>
+
 namespace pvl {
 
 constexpr int kSortLdsBytes = 40 * 1024;
+constexpr int64_t kSortLargeWgs = 256;   // cells in flight of the large-cell sort
 
 __device__ __forceinline__ int sort_buckets(int cnt)
 {
@@ -158,7 +161,11 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
     if (on && (r & 15) == 0) tiles[kTileBHX * tslots + slot0 + (r >> 4)] = hx;
 }
 
-// Cells above the small sizes: G axes per pass, as many as fit the LDS.
+// Cells above kSortSmallMax particles (listed by the cell finish): one
+// workgroup per (listed cell, axis), so that a large cell's 13 sorts run side
+// by side; a grid of at most a few hundred cells by 13 axes loops over the
+// list.  The keys, the arrival slots and the bucket-order list of the axis
+// live in LDS (at most 36 KB for PV_MAX_CELL particles).
 __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restrict__ box,
                                                     const int32_t *__restrict__ cell_box,
                                                     const int32_t *__restrict__ start,
@@ -166,140 +173,119 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
                                                     const float *__restrict__ Hc, int64_t n,
                                                     uint16_t *__restrict__ sidx,
                                                     float *__restrict__ skey, int64_t tslots,
-                                                    float *__restrict__ tiles, int min_cnt)
+                                                    float *__restrict__ tiles,
+                                                    const int32_t *__restrict__ big)
 {
     __shared__ __align__(16) unsigned char lds[kSortLdsBytes];
-    __shared__ float ax_kmin[13], ax_scale[13];
-    const int c = blockIdx.x;
-    const int s0 = start[c];
-    const int cnt = start[c + 1] - s0;
-    if (cnt < min_cnt || cnt > PV_MAX_CELL) return;
-    const BoxDesc &B = box[cell_box[c]];
-    const int NB = sort_buckets(cnt);   // 128 whenever cnt <= kBlock
-    // per axis: histogram (NB u32), keys (cnt f32), the arrival-slot list (later
-    // reused for the final order) and the bucket-order list (cnt u16 each),
-    // rows rounded to 16 bytes
-    const int keyw = ((cnt * 4 + 15) & ~15) / 4;     // floats per key row
-    const int u16w = ((cnt * 2 + 15) & ~15) / 2;     // u16 per list row
-    const int per_axis = NB * 4 + keyw * 4 + 2 * u16w * 2;
-    int G = kSortLdsBytes / per_axis;
-    G = G > 13 ? 13 : (G < 1 ? 1 : G);
-    if (threadIdx.x < 13) {
-        float e[3];
-        dir_axis(threadIdx.x, e);
-        const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
-                           fminf(e[2], 0.f) * B.edge[2];
-        const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
-                           fmaxf(e[2], 0.f) * B.edge[2];
-        ax_kmin[threadIdx.x] = kmin;
-        ax_scale[threadIdx.x] = (float)NB / (kmax - kmin);
-    }
-    __syncthreads();
-
-    for (int sf = 0; sf < 13; sf += G) {
-        const int ng = 13 - sf < G ? 13 - sf : G;
-        uint32_t *hist = reinterpret_cast<uint32_t *>(lds);                     // [ng][NB]
-        float *key = reinterpret_cast<float *>(lds + (size_t)ng * NB * 4);      // [ng][keyw]
-        uint16_t *slot = reinterpret_cast<uint16_t *>(key + (size_t)ng * keyw); // [ng][u16w]
-        uint16_t *border = slot + (size_t)ng * u16w;                            // bucket order
-        uint16_t *forder = slot;                                                // final order
-        for (int t = threadIdx.x; t < ng * NB; t += blockDim.x) hist[t] = 0u;
+    __shared__ float ax_kmin, ax_scale;
+    const int s = blockIdx.y;   // the axis of this workgroup
+    const int nbig = big[0];
+    for (int item = blockIdx.x; item < nbig; item += gridDim.x) {
+        const int c = big[1 + item];
+        const int s0 = start[c];
+        const int cnt = start[c + 1] - s0;
+        const BoxDesc &B = box[cell_box[c]];
+        const int NB = sort_buckets(cnt);
+        // histogram (NB u32), keys (cnt f32), the arrival-slot list (later
+        // reused for the final order) and the bucket-order list (cnt u16
+        // each), rows rounded to 16 bytes
+        const int keyw = ((cnt * 4 + 15) & ~15) / 4;
+        const int u16w = ((cnt * 2 + 15) & ~15) / 2;
+        uint32_t *hist = reinterpret_cast<uint32_t *>(lds);
+        float *key = reinterpret_cast<float *>(lds + (size_t)NB * 4);
+        uint16_t *slot = reinterpret_cast<uint16_t *>(key + keyw);
+        uint16_t *border = slot + u16w;
+        uint16_t *forder = slot;
+        if (threadIdx.x == 0) {
+            float e[3];
+            dir_axis(s, e);
+            const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
+                               fminf(e[2], 0.f) * B.edge[2];
+            const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
+                               fmaxf(e[2], 0.f) * B.edge[2];
+            ax_kmin = kmin;
+            ax_scale = (float)NB / (kmax - kmin);
+        }
+        for (int t = threadIdx.x; t < NB; t += blockDim.x) hist[t] = 0u;
         __syncthreads();
-        // keys of every axis in the pass from one position read per particle;
-        // the histogram atomic gives each key its arrival slot in its bucket
+        const float kmin = ax_kmin, scale = ax_scale;
+        // the key of every particle; the histogram atomic gives each key its
+        // arrival slot in its bucket
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
             const float4 p = xyzm[s0 + r];
-            for (int g = 0; g < ng; ++g) {
-                const float k = proj_key(p.x, p.y, p.z, sf + g);
-                const int b = key_bucket(k, ax_kmin[sf + g], ax_scale[sf + g], NB);
-                key[g * keyw + r] = k;
-                slot[g * u16w + r] = (uint16_t)atomicAdd(&hist[g * NB + b], 1u);
-            }
+            const float k = proj_key(p.x, p.y, p.z, s);
+            key[r] = k;
+            slot[r] = (uint16_t)atomicAdd(&hist[key_bucket(k, kmin, scale, NB)], 1u);
         }
         __syncthreads();
-        // exclusive scan of every axis' histogram (one wave per axis)
-        {
-            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        // exclusive scan of the histogram (first wavefront)
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
             const int per = (NB + 63) >> 6;
-            for (int g = wave; g < ng; g += (int)(blockDim.x >> 6)) {
-                uint32_t *hh = hist + g * NB;
-                uint32_t loc = 0;
-                for (int k = 0; k < per; ++k) {
-                    const int q = lane * per + k;
-                    if (q < NB) loc += hh[q];
-                }
-                uint32_t inc = loc;
-                for (int off = 1; off < 64; off <<= 1) {
-                    const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
-                    if (lane >= off) inc += o;
-                }
-                uint32_t run = inc - loc;
-                for (int k = 0; k < per; ++k) {
-                    const int q = lane * per + k;
-                    if (q < NB) {
-                        const uint32_t v = hh[q];
-                        hh[q] = run;
-                        run += v;
-                    }
+            uint32_t loc = 0;
+            for (int k = 0; k < per; ++k) {
+                const int q = lane * per + k;
+                if (q < NB) loc += hist[q];
+            }
+            uint32_t inc = loc;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+                if (lane >= off) inc += o;
+            }
+            uint32_t run = inc - loc;
+            for (int k = 0; k < per; ++k) {
+                const int q = lane * per + k;
+                if (q < NB) {
+                    const uint32_t v = hist[q];
+                    hist[q] = run;
+                    run += v;
                 }
             }
         }
         __syncthreads();
         // bucket start + arrival slot: the list of every bucket's members
-        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-            for (int g = 0; g < ng; ++g) {
-                const int b = key_bucket(key[g * keyw + r], ax_kmin[sf + g], ax_scale[sf + g], NB);
-                border[g * u16w + (int)hist[g * NB + b] + slot[g * u16w + r]] = (uint16_t)r;
-            }
-        }
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x)
+            border[(int)hist[key_bucket(key[r], kmin, scale, NB)] + slot[r]] = (uint16_t)r;
         __syncthreads();
         // exact rank: bucket start + bucket mates with a smaller (key, rank);
         // the members of bucket b sit at [hist[b], hist[b+1])
         for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-            for (int g = 0; g < ng; ++g) {
-                const float *kk = key + g * keyw;
-                const uint16_t *bo = border + g * u16w;
-                const float k = kk[r];
-                const int b = key_bucket(k, ax_kmin[sf + g], ax_scale[sf + g], NB);
-                const int q0 = (int)hist[g * NB + b];
-                const int q1 = b + 1 < NB ? (int)hist[g * NB + b + 1] : cnt;
-                int rank = q0;
-                for (int q = q0; q < q1; ++q) {
-                    const int r2 = bo[q];
-                    const float k2 = kk[r2];
-                    rank += (k2 < k) || (k2 == k && r2 < r);
-                }
-                forder[g * u16w + rank] = (uint16_t)r;
+            const float k = key[r];
+            const int b = key_bucket(k, kmin, scale, NB);
+            const int q0 = (int)hist[b];
+            const int q1 = b + 1 < NB ? (int)hist[b + 1] : cnt;
+            int rank = q0;
+            for (int q = q0; q < q1; ++q) {
+                const int r2 = border[q];
+                const float k2 = key[r2];
+                rank += (k2 < k) || (k2 == k && r2 < r);
             }
+            forder[rank] = (uint16_t)r;
         }
         __syncthreads();
-        // coalesced output of the sorted lists and of the tiles' first keys
+        // coalesced output of the sorted list and of the tiles' first keys
         const int64_t slot0 = tile_slot(s0, c, 0);
-        for (int g = 0; g < ng; ++g) {
-            const int s = sf + g;
-            const float *kk = key + g * keyw;
-            const uint16_t *fo = forder + g * u16w;
-            const size_t o = (size_t)s * (size_t)n + (size_t)s0;
-            for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
-                const int r = fo[q];
-                const float kq = kk[r];
-                sidx[o + q] = (uint16_t)r;
-                skey[o + q] = kq;
-                const int re = cnt - 1 - q;
-                if ((q & 15) == 0) tiles[kTileTS(s) * tslots + slot0 + (q >> 4)] = kq;
-                if ((re & 15) == 0) tiles[kTileTE(s) * tslots + slot0 + (re >> 4)] = kq;
-                if (s == kTileAxisX && ((q & 15) == 15 || re == 0))
-                    tiles[kTileTLX * tslots + slot0 + (q >> 4)] = kq;
+        const size_t o = (size_t)s * (size_t)n + (size_t)s0;
+        for (int q = threadIdx.x; q < cnt; q += blockDim.x) {
+            const int r = forder[q];
+            const float kq = key[r];
+            sidx[o + q] = (uint16_t)r;
+            skey[o + q] = kq;
+            const int re = cnt - 1 - q;
+            if ((q & 15) == 0) tiles[kTileTS(s) * tslots + slot0 + (q >> 4)] = kq;
+            if ((re & 15) == 0) tiles[kTileTE(s) * tslots + slot0 + (re >> 4)] = kq;
+            if (s == kTileAxisX && ((q & 15) == 15 || re == 0))
+                tiles[kTileTLX * tslots + slot0 + (q >> 4)] = kq;
+        }
+        // largest cut-off of each tile of the cell order (once per cell)
+        if (s == kTileAxisX) {
+            for (int j = threadIdx.x; j * 16 < cnt; j += blockDim.x) {
+                float hx = 0.0f;
+                for (int q = 16 * j; q < min(16 * j + 16, cnt); ++q) hx = fmaxf(hx, Hc[s0 + q]);
+                tiles[kTileBHX * tslots + slot0 + j] = hx;
             }
         }
         __syncthreads();
-    }
-    // largest cut-off of each tile of the cell order
-    const int64_t slot0 = tile_slot(s0, c, 0);
-    for (int j = threadIdx.x; j * 16 < cnt; j += blockDim.x) {
-        float hx = 0.0f;
-        for (int q = 16 * j; q < min(16 * j + 16, cnt); ++q) hx = fmaxf(hx, Hc[s0 + q]);
-        tiles[kTileBHX * tslots + slot0 + j] = hx;
     }
 }
 
@@ -324,9 +310,11 @@ hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t n
     hipLaunchKernelGGL((k_sort13_small<512, 256>), dim3((unsigned)ncell), dim3(512), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
                        c.tslots, c.tiles, 257);
-    hipLaunchKernelGGL(k_sort13_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
+    // the listed large cells, one workgroup per (cell, axis)
+    const unsigned big_wgs = (unsigned)std::min<int64_t>(ncell, kSortLargeWgs);
+    hipLaunchKernelGGL(k_sort13_large, dim3(big_wgs, 13), dim3(kBlock), 0, st, c.box,
                        c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
-                       c.tiles, 513);
+                       c.tiles, c.big);
     return hipGetLastError();
 }
 
