@@ -18,6 +18,7 @@
 #include "device_util.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace pvl {
 
@@ -58,24 +59,16 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
                                                       float *__restrict__ tiles, int min_cnt)
 {
     __shared__ uint32_t hist[13][NB];
-    __shared__ uint16_t border[13][MAXC];
+    // in-cell ranks in bucket order: bytes while they fit (smaller LDS, more
+    // cells per compute unit)
+    using rank_t = typename std::conditional<MAXC <= 256, uint8_t, uint16_t>::type;
+    __shared__ rank_t border[13][MAXC];
     __shared__ float bkey[13][MAXC];
-    __shared__ float ax_kmin[13], ax_scale[13];
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
     if (cnt < min_cnt || cnt > MAXC) return;
     const BoxDesc &B = box[cell_box[c]];
-    if (threadIdx.x < 13) {
-        float e[3];
-        dir_axis(threadIdx.x, e);
-        const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
-                           fminf(e[2], 0.f) * B.edge[2];
-        const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
-                           fmaxf(e[2], 0.f) * B.edge[2];
-        ax_kmin[threadIdx.x] = kmin;
-        ax_scale[threadIdx.x] = (float)NB / (kmax - kmin);
-    }
     for (int t = threadIdx.x; t < 13 * NB; t += blockDim.x) (&hist[0][0])[t] = 0u;
     const int r = threadIdx.x;
     const bool on = r < cnt;
@@ -87,8 +80,17 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
     uint32_t sl[13];
 #pragma unroll
     for (int g = 0; g < 13; ++g) {
+        // the cell's key range on axis g cut into NB buckets (any monotone map
+        // of the key will do: each key's bucket is computed once)
+        float e[3];
+        dir_axis(g, e);
+        const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
+                           fminf(e[2], 0.f) * B.edge[2];
+        const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
+                           fmaxf(e[2], 0.f) * B.edge[2];
+        const float scale = (float)NB * __builtin_amdgcn_rcpf(kmax - kmin);
         k[g] = proj_key(p.x, p.y, p.z, g);
-        b[g] = key_bucket(k[g], ax_kmin[g], ax_scale[g], NB);
+        b[g] = key_bucket(k[g], kmin, scale, NB);
     }
     if (on) {
 #pragma unroll
@@ -128,7 +130,7 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
 #pragma unroll
         for (int g = 0; g < 13; ++g) {
             q0[g] = (int)hist[g][b[g]];
-            border[g][q0[g] + (int)sl[g]] = (uint16_t)r;
+            border[g][q0[g] + (int)sl[g]] = (rank_t)r;
             bkey[g][q0[g] + (int)sl[g]] = k[g];
         }
     }
