@@ -200,6 +200,14 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
  *                         persistent workgroups when there are at least
  *                         twice as many cells as workgroups, else none.
  *                         Default 0.
+ *   PV_PARAM_GROUP        small cells per work item, at most (1..8): each
+ *                         row of cells along z is cut into blocks of this
+ *                         many cells, and consecutive single-chunk cells of a
+ *                         block whose particles fit one chunk together run as
+ *                         one work item (1: one cell per item).  Results may
+ *                         differ in the last bits, since the receivers' sums
+ *                         are taken in another order.  The plain sweep
+ *                         always takes one cell per item.  Default 4.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,
@@ -208,6 +216,7 @@ typedef enum {
     PV_PARAM_CHUNK = 4,
     PV_PARAM_TAIL_PARTS = 5,
     PV_PARAM_TAIL_CELLS = 6,
+    PV_PARAM_GROUP = 7,
     PV_PARAM_ADJOINT = 16,
     PV_PARAM_PLAIN = 32
 } pv_param;
@@ -220,8 +229,9 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value);
  * on `cells` for every combination of the
  * parameters above (chunk 64/128/256, 1..8 workgroups per compute unit, task
  * order, receiver order), then the tail split (2 or 4 parts of the last 256,
- * 512 or 1024 cells) on top of the best, `reps` timed runs each after one
- * warm-up, and keeps the fastest on the context.  times_ms (host, may be NULL) receives the mean
+ * 512 or 1024 cells) and then the small-cell groups (1, 2, 4 or 8 cells per
+ * item; not for the plain sweep) on top of the best, `reps` timed runs each
+ * after one warm-up, and keeps the fastest on the context.  times_ms (host, may be NULL) receives the mean
  * time of the setting in place before the call and of the chosen one.  The
  * kernels write into temporary device buffers that the call allocates and
  * frees; the call synchronises the context's stream and must not be

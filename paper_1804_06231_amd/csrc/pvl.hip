@@ -551,6 +551,11 @@ pv_status pv_set_param(pv_ctx *ctx, int param, int value)
             return fail(ctx, PV_EINVAL, "tail_cells must be in 0..2048");
         t.tail_cells = value;
         return PV_OK;
+    case PV_PARAM_GROUP:
+        if (value < 1 || value > pvl::kGroupMax)
+            return fail(ctx, PV_EINVAL, "group must be 1..8");
+        t.group = value;
+        return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -566,6 +571,7 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value)
     case PV_PARAM_CHUNK: *value = t.chunk; return PV_OK;
     case PV_PARAM_TAIL_PARTS: *value = t.tail_parts; return PV_OK;
     case PV_PARAM_TAIL_CELLS: *value = t.tail_cells; return PV_OK;
+    case PV_PARAM_GROUP: *value = t.group; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -657,6 +663,22 @@ pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const floa
                     best = t;
                 }
             }
+    }
+    // then the small-cell groups (the plain sweep takes one cell per item)
+    if (!plain) {
+        const pvl::SweepTuning base = best;
+        static const int groups[] = {1, 2, 4, 8};
+        for (int gsz : groups) {
+            if (e != hipSuccess || gsz == base.group) continue;
+            pvl::SweepTuning t = base;
+            t.group = gsz;
+            float ms = 0.0f;
+            e = time_of(t, &ms);
+            if (e == hipSuccess && ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

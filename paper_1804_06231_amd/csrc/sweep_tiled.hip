@@ -75,7 +75,13 @@ constexpr int kModeLJ = 3;
 constexpr int kChunk = 256;                    // largest receivers per work item
 static_assert(kChunk == kTailRecv, "tail slots hold one chunk");
 constexpr int kChunkMin = 32;                  // smallest (sizes the queue)
-constexpr int kMaxTasks = 27 * (kChunk / 16);  // task slots per item
+// Cells per work item that a mode's LDS holds: the plain sweep takes one cell
+// per item (its smaller LDS then leaves room for five workgroups per compute
+// unit), the others up to kGroupMax.
+constexpr int group_cap(int mode) { return mode == kModePlain ? 1 : kGroupMax; }
+// task slots per item: 27 directions of at most chunk / 16 blocks per cell,
+// plus one partial block per (cell, direction) when several cells share it
+constexpr int max_tasks(int G) { return 27 * (kChunk / 16 + (G > 1 ? G : 0)); }
 constexpr int kMaxRecv = 26 * kChunk;          // compacted receiver lists per item
 constexpr int kSelfAxis = 4;                   // d = (1, 0, 0): cell order is x order
 constexpr int kReachBuckets = 16;              // reach levels of the receiver ordering
@@ -227,11 +233,12 @@ __device__ __forceinline__ void lj_interact(float dx, float dy, float dz, float 
         if (r2 < H2) tile_interact_unit(r2, invH2, acc);                  \
     }
 
-// Task word: bits 0-8 source tiles, 9-13 receiver block, 14-18 direction
-// (0..25 neighbour, 26 = own cell), 19-27 first source tile.
-__device__ __forceinline__ uint32_t pack_task(int dir, int blk, int nt, int t0)
+// Task word: bits 0-8 source tiles, 9-13 receiver block, 14-21 the item's
+// cell and direction (27 g + d: d 0..25 neighbour, 26 = own cell), 22-30
+// first source tile.
+__device__ __forceinline__ uint32_t pack_task(int gd, int blk, int nt, int t0)
 {
-    return (uint32_t)nt | ((uint32_t)blk << 9) | ((uint32_t)dir << 14) | ((uint32_t)t0 << 19);
+    return (uint32_t)nt | ((uint32_t)blk << 9) | ((uint32_t)gd << 14) | ((uint32_t)t0 << 22);
 }
 
 __device__ __forceinline__ void nb_offset(int dir, int &dx, int &dy, int &dz)
@@ -302,18 +309,24 @@ struct SweepArgs {
     int chunk;           // receivers per work item: a multiple of 16 in [kChunkMin, kChunk]
 };
 
+template <int G>
 struct SweepLds {
     float4 acc[4][kChunk];       // per-wave receiver sums; aliased during set-up
     uint16_t rlist[kMaxRecv];    // receivers per direction (compacted or reach-ordered)
-    uint32_t tasks[kMaxTasks];
-    uint16_t torder[kMaxTasks];  // also the direction of each task (bytes) until ordered
-    int n_act[27];
-    int act_cell[26];
-    int task_off[28];
-    int recv_off[27];
-    int flag;
+    uint32_t tasks[max_tasks(G)];
+    uint16_t torder[max_tasks(G)];  // also each task's (cell, direction) (bytes) until ordered
+    // per (cell g of the item, direction d): entry 27 g + d (26 g + d for the
+    // neighbour directions alone)
+    int n_act[27 * G];
+    int act_cell[26 * G];
+    int task_off[27 * G + 1];
+    int recv_off[26 * G];
+    // per cell of the item: first particle, count, largest cut-off,
+    // displacement bound
+    int gsa[G], gna[G];
+    float ghmax[G], gdx[G];
+    int mbad[4];         // per wave: a mass differs from the first cell's
     int item;
-    float mass;          // the item's common mass (NaN: masses differ)
 };
 
 // Outputs of receiver p (cell order) from its sums over all sources: the
@@ -353,66 +366,123 @@ __device__ __forceinline__ void finalize_receiver(const SweepArgs &A, int p, flo
     }
 }
 
-// One work item: receivers [chunk * A.chunk, ...) of cell a.  An item split
-// into nparts > 1 parts (tail slot `slot`) runs every nparts-th group of
-// tasks and leaves its sums in A.partial for k_tail_combine.
+// Exclusive prefix sums over entries k < m (m <= 256) on one wavefront, entry
+// k in lane k % 64 of column k / 64: emit(k, offset, value(k)) for every
+// entry; returns the total (wavefront-uniform).
+template <class V, class E>
+__device__ __forceinline__ int wave_scan(int m, int lane, V value, E emit)
+{
+    int run = 0;   // sum of the earlier columns
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (u * 64 >= m) break;
+        const int k = u * 64 + lane;
+        const int c = k < m ? value(k) : 0;
+        int inc = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(inc, o);
+            if (lane >= o) inc += v;
+        }
+        if (k < m) emit(k, run + inc - c, c);
+        run += __shfl(inc, 63);
+    }
+    return run;
+}
+
+// One work item.  chunk >= 0: receivers [chunk * A.chunk, ...) of cell a; an
+// item split into nparts > 1 parts (tail slot `slot`) runs every nparts-th
+// group of tasks and leaves its sums in A.partial for k_tail_combine.
+// chunk < 0: the -chunk consecutive cells a, a + 1, ... of one row of cells
+// along z, each swept whole (small cells whose particles fit one chunk
+// together).  The item's receivers are numbered in cell order from the
+// first receiver's position.
 template <int MODE>
-__device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, int part,
-                           int nparts, int slot)
+__device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int a, int chunk,
+                           int part, int nparts, int slot)
 {
     constexpr bool PLAIN = MODE == kModePlain;
     constexpr bool ADJ = MODE == kModeAdjoint;
     constexpr bool LJ = MODE == kModeLJ;
+    static_assert(kBlock == 256, "four wavefronts");
     const int64_t n = A.n;
-    const int sa = A.start[a];
-    const int na = A.start[a + 1] - sa;
+    const int ncg = chunk < 0 ? -chunk : 1;   // cells of the item (the queue keeps
+                                              // it within group_cap(MODE))
+    if (chunk < 0) chunk = 0;
+    const int sa0 = A.start[a];
+    const int na0 = A.start[a + 1] - sa0;
     const int r_lo = chunk * A.chunk;
-    const int r_hi = min(r_lo + A.chunk, na);
-    const int nr = r_hi - r_lo;
-    const bool whole = na <= A.chunk;
+    // the item's receivers: positions [base, base + nrt) of the cell order
+    const int base = sa0 + r_lo;
+    const int nrt = ncg > 1 ? A.start[a + ncg] - sa0 : min(r_lo + A.chunk, na0) - r_lo;
+    const bool whole = na0 <= A.chunk;   // grouped cells are single-chunk
     const BoxDesc &B = A.box[A.cell_box[a]];
     const CellGeom ga = cell_geom(B, a);
     const float slack = 1.52587890625e-5f * (B.edge[0] + B.edge[1] + B.edge[2]);
-    const float hmax_a = __uint_as_float(A.cell_hmax[a]);
-    // Section 2: sorted lists stay usable after the particles move, with every
-    // projected bound widened by the displacements; the cells stay usable while
-    // H + dx_i + dx_j fits the edge
-    const float dx_a = A.cell_dx[a];
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        const float dx_all = __uint_as_float(*A.dx_all);
-        const float emin = fminf(B.edge[0], fminf(B.edge[1], B.edge[2]));
-        if (dx_all > 0.0f && hmax_a + dx_a + dx_all > emin) atomicOr(A.dflags, kErrDrift);
-    }
+    // the thread index, opaque to the compiler: values derived from it are
+    // then formed per item, not kept in registers across the item loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
     const int wave = tid >> 6, lane = tid & 63;
     const uint16_t *sidx = A.sidx;
     const float *skey = A.skey;
     const int64_t ts = A.tslots;
     const float *tiles = A.tiles;
-    const int ntile_a = (na + 15) >> 4;
-    const int64_t slot_a = tile_slot(sa, a, 0);
+    // cell g of the item: g steps along z in the first cell's row
+    auto geom_of = [&](int g) {
+        CellGeom c = ga;
+        c.cz += g;
+        c.oz = (float)c.cz * B.edge[2];
+        return c;
+    };
 
-    // receivers of each direction that can have a candidate (first_a), whole
-    // cell, rounded up to whole tiles of the interface-first order (the extra
-    // receivers have no candidate either; they only fill their row)
+    // per cell of the item: first particle, count, largest cut-off and
+    // displacement bound
+    if (tid < ncg) {
+        const int c = a + tid;
+        const int s0 = A.start[c];
+        const float hm = __uint_as_float(A.cell_hmax[c]);
+        const float dxc = A.cell_dx[c];
+        L.gsa[tid] = s0;
+        L.gna[tid] = A.start[c + 1] - s0;
+        L.ghmax[tid] = hm;
+        L.gdx[tid] = dxc;
+        // Section 2: sorted lists stay usable after the particles move, with
+        // every projected bound widened by the displacements; the cells stay
+        // usable while H + dx_i + dx_j fits the edge
+        const float dx_all = __uint_as_float(*A.dx_all);
+        const float emin = fminf(B.edge[0], fminf(B.edge[1], B.edge[2]));
+        if (dx_all > 0.0f && hm + dxc + dx_all > emin) atomicOr(A.dflags, kErrDrift);
+    }
+
+    // receivers of each (cell, direction) that can have a candidate (first_a),
+    // whole cell, rounded up to whole tiles of the interface-first order (the
+    // extra receivers have no candidate either; they only fill their row)
     float mb = INFINITY;   // the neighbour's common mass (see DevCells::cell_m)
-    if (tid < 26) {
+    if (tid < 26 * ncg) {
+        const int g = tid / 26, d = tid - 26 * g;
+        const int c = a + g;
+        const int sa = A.start[c], na = A.start[c + 1] - sa;
+        const float hmax_a = __uint_as_float(A.cell_hmax[c]);
+        const float dx_a = A.cell_dx[c];
         int dx, dy, dz;
-        nb_offset(tid, dx, dy, dz);
+        nb_offset(d, dx, dy, dz);
         float sx, sy, sz;
-        int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
+        int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
         int sb = A.start[b], nb = A.start[b + 1] - sb;
         if (!ADJ && !LJ) mb = A.cell_m[b];
         int act = 0;
         if (PLAIN) {
             act = nb > 0 ? na : 0;
-        } else if (nb > 0) {
+        } else if (nb > 0 && na > 0) {
             int sign;
             int s = dir_canon(dx, dy, dz, &sign);
             float e[3];
             dir_axis(s, e);
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
+            const int64_t slot_a = tile_slot(sa, c, 0);
             const int64_t slot_b = tile_slot(sb, b, 0);
+            const int ntile_a = (na + 15) >> 4;
             // the adjoint also keeps pairs decided by the source's cut-off
             const float reach = (ADJ ? fmaxf(hmax_a, __uint_as_float(A.cell_hmax[b])) : hmax_a) +
                                 (dx_a + A.cell_dx[b]);
@@ -431,36 +501,42 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
         }
         L.act_cell[tid] = act;
     }
-    // equal masses: when this cell and every non-empty neighbour share one
-    // mass m, the density sums are m times the unit-mass sums, and the steps
-    // need neither the sources' masses nor a separate density sum
+    // equal masses: when the item's cells and every non-empty neighbour share
+    // one mass m, the density sums are m times the unit-mass sums, and the
+    // steps need neither the sources' masses nor a separate density sum
+    const float ma = (!ADJ && !LJ) ? A.cell_m[a] : 0.0f;
     if constexpr (!ADJ && !LJ) {
-        if (wave == 0) {
-            const float ma = A.cell_m[a];
-            const bool ok = lane >= 26 || mb == ma || mb == INFINITY;
-            const uint64_t bad = __ballot(!ok);
-            if (lane == 0)
-                L.mass = (bad == 0 && ma == ma && ma != INFINITY) ? ma : __builtin_nanf("");
+        bool ok = mb == ma || mb == INFINITY;
+        if (tid >= 26 * ncg && tid < 27 * ncg) {
+            const float mc = A.cell_m[a + (tid - 26 * ncg)];
+            ok = mc == ma || mc == INFINITY;
         }
+        const uint64_t bad = __ballot(!ok);
+        if (lane == 0) L.mbad[wave] = bad != 0;
     }
     __syncthreads();
+    float mass = __builtin_nanf("");
+    if constexpr (!ADJ && !LJ) {
+        if ((L.mbad[0] | L.mbad[1] | L.mbad[2] | L.mbad[3]) == 0 && ma == ma && ma != INFINITY)
+            mass = ma;
+    }
 
-    // active receivers of this chunk, per direction
+    // active receivers of this item, per (cell, direction): n_act[27 g + d]
     bool listed = false;   // receivers taken from L.rlist
     if (PLAIN) {
-        if (tid < 26) L.n_act[tid] = L.act_cell[tid] > 0 ? nr : 0;
-    } else if (whole) {
-        if (tid < 26) L.n_act[tid] = L.act_cell[tid];
-        if (tid == 0) {
-            int roff = 0;
-            for (int d = 0; d < 26; ++d) {
-                L.recv_off[d] = roff;
-                roff += L.act_cell[d];
-            }
+        if (tid < 26 * ncg) {
+            const int g = tid / 26;
+            L.n_act[tid + g] = L.act_cell[tid] > 0 ? (ncg > 1 ? L.gna[g] : nrt) : 0;
         }
-        __syncthreads();
+    } else if (whole) {
+        if (tid < 26 * ncg) L.n_act[tid + tid / 26] = L.act_cell[tid];
         listed = !ADJ && A.reach_order;
         if (listed) {
+            // each (cell, direction) list at the sum of the ones before it
+            if (wave == 0)
+                wave_scan(26 * ncg, lane, [&](int k) { return L.act_cell[k]; },
+                          [&](int k, int off, int) { L.recv_off[k] = off; });
+            __syncthreads();
             // Receivers of a face direction are ordered by how far past the
             // shared face their cut-off reaches (key + H toward a neighbour ahead
             // on the axis, H - key toward one behind), quantised to
@@ -469,19 +545,23 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             // stable counting sort made of wavefront ballots (one wavefront per
             // direction, no atomics: the order is deterministic).  Edge and
             // corner directions keep the interface-first key order.
-            for (int d = wave; d < 26; d += (int)(blockDim.x >> 6)) {
-                const int act = L.act_cell[d];
+            for (int gd = wave; gd < 26 * ncg; gd += (int)(blockDim.x >> 6)) {
+                const int g = gd / 26, d = gd - 26 * g;
+                const int sa = L.gsa[g], na = L.gna[g];
+                const float hmax_a = L.ghmax[g];
+                const int act = L.act_cell[gd];
                 int dx, dy, dz, sign;
                 nb_offset(d, dx, dy, dz);
                 const int s = dir_canon(dx, dy, dz, &sign);
                 const float *ka = skey + (size_t)s * n + sa;
                 const uint16_t *il = sidx + (size_t)s * n + sa;
-                uint16_t *out = L.rlist + L.recv_off[d];
+                uint16_t *out = L.rlist + L.recv_off[gd];
                 const bool face = (dx != 0) + (dy != 0) + (dz != 0) == 1;
                 if (!face) {
                     for (int q = lane; q < act; q += 64) out[q] = il[sign > 0 ? na - 1 - q : q];
                     continue;
                 }
+                if (act == 0) continue;
                 const float lo = sign > 0 ? ka[0] : -ka[na - 1];
                 const float hi = (sign > 0 ? ka[na - 1] : -ka[0]) + hmax_a;
                 const float scale = (float)kReachBuckets / fmaxf(hi - lo, 1e-30f);
@@ -526,27 +606,29 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             }
         }
     } else {
-        // compact, in interface-first order, the active receivers that belong to
-        // this chunk (in-cell rank in [r_lo, r_hi)): one wavefront per direction,
-        // ballots over the direction's list (four loads in flight per lane),
-        // into the direction's own slot of chunk entries (a direction keeps at
-        // most the chunk's receivers), so the directions need no barrier or
-        // prefix between them
+        // one cell larger than a chunk: compact, in interface-first order, the
+        // active receivers that belong to this chunk (in-cell rank in [r_lo,
+        // r_lo + nrt)): one wavefront per direction, ballots over the
+        // direction's list (four loads in flight per lane), into the
+        // direction's own slot of chunk entries (a direction keeps at most the
+        // chunk's receivers), so the directions need no barrier or prefix
+        // between them
         listed = true;
+        const int r_hi = r_lo + nrt;
         for (int d = wave; d < 26; d += (int)(blockDim.x >> 6)) {
             const int act = L.act_cell[d];
             int dx, dy, dz, sign;
             nb_offset(d, dx, dy, dz);
             const int s = dir_canon(dx, dy, dz, &sign);
-            const uint16_t *il = sidx + (size_t)s * n + sa;
+            const uint16_t *il = sidx + (size_t)s * n + sa0;
             uint16_t *out = L.rlist + d * A.chunk;
             int cnt = 0;   // wavefront-uniform
-            for (int base = 0; base < act; base += 4 * 64) {
+            for (int q0 = 0; q0 < act; q0 += 4 * 64) {
                 int iv[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const int q = base + u * 64 + lane;
-                    iv[u] = q < act ? (int)il[sign > 0 ? na - 1 - q : q] : -1;
+                    const int q = q0 + u * 64 + lane;
+                    iv[u] = q < act ? (int)il[sign > 0 ? na0 - 1 - q : q] : -1;
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -565,32 +647,34 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             }
         }
     }
-    if (tid == 0) L.n_act[26] = nr;
+    if (tid < ncg) L.n_act[27 * tid + 26] = ncg > 1 ? L.gna[tid] : nrt;
     uint8_t *tdir = reinterpret_cast<uint8_t *>(L.torder);
     __syncthreads();
-    // tasks (blocks of 16 receivers) per direction, their offsets by a scan
-    // over the first wavefront's lanes, and the direction of every task
+    // tasks (blocks of 16 receivers) per (cell, direction), their offsets by a
+    // scan on the first wavefront, and the (cell, direction) of every task
+    const int ne = 27 * ncg;
     if (wave == 0) {
-        const int nt_d = lane < 27 ? (L.n_act[lane] + 15) >> 4 : 0;
-        int inc = nt_d;
-#pragma unroll
-        for (int o = 1; o < 32; o <<= 1) {
-            const int v = __shfl_up(inc, o);
-            if (lane >= o) inc += v;
-        }
-        if (lane < 27) {
-            L.task_off[lane + 1] = inc;
-            for (int t = inc - nt_d; t < inc; ++t) tdir[t] = (uint8_t)lane;
-        }
-        if (lane == 0) L.task_off[0] = 0;
+        const int tot = wave_scan(
+            ne, lane, [&](int k) { return (L.n_act[k] + 15) >> 4; },
+            [&](int k, int off, int c) {
+                L.task_off[k] = off;
+                for (int t = off; t < off + c; ++t) tdir[t] = (uint8_t)k;
+            });
+        if (lane == 0) L.task_off[ne] = tot;
     }
     __syncthreads();
-    const int ntask = L.task_off[27];
+    const int ntask = L.task_off[ne];
 
     // source tiles of every task: the paper's bound for the block of receivers
     for (int t = tid; t < ntask; t += blockDim.x) {
-        const int dir = tdir[t];
-        const int blk = t - L.task_off[dir];
+        const int gd = tdir[t];
+        const int g = gd / 27, dir = gd - 27 * g;
+        const int blk = t - L.task_off[gd];
+        const int c = a + g;
+        const int sa = L.gsa[g], na = L.gna[g];
+        const int64_t slot_a = tile_slot(sa, c, 0);
+        const int ntile_a = (na + 15) >> 4;
+        const float hmax_a = L.ghmax[g], dx_a = L.gdx[g];
         int nt, t0 = 0;
         if (PLAIN) {
             int nb = na;
@@ -598,7 +682,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
                 int dx, dy, dz;
                 nb_offset(dir, dx, dy, dz);
                 float sx, sy, sz;
-                int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
+                int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
                 nb = A.start[b + 1] - A.start[b];
             }
             nt = (nb + 15) >> 4;
@@ -620,7 +704,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             int dx, dy, dz;
             nb_offset(dir, dx, dy, dz);
             float sx, sy, sz;
-            int b = neighbour(B, ga, dx, dy, dz, sx, sy, sz);
+            int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
             int sb = A.start[b], nb = A.start[b + 1] - sb;
             int sign;
             int s = dir_canon(dx, dy, dz, &sign);
@@ -629,7 +713,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
             const float *ka = skey + (size_t)s * n + sa;
             const uint16_t *il = sidx + (size_t)s * n + sa;
-            const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[dir]);
+            const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[gd]);
             const float hmax_b = __uint_as_float(A.cell_hmax[b]);
             const float mg = dx_a + A.cell_dx[b];
             // block reach: the largest key + H (ahead) or smallest key - H (behind);
@@ -640,7 +724,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             for (int g0 = r0; g0 < r1; g0 += 8) {
                 float kv[8], hv[8];
                 if (listed) {
-                    const uint16_t *rl = L.rlist + L.recv_off[dir];
+                    const uint16_t *rl = L.rlist + L.recv_off[26 * g + dir];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const int ia = rl[min(g0 + u, r1 - 1)];
@@ -678,7 +762,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
                 nt = prefix_count<2>(tiles + kTileTE(s) * ts + slot_b, ntile_b, T);
             }
         }
-        L.tasks[t] = pack_task(dir, blk, nt, t0);
+        L.tasks[t] = pack_task(gd, blk, nt, t0);
     }
     __syncthreads();
     // longest tasks first, so the four rows of a wave carry similar loads: a
@@ -730,35 +814,39 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
     const int row = lane >> 4;
     const int l16 = lane & 15;
     for (int gp = wave; (part + nparts * gp) * 4 < ntask; gp += 4) {
-        const int g = part + nparts * gp;
-        const int t = g * 4 + row;
+        const int tg = part + nparts * gp;
+        const int t = tg * 4 + row;
         const bool row_valid = t < ntask;
         const uint32_t tw = row_valid ? L.tasks[L.torder[t]] : 0u;
         const int nt = row_valid ? (int)(tw & 511u) : 0;
         const int blk = (int)((tw >> 9) & 31u);
-        const int dir = (int)((tw >> 14) & 31u);
-        const int t0 = (int)(tw >> 19);
+        const int gd = (int)((tw >> 14) & 255u);
+        const int t0 = (int)(tw >> 22);
+        const int g = gd / 27, dir = gd - 27 * g;
+        const int sa = L.gsa[g], na = L.gna[g];
         // receiver of this lane and the source list of its row
         int dx = 0, dy = 0, dz = 0, sb = sa, nb = na, sign = 1, s = kSelfAxis;
         float shx = 0.f, shy = 0.f, shz = 0.f;
         if (dir < 26) {
             nb_offset(dir, dx, dy, dz);
-            int b = neighbour(B, ga, dx, dy, dz, shx, shy, shz);
+            int b = neighbour(B, geom_of(g), dx, dy, dz, shx, shy, shz);
             sb = A.start[b];
             nb = A.start[b + 1] - sb;
             s = dir_canon(dx, dy, dz, &sign);
         }
         const int r = blk * 16 + l16;
-        const bool recv_ok = row_valid && r < L.n_act[dir];
+        const bool recv_ok = row_valid && r < L.n_act[gd];
         int ia = 0;
         if (recv_ok) {
             if (PLAIN || dir == 26) ia = r_lo + r;
-            else if (listed) ia = L.rlist[L.recv_off[dir] + r];
+            else if (listed) ia = L.rlist[L.recv_off[26 * g + dir] + r];
             else if (sign > 0) ia = sidx[(size_t)s * n + sa + (na - 1 - r)];
             else ia = sidx[(size_t)s * n + sa + r];
         }
-        const float4 pi = recv_ok ? A.xyzm[sa + ia] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float Hi = recv_ok ? A.Hc[sa + ia] : 0.0f;
+        const int pr = sa + ia;      // the receiver's position in the cell order
+        const int ai = pr - base;    // and in the item's sums
+        const float4 pi = recv_ok ? A.xyzm[pr] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float Hi = recv_ok ? A.Hc[pr] : 0.0f;
         const float H2 = Hi * Hi;
         const float invH = recv_ok ? 1.0f / Hi : 0.0f;
         const float invH2 = invH * invH;
@@ -790,7 +878,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             // that no source is within its own or the source's cut-off
             const float far = recv_ok ? 0.0f : 1e30f;
             const float tfx = tx + far, tfy = ty + far, tfz = tz + far;
-            const float Gi = recv_ok ? A.gcell[sa + ia] : 0.0f;
+            const float Gi = recv_ok ? A.gcell[pr] : 0.0f;
             const float ck = Gi * ((8.0f / kPi) * (invH * invH) * (invH * invH));
             const float mi = pi.w;
             GradAcc acc = {0.f, 0.f, 0.f, 0.f};
@@ -831,7 +919,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
         } else {
             TileAcc acc = {0.f, 0.f, 0.f, 0.f};
             const float sig2 = A.lj_sigma2, eps = A.lj_eps;
-            const bool unit = !LJ && L.mass == L.mass;
+            const bool unit = !LJ && mass == mass;
             auto load_src = [&](int p) {
                 return p >= 0 ? A.xyzm[sb + p] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
             };
@@ -869,7 +957,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
             res = make_float4(acc.rho, acc.wc, acc.dh, acc.cnt);
         }
         if (recv_ok) {
-            float *dst = reinterpret_cast<float *>(&L.acc[wave][ia - r_lo]);
+            float *dst = reinterpret_cast<float *>(&L.acc[wave][ai]);
             atomicAdd(dst + 0, res.x);
             atomicAdd(dst + 1, res.y);
             atomicAdd(dst + 2, res.z);
@@ -878,21 +966,21 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds &L, int a, int chunk, in
     }
     __syncthreads();
 
-    for (int i = tid; i < nr; i += blockDim.x) {
+    for (int i = tid; i < nrt; i += blockDim.x) {
         const float4 s0 = L.acc[0][i], s1 = L.acc[1][i], s2 = L.acc[2][i], s3 = L.acc[3][i];
         float sr = ((s0.x + s1.x) + s2.x) + s3.x;
         const float sw = ((s0.y + s1.y) + s2.y) + s3.y;
         float sd = ((s0.z + s1.z) + s2.z) + s3.z;
         const float sc = ((s0.w + s1.w) + s2.w) + s3.w;
-        if (!ADJ && !LJ && L.mass == L.mass) {
+        if (!ADJ && !LJ && mass == mass) {
             // equal masses: the sums were taken with unit masses
-            sr = L.mass * sw;
-            sd = L.mass * sd;
+            sr = mass * sw;
+            sd = mass * sd;
         }
         if (nparts > 1)
             A.partial[((size_t)slot * nparts + part) * kChunk + i] = make_float4(sr, sw, sd, sc);
         else
-            finalize_receiver<MODE>(A, sa + r_lo + i, sr, sw, sd, sc);
+            finalize_receiver<MODE>(A, base + i, sr, sw, sd, sc);
     }
 }
 
@@ -900,7 +988,7 @@ template <int MODE>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(MODE == kModePlain ? 5 : 4, 8))) k_sweep_queue(SweepArgs A)
 {
-    __shared__ SweepLds L;
+    __shared__ SweepLds<group_cap(MODE)> L;
     if (A.dflags[0]) return;
     const int nbig = A.qcount[0], nsmall = A.qcount[1];
     // the tail cells (a fixed set: single-chunk cells among the last
@@ -954,27 +1042,57 @@ __global__ void __launch_bounds__(kBlock) k_tail_combine(SweepArgs A)
 }
 
 // Work items: the chunks of cells larger than one chunk at the front, in any
-// order; single-chunk cells at the back, counted from the end; the tail cells
-// (single-chunk cells with index >= tail_from) after cap.
-__global__ void k_queue_items(const int32_t *__restrict__ start, int64_t ncell, int cap,
-                              int chunk, int64_t tail_from, int2 *__restrict__ items,
+// order; the other items at the back, counted from the end; the tail cells
+// (single-chunk cells with index >= tail_from) after cap.  The other items
+// are single cells or, with group > 1, runs of consecutive single-chunk cells
+// whose particles fit one chunk together: each row of cells along z is cut
+// into blocks of `group` cells, and one thread per block fills runs greedily
+// in cell order (empty cells join the run they fall in; a run starts and ends
+// at a non-empty cell).  Items depend only on the cell counts and the box's
+// own cell numbering, not on the other boxes of a batch.
+__global__ void k_queue_items(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
+                              const int32_t *__restrict__ start, int64_t ncell, int cap, int chunk,
+                              int group, int64_t tail_from, int2 *__restrict__ items,
                               int *__restrict__ qcount)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const int na = start[c + 1] - start[c];
-    if (na <= 0) return;
-    if (na > chunk) {
-        const int nch = (na + chunk - 1) / chunk;
-        const int p = atomicAdd(&qcount[0], nch);
-        for (int k = 0; k < nch; ++k) items[p + k] = make_int2((int)c, k);
-    } else if (c >= tail_from) {
-        const int p = atomicAdd(&qcount[3], 1);
-        items[cap + p] = make_int2((int)c, 0);
-    } else {
-        const int p = atomicAdd(&qcount[1], 1);
-        items[cap - 1 - p] = make_int2((int)c, 0);
+    const int64_t c0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c0 >= ncell) return;
+    int end = (int)c0 + 1;
+    if (group > 1) {
+        const BoxDesc &B = box[cell_box[c0]];
+        const int zr = ((int)c0 - B.cell_off) % B.g[2];   // place in its z-row
+        if (zr % group != 0) return;                      // not the first of a block
+        end = (int)c0 + min(group, B.g[2] - zr);
     }
+    int first = -1, last = -1, sum = 0;   // the open run
+    auto close_run = [&]() {
+        if (first < 0) return;
+        const int p = atomicAdd(&qcount[1], 1);
+        items[cap - 1 - p] = make_int2(first, last > first ? -(last - first + 1) : 0);
+        first = -1;
+    };
+    for (int c = (int)c0; c < end; ++c) {
+        const int na = start[c + 1] - start[c];
+        if (na <= 0) continue;
+        if (na > chunk) {
+            close_run();
+            const int nch = (na + chunk - 1) / chunk;
+            const int p = atomicAdd(&qcount[0], nch);
+            for (int k = 0; k < nch; ++k) items[p + k] = make_int2(c, k);
+        } else if (c >= tail_from) {
+            close_run();
+            const int p = atomicAdd(&qcount[3], 1);
+            items[cap + p] = make_int2(c, 0);
+        } else if (first >= 0 && sum + na <= chunk) {
+            sum += na;
+            last = c;
+        } else {
+            close_run();
+            first = last = c;
+            sum = na;
+        }
+    }
+    close_run();
 }
 
 // Entries before the tail region; the tail region holds kTailMaxCells more.
@@ -987,6 +1105,8 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
 {
     if (ncell == 0 || n == 0) return hipSuccess;
     const int cap = (int)queue_main(n, ncell);
+    const int group = std::min(tune.group, group_cap(mode));
+    if (group < 1) return hipErrorInvalidValue;
     // persistent workgroups: a few per compute unit, never more than the cells
     int64_t grid = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
     if (grid > ncell) grid = ncell;
@@ -1002,8 +1122,8 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     hipError_t e = launch_zero(st, c.qcount, kQueueCounters);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_queue_items, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st,
-                       c.cell_start, ncell, cap, tune.chunk, ncell - A.tail_cells, c.items,
-                       c.qcount);
+                       c.box, c.cell_box, c.cell_start, ncell, cap, tune.chunk, group,
+                       ncell - A.tail_cells, c.items, c.qcount);
     A.box = c.box;
     A.cell_box = c.cell_box;
     A.start = c.cell_start;

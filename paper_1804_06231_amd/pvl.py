@@ -31,7 +31,7 @@ EXPORTS = (
     "pv_lj", "pv_autotune_grid",
 )
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4, "tail_parts": 5,
-          "tail_cells": 6}
+          "tail_cells": 6, "group": 7}
 PV_PARAM_ADJOINT = 16
 PV_PARAM_PLAIN = 32
 TUNE_TARGETS = {"density": 0, "adjoint": 1, "plain": 2}

@@ -330,6 +330,41 @@ def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
             ctx.set_param("tail_cells", 0, sw)
 
 
+@pytest.mark.parametrize("group", [1, 3, 8])
+def test_cell_groups_keep_results(ctx, clustered_ref, group):
+    """Runs of small cells swept as one work item (up to `group` cells of a
+    z-row whose particles fit one chunk) give the oracle's results in the
+    density and adjoint sweeps, bit-identically from run to run, with the
+    same exact neighbour counts as one cell per item."""
+    s, ref, G, gref = clustered_ref
+    for sw in ("density", "adjoint"):
+        ctx.set_param("group", group, sw)
+    try:
+        _flush(f"cell groups {group}")
+        c1, out = run_density(ctx, s, "sorted")
+        compare_density(out, ref, label=f"group {group}")
+        _, out2 = run_density(ctx, s, "sorted", cells=c1)
+        for x, y in zip(out, out2):
+            assert np.array_equal(x, y)
+        g = torch.from_numpy(G).to(dev())
+        gp, gh = ctx.density_backward(c1, g)
+        gp2, gh2 = ctx.density_backward(c1, g)
+        ctx.check()
+        gp, gh = gp.cpu().numpy(), gh.cpu().numpy()
+        assert np.array_equal(gp, gp2.cpu().numpy()) and np.array_equal(gh, gh2.cpu().numpy())
+        ex = np.max(np.abs(gp - gref["gx"]) / np.maximum(gref["gx_abs"], 1e-300))
+        eh = np.max(np.abs(gh - gref["gh"]) / np.maximum(gref["gh_abs"], 1e-300))
+        assert ex < 1e-5 and eh < 1e-5, (ex, eh)
+        # small cells on the finest grid (11^3 cells, about 25 particles per
+        # cell): runs of up to eight cells
+        u = uniform_set(32768, 5, hmode="jitter")
+        _, ou = run_density(ctx, u, "sorted")
+        compare_density(ou, oracle_for(u).density(), label=f"group {group} fine grid")
+    finally:
+        for sw in ("density", "adjoint"):
+            ctx.set_param("group", 4, sw)
+
+
 def test_autotune(ctx, clustered_ref):
     """The autotuner keeps a setting at least as fast as the one in place, and
     the tuned sweeps still give the oracle's results."""
