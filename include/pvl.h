@@ -204,10 +204,13 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
  *                         row of cells along z is cut into blocks of this
  *                         many cells, and consecutive single-chunk cells of a
  *                         block whose particles fit one chunk together run as
- *                         one work item (1: one cell per item).  Results may
- *                         differ in the last bits, since the receivers' sums
- *                         are taken in another order.  The plain sweep
- *                         always takes one cell per item.  Default 4.
+ *                         one work item (1: one cell per item).  0: automatic,
+ *                         8 with at least 16 cells per persistent workgroup,
+ *                         4 with at least 2, 2 with at least 1, else 1.
+ *                         Results may differ in the last bits, since the
+ *                         receivers' sums are taken in another order.  The
+ *                         plain sweep always takes one cell per item.
+ *                         Default 0.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,

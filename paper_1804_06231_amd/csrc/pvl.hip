@@ -552,8 +552,8 @@ pv_status pv_set_param(pv_ctx *ctx, int param, int value)
         t.tail_cells = value;
         return PV_OK;
     case PV_PARAM_GROUP:
-        if (value < 1 || value > pvl::kGroupMax)
-            return fail(ctx, PV_EINVAL, "group must be 1..8");
+        if (value < 0 || value > pvl::kGroupMax)
+            return fail(ctx, PV_EINVAL, "group must be 0..8");
         t.group = value;
         return PV_OK;
     }

@@ -158,7 +158,7 @@ struct SweepTuning {
     int chunk = 256;            // receivers per work item (multiple of 16, 32..256)
     int tail_parts = 2;         // the queue's last cells run as this many items (1, 2, 4)
     int tail_cells = 0;         // how many cells (0: automatic)
-    int group = 4;              // small cells per work item, at most (1..8)
+    int group = 0;              // small cells per work item, at most (1..8; 0: automatic)
     int num_cu = 256;           // compute units of the device
 };
 

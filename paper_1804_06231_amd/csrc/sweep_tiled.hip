@@ -1105,12 +1105,22 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
 {
     if (ncell == 0 || n == 0) return hipSuccess;
     const int cap = (int)queue_main(n, ncell);
-    const int group = std::min(tune.group, group_cap(mode));
-    if (group < 1) return hipErrorInvalidValue;
     // persistent workgroups: a few per compute unit, never more than the cells
-    int64_t grid = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
+    const int64_t wgs = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
+    int64_t grid = wgs;
     if (grid > ncell) grid = ncell;
     if (grid < 1) grid = 1;
+    // small cells per item, at most.  Auto: eight with at least 16 cells per
+    // workgroup (long runs then still leave every workgroup several items),
+    // four with at least two, two with at least one, else one cell per item
+    // (fewer items than workgroups would leave compute units idle)
+    int group = tune.group > 0  ? tune.group
+                : ncell >= 16 * wgs ? 8
+                : ncell >= 2 * wgs  ? 4
+                : ncell >= wgs      ? 2
+                                    : 1;
+    group = std::min(group, group_cap(mode));
+    if (group < 1 || group > kGroupMax) return hipErrorInvalidValue;
     A.tail_parts = tune.tail_parts;
     // auto: a quarter of the workgroups' worth of cells, when the queue holds
     // at least two cells per workgroup (with fewer there is no tail to trim)

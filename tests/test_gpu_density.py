@@ -330,7 +330,7 @@ def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
             ctx.set_param("tail_cells", 0, sw)
 
 
-@pytest.mark.parametrize("group", [1, 3, 8])
+@pytest.mark.parametrize("group", [1, 3, 8, 0])
 def test_cell_groups_keep_results(ctx, clustered_ref, group):
     """Runs of small cells swept as one work item (up to `group` cells of a
     z-row whose particles fit one chunk) give the oracle's results in the
@@ -362,7 +362,7 @@ def test_cell_groups_keep_results(ctx, clustered_ref, group):
         compare_density(ou, oracle_for(u).density(), label=f"group {group} fine grid")
     finally:
         for sw in ("density", "adjoint"):
-            ctx.set_param("group", 4, sw)
+            ctx.set_param("group", 0, sw)
 
 
 def test_autotune(ctx, clustered_ref):
