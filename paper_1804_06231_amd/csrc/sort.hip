@@ -46,17 +46,16 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
 // of in-cell ranks and keys live in LDS (about 25 KB for MAXC = 256), so
 // several cells share a compute unit; a particle's rank counts its bucket
 // mates with a smaller (key, in-cell rank), read from the bucket-order lists
-// with one LDS load each.  Each particle writes its own entries of the sorted
-// lists at its ranks, and the first keys of the tiles of 16 positions.
+// with one LDS load each, the 13 axes' mates a round at a time.  Each
+// particle writes its own entries of the sorted lists at its ranks, and the
+// first keys of the tiles of 16 positions.  Six waves per SIMD at least: the
+// register bound keeps the rounds' loads from costing occupancy.
 template <int MAXC, int NB>
-__global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict__ box,
-                                                      const int32_t *__restrict__ cell_box,
-                                                      const int32_t *__restrict__ start,
-                                                      const float4 *__restrict__ xyzm,
-                                                      const float *__restrict__ Hc, int64_t n,
-                                                      uint16_t *__restrict__ sidx,
-                                                      float *__restrict__ skey, int64_t tslots,
-                                                      float *__restrict__ tiles, int min_cnt)
+__global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(6)))
+k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
+               const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
+               const float *__restrict__ Hc, int64_t n, uint16_t *__restrict__ sidx,
+               float *__restrict__ skey, int64_t tslots, float *__restrict__ tiles, int min_cnt)
 {
     __shared__ uint32_t hist[13][NB];
     // in-cell ranks in bucket order: bytes while they fit (smaller LDS, more
@@ -136,15 +135,35 @@ __global__ void __launch_bounds__(MAXC) k_sort13_small(const BoxDesc *__restrict
     }
     __syncthreads();
     if (on) {
+        // exact rank: bucket start + bucket mates with a smaller (key, rank).
+        // The 13 axes' bucket scans advance together, one mate per axis per
+        // round, so each round issues its LDS reads side by side instead of
+        // 13 dependent chains; q0 packs the bucket start (low 16 bits) and
+        // its size (high 16 bits)
+        int rk[13];
+        int maxlen = 0;
 #pragma unroll
         for (int g = 0; g < 13; ++g) {
             const int q1 = b[g] + 1 < NB ? (int)hist[g][b[g] + 1] : cnt;
-            int rank = q0[g];
-            for (int q = q0[g]; q < q1; ++q) {
+            rk[g] = q0[g];
+            maxlen = max(maxlen, q1 - q0[g]);
+            q0[g] |= (q1 - q0[g]) << 16;
+        }
+        for (int j = 0; j < maxlen; ++j) {
+#pragma unroll
+            for (int g = 0; g < 13; ++g) {
+                // every bucket holds at least this particle, so the clamped
+                // index stays in it; past its end the round counts nothing
+                const int len = q0[g] >> 16;
+                const int q = (q0[g] & 0xffff) + min(j, len - 1);
                 const int r2 = border[g][q];
                 const float k2 = bkey[g][q];
-                rank += (k2 < k[g]) || (k2 == k[g] && r2 < r);
+                rk[g] += (int)(j < len) & ((int)(k2 < k[g]) | ((int)(k2 == k[g]) & (int)(r2 < r)));
             }
+        }
+#pragma unroll
+        for (int g = 0; g < 13; ++g) {
+            const int rank = rk[g];
             const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
             sidx[o] = (uint16_t)r;
             skey[o] = k[g];
