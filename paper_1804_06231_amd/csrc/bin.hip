@@ -332,7 +332,8 @@ __global__ void __launch_bounds__(MAXC) k_cell_finish_small(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
-    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int min_cnt)
+    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int min_cnt,
+    int32_t *__restrict__ large)
 {
     __shared__ float key[MAXC];
     __shared__ int32_t okey[MAXC];
@@ -343,7 +344,12 @@ __global__ void __launch_bounds__(MAXC) k_cell_finish_small(
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
-    if (cnt < min_cnt || cnt > MAXC) return;
+    if (cnt > MAXC) {
+        // listed for k_cell_finish_large
+        if (large && threadIdx.x == 0) large[1 + atomicAdd(&large[0], 1)] = c;
+        return;
+    }
+    if (cnt < min_cnt) return;
     if (cnt == 0) {
         if (threadIdx.x == 0) {
             cell_hmax[c] = 0u;
@@ -431,8 +437,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
-    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int32_t *__restrict__ big,
-    int min_cnt)
+    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m,
+    const int32_t *__restrict__ large, int32_t *__restrict__ mid, int32_t *__restrict__ big)
 {
     __shared__ float key[PV_MAX_CELL];
     __shared__ uint16_t slot[PV_MAX_CELL];
@@ -440,102 +446,110 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     __shared__ uint32_t hist[kFinishMaxBuckets];
     __shared__ uint32_t hred[kBlock / 64];
     __shared__ float2 mred[kBlock / 64];
-    const int c = blockIdx.x;
-    const int s0 = start[c];
-    const int cnt = start[c + 1] - s0;
-    if (cnt < min_cnt) return;
-    if (cnt > PV_MAX_CELL) {
+    // the cells listed by the 256-class finish, a grid's worth at a time
+    const int nlarge = large[0];
+    for (int item = blockIdx.x; item < nlarge; item += gridDim.x) {
+        const int c = large[1 + item];
+        const int s0 = start[c];
+        const int cnt = start[c + 1] - s0;
+        if (cnt > PV_MAX_CELL) {
+            if (threadIdx.x == 0) {
+                cell_hmax[c] = 0u;
+                cell_m[c] = __builtin_nanf("");
+            }
+            continue;
+        }
+        // the per-cell sort's lists: 257..kSortSmallMax and larger
         if (threadIdx.x == 0) {
-            cell_hmax[c] = 0u;
-            cell_m[c] = __builtin_nanf("");
+            int32_t *l = cnt > kSortSmallMax ? big : mid;
+            l[1 + atomicAdd(&l[0], 1)] = c;
         }
-        return;
-    }
-    if (cnt > kSortSmallMax && threadIdx.x == 0) big[1 + atomicAdd(&big[0], 1)] = c;
-    const BoxDesc &B = box[cell_box[c]];
-    const int local = c - B.cell_off;
-    const int cz = local % B.g[2];
-    const int cy = (local / B.g[2]) % B.g[1];
-    const int cx = local / (B.g[2] * B.g[1]);
-    const float ox = (float)cx * B.edge[0], oy = (float)cy * B.edge[1], oz = (float)cz * B.edge[2];
-    int NB = cnt <= 256 ? 128 : next_pow2(cnt) >> 2;
-    NB = NB > kFinishMaxBuckets ? kFinishMaxBuckets : NB;
-    const float scale = (float)NB / B.edge[0];
-    auto bucket = [&](float xr) {
-        int b = (int)(xr * scale);
-        return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
-    };
-    for (int b = threadIdx.x; b < NB; b += blockDim.x) hist[b] = 0u;
-    __syncthreads();
-    for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-        const float xr = stage[2 * (int64_t)(s0 + r)].x - ox;
-        key[r] = xr;
-        slot[r] = (uint16_t)atomicAdd(&hist[bucket(xr)], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        const int per = (NB + 63) >> 6;
-        uint32_t loc = 0;
-        for (int k = 0; k < per; ++k) {
-            const int q = lane * per + k;
-            if (q < NB) loc += hist[q];
+        const BoxDesc &B = box[cell_box[c]];
+        const int local = c - B.cell_off;
+        const int cz = local % B.g[2];
+        const int cy = (local / B.g[2]) % B.g[1];
+        const int cx = local / (B.g[2] * B.g[1]);
+        const float ox = (float)cx * B.edge[0], oy = (float)cy * B.edge[1], oz = (float)cz * B.edge[2];
+        int NB = cnt <= 256 ? 128 : next_pow2(cnt) >> 2;
+        NB = NB > kFinishMaxBuckets ? kFinishMaxBuckets : NB;
+        const float scale = (float)NB / B.edge[0];
+        auto bucket = [&](float xr) {
+            int b = (int)(xr * scale);
+            return b < 0 ? 0 : (b >= NB ? NB - 1 : b);
+        };
+        for (int b = threadIdx.x; b < NB; b += blockDim.x) hist[b] = 0u;
+        __syncthreads();
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+            const float xr = stage[2 * (int64_t)(s0 + r)].x - ox;
+            key[r] = xr;
+            slot[r] = (uint16_t)atomicAdd(&hist[bucket(xr)], 1u);
         }
-        uint32_t inc = loc;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
-            if (lane >= off) inc += o;
-        }
-        uint32_t run = inc - loc;
-        for (int k = 0; k < per; ++k) {
-            const int q = lane * per + k;
-            if (q < NB) {
-                const uint32_t v = hist[q];
-                hist[q] = run;
-                run += v;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int lane = threadIdx.x;
+            const int per = (NB + 63) >> 6;
+            uint32_t loc = 0;
+            for (int k = 0; k < per; ++k) {
+                const int q = lane * per + k;
+                if (q < NB) loc += hist[q];
+            }
+            uint32_t inc = loc;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+                if (lane >= off) inc += o;
+            }
+            uint32_t run = inc - loc;
+            for (int k = 0; k < per; ++k) {
+                const int q = lane * per + k;
+                if (q < NB) {
+                    const uint32_t v = hist[q];
+                    hist[q] = run;
+                    run += v;
+                }
             }
         }
-    }
-    __syncthreads();
-    for (int r = threadIdx.x; r < cnt; r += blockDim.x)
-        border[hist[bucket(key[r])] + slot[r]] = (uint16_t)r;
-    __syncthreads();
-    uint32_t hm = 0u;
-    float mmin = INFINITY, mmax = -INFINITY;
-    for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
-        const float k = key[r];
-        const int b = bucket(k);
-        const int q0 = (int)hist[b];
-        const int q1 = b + 1 < NB ? (int)hist[b + 1] : cnt;
-        const float4 a = stage[2 * (int64_t)(s0 + r)];
-        const float4 m = stage[2 * (int64_t)(s0 + r) + 1];
-        const int my_orig = __float_as_int(m.y);
-        int rank = q0;
-        for (int q = q0; q < q1; ++q) {
-            const int r2 = border[q];
-            const float k2 = key[r2];
-            bool before = k2 < k;
-            if (k2 == k && r2 != r)
-                before = __float_as_int(stage[2 * (int64_t)(s0 + r2) + 1].y) < my_orig;
-            rank += before;
+        __syncthreads();
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x)
+            border[hist[bucket(key[r])] + slot[r]] = (uint16_t)r;
+        __syncthreads();
+        uint32_t hm = 0u;
+        float mmin = INFINITY, mmax = -INFINITY;
+        for (int r = threadIdx.x; r < cnt; r += blockDim.x) {
+            const float k = key[r];
+            const int b = bucket(k);
+            const int q0 = (int)hist[b];
+            const int q1 = b + 1 < NB ? (int)hist[b + 1] : cnt;
+            const float4 a = stage[2 * (int64_t)(s0 + r)];
+            const float4 m = stage[2 * (int64_t)(s0 + r) + 1];
+            const int my_orig = __float_as_int(m.y);
+            int rank = q0;
+            for (int q = q0; q < q1; ++q) {
+                const int r2 = border[q];
+                const float k2 = key[r2];
+                bool before = k2 < k;
+                if (k2 == k && r2 != r)
+                    before = __float_as_int(stage[2 * (int64_t)(s0 + r2) + 1].y) < my_orig;
+                rank += before;
+            }
+            xyzm[s0 + rank] = make_float4(k, a.y - oy, a.z - oz, m.x);
+            Hout[s0 + rank] = a.w;
+            orig[s0 + rank] = my_orig;
+            hm = max(hm, __float_as_uint(a.w));
+            mmin = fminf(mmin, m.x);
+            mmax = fmaxf(mmax, m.x);
         }
-        xyzm[s0 + rank] = make_float4(k, a.y - oy, a.z - oz, m.x);
-        Hout[s0 + rank] = a.w;
-        orig[s0 + rank] = my_orig;
-        hm = max(hm, __float_as_uint(a.w));
-        mmin = fminf(mmin, m.x);
-        mmax = fmaxf(mmax, m.x);
+        // largest cut-off of the cell (positive floats order as their bits)
+        for (int off = 32; off > 0; off >>= 1) hm = max(hm, (uint32_t)__shfl_xor((int)hm, off));
+        if ((threadIdx.x & 63) == 0) hred[threadIdx.x >> 6] = hm;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t mx = 0u;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = max(mx, hred[w]);
+            cell_hmax[c] = mx;
+        }
+        reduce_cell_mass(mmin, mmax, mred, (int)(blockDim.x >> 6), cell_m + c);
+        __syncthreads();   // the next cell reuses the LDS
     }
-    // largest cut-off of the cell (positive floats order as their bits)
-    for (int off = 32; off > 0; off >>= 1) hm = max(hm, (uint32_t)__shfl_xor((int)hm, off));
-    if ((threadIdx.x & 63) == 0) hred[threadIdx.x >> 6] = hm;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t mx = 0u;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mx = max(mx, hred[w]);
-        cell_hmax[c] = mx;
-    }
-    reduce_cell_mass(mmin, mmax, mred, (int)(blockDim.x >> 6), cell_m + c);
 }
 
 // Owning box of every cell; also clears the per-build state: the cells'
@@ -550,7 +564,7 @@ __global__ void k_cell_box(const BoxDesc *__restrict__ box, int nbox, int64_t nc
     if (c == 0) {
         *dx_all = 0u;
         dflags[1] = 0;
-        big[0] = 0;
+        for (int k = 0; k < kCellLists; ++k) cell_list(big, ncell, k)[0] = 0;
     }
     if (c >= ncell) return;
     cell_dx[c] = 0.0f;
@@ -674,13 +688,16 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
     if (!dense)
         hipLaunchKernelGGL((k_cell_finish_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
                            c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
-                           c.cell_hmax, c.cell_m, 0);
+                           c.cell_hmax, c.cell_m, 0, (int32_t *)nullptr);
     hipLaunchKernelGGL((k_cell_finish_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0,
                        st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
-                       c.cell_hmax, c.cell_m, dense ? 0 : 65);
-    hipLaunchKernelGGL(k_cell_finish_large, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig, c.cell_hmax,
-                       c.cell_m, c.big, 257);
+                       c.cell_hmax, c.cell_m, dense ? 0 : 65, cell_list(c.big, ncell, kListLarge));
+    // the cells above 256 particles, listed by the 256-class finish
+    hipLaunchKernelGGL(k_cell_finish_large, dim3((unsigned)std::min<int64_t>(ncell, kListWgs)),
+                       dim3(kBlock), 0, st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm,
+                       c.H, c.orig, c.cell_hmax, c.cell_m,
+                       (const int32_t *)cell_list(c.big, ncell, kListLarge),
+                       cell_list(c.big, ncell, kListMid), cell_list(c.big, ncell, kListBig));
     return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.bin_blocks, NB);
     ALLOC(d.cell_dx, C);
     ALLOC(d.cell_m, C);
-    ALLOC(d.big, C + 1);
+    ALLOC(d.big, pvl::kCellLists * (C + 1));
     d.tslots = pvl::tile_slots(N, C);
     ALLOC(d.tiles, pvl::kTileArrays * d.tslots);
     ALLOC(d.dx_all, 1);

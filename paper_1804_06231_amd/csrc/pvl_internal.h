@@ -92,7 +92,7 @@ struct DevCells {
     uint32_t *box_hmax = nullptr; // nbox: max cut-off per box (fp32 bits)
     int32_t *scan_tmp = nullptr;  // scan_scratch_words(matrix entries): tile sums / offsets
     int32_t *binm = nullptr;      // binning count matrix (chunks x cells per box)
-    int32_t *big = nullptr;       // ncell + 1: [0] count, then the cells above kSortSmallMax
+    int32_t *big = nullptr;       // kCellLists lists of ncell + 1 (see cell_list)
                                   // particles (written by the cell finish, any order)
     // Tile summaries of the sorted lists, written by the per-cell sorts: for
     // axis s and tile slot t = cell_start[c] / 16 + c + j of tile j of cell c,
@@ -119,6 +119,18 @@ struct BinPlan {
 // Largest cell sorted with one particle per thread; larger cells are listed
 // and sorted one axis per workgroup.
 constexpr int kSortSmallMax = 512;
+
+// Cell lists made during a build, each a count followed by cell indices with
+// room for every cell: the cells above 256 particles (by the 256-class cell
+// finish), then of those the cells of 257..kSortSmallMax and the cells above
+// kSortSmallMax (by the large-cell finish).  The kernels that take a list
+// run a fixed grid of at most kListWgs workgroups over it.
+constexpr int kListLarge = 0, kListMid = 1, kListBig = 2, kCellLists = 3;
+constexpr int64_t kListWgs = 1024;
+__host__ __device__ inline int32_t *cell_list(int32_t *lists, int64_t ncell, int k)
+{
+    return lists + k * (ncell + 1);
+}
 
 // Mean cell occupancy from which the per-cell kernels fold their rare size
 // classes into their neighbours' launches.

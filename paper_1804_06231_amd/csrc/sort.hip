@@ -48,14 +48,16 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
 // mates with a smaller (key, in-cell rank), read from the bucket-order lists
 // with one LDS load each, the 13 axes' mates a round at a time.  Each
 // particle writes its own entries of the sorted lists at its ranks, and the
-// first keys of the tiles of 16 positions.  Six waves per SIMD at least: the
-// register bound keeps the rounds' loads from costing occupancy.
-template <int MAXC, int NB>
-__global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(6)))
+// first keys of the tiles of 16 positions.  Six waves per SIMD at least (four
+// for the 512 class, which spills at six): the register bound keeps the
+// rounds' loads from costing occupancy.
+template <int MAXC, int NB, bool LIST>
+__global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(MAXC > 256 ? 4 : 6)))
 k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
                const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
                const float *__restrict__ Hc, int64_t n, uint16_t *__restrict__ sidx,
-               float *__restrict__ skey, int64_t tslots, float *__restrict__ tiles, int min_cnt)
+               float *__restrict__ skey, int64_t tslots, float *__restrict__ tiles, int min_cnt,
+               const int32_t *__restrict__ list)
 {
     __shared__ uint32_t hist[13][NB];
     // in-cell ranks in bucket order: bytes while they fit (smaller LDS, more
@@ -63,123 +65,128 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
     using rank_t = typename std::conditional<MAXC <= 256, uint8_t, uint16_t>::type;
     __shared__ rank_t border[13][MAXC];
     __shared__ float bkey[13][MAXC];
-    const int c = blockIdx.x;
-    const int s0 = start[c];
-    const int cnt = start[c + 1] - s0;
-    if (cnt < min_cnt || cnt > MAXC) return;
-    const BoxDesc &B = box[cell_box[c]];
-    for (int t = threadIdx.x; t < 13 * NB; t += blockDim.x) (&hist[0][0])[t] = 0u;
-    const int r = threadIdx.x;
-    const bool on = r < cnt;
-    const float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float Hi = on ? Hc[s0 + r] : 0.0f;
-    __syncthreads();
-    float k[13];
-    int b[13];
-    uint32_t sl[13];
-#pragma unroll
-    for (int g = 0; g < 13; ++g) {
-        // the cell's key range on axis g cut into NB buckets (any monotone map
-        // of the key will do: each key's bucket is computed once)
-        float e[3];
-        dir_axis(g, e);
-        const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
-                           fminf(e[2], 0.f) * B.edge[2];
-        const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
-                           fmaxf(e[2], 0.f) * B.edge[2];
-        const float scale = (float)NB * __builtin_amdgcn_rcpf(kmax - kmin);
-        k[g] = proj_key(p.x, p.y, p.z, g);
-        b[g] = key_bucket(k[g], kmin, scale, NB);
-    }
-    if (on) {
-#pragma unroll
-        for (int g = 0; g < 13; ++g) sl[g] = atomicAdd(&hist[g][b[g]], 1u);
-    }
-    __syncthreads();
-    {
-        // exclusive scans of the 13 histograms, one wave per axis at a time,
-        // NB / 64 buckets per lane (NB <= 64: one bucket on the first lanes)
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        constexpr int per = NB >= 64 ? NB / 64 : 1;
-        for (int g = wave; g < 13; g += (int)(blockDim.x >> 6)) {
-            uint32_t v[per];
-            uint32_t loc = 0;
-#pragma unroll
-            for (int q = 0; q < per; ++q) {
-                v[q] = lane * per + q < NB ? hist[g][lane * per + q] : 0u;
-                loc += v[q];
-            }
-            uint32_t inc = loc;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
-                if (lane >= off) inc += o;
-            }
-            uint32_t run = inc - loc;
-#pragma unroll
-            for (int q = 0; q < per; ++q) {
-                if (lane * per + q < NB) hist[g][lane * per + q] = run;
-                run += v[q];
-            }
-        }
-    }
-    __syncthreads();
-    const int64_t slot0 = tile_slot(s0, c, 0);
-    int q0[13];
-    if (on) {
-#pragma unroll
+    // one cell (blockIdx.x), or LIST: the listed cells, a grid's worth at a time
+    const int nitem = LIST ? list[0] : 1;
+    for (int item = LIST ? (int)blockIdx.x : 0; item < nitem; item += LIST ? (int)gridDim.x : 1) {
+        const int c = LIST ? list[1 + item] : (int)blockIdx.x;
+        const int s0 = start[c];
+        const int cnt = start[c + 1] - s0;
+        if (cnt < min_cnt || cnt > MAXC) continue;
+        const BoxDesc &B = box[cell_box[c]];
+        for (int t = threadIdx.x; t < 13 * NB; t += blockDim.x) (&hist[0][0])[t] = 0u;
+        const int r = threadIdx.x;
+        const bool on = r < cnt;
+        const float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float Hi = on ? Hc[s0 + r] : 0.0f;
+        __syncthreads();
+        float k[13];
+        int b[13];
+        uint32_t sl[13];
+    #pragma unroll
         for (int g = 0; g < 13; ++g) {
-            q0[g] = (int)hist[g][b[g]];
-            border[g][q0[g] + (int)sl[g]] = (rank_t)r;
-            bkey[g][q0[g] + (int)sl[g]] = k[g];
+            // the cell's key range on axis g cut into NB buckets (any monotone map
+            // of the key will do: each key's bucket is computed once)
+            float e[3];
+            dir_axis(g, e);
+            const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
+                               fminf(e[2], 0.f) * B.edge[2];
+            const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
+                               fmaxf(e[2], 0.f) * B.edge[2];
+            const float scale = (float)NB * __builtin_amdgcn_rcpf(kmax - kmin);
+            k[g] = proj_key(p.x, p.y, p.z, g);
+            b[g] = key_bucket(k[g], kmin, scale, NB);
         }
-    }
-    __syncthreads();
-    if (on) {
-        // exact rank: bucket start + bucket mates with a smaller (key, rank).
-        // The 13 axes' bucket scans advance together, one mate per axis per
-        // round, so each round issues its LDS reads side by side instead of
-        // 13 dependent chains; q0 packs the bucket start (low 16 bits) and
-        // its size (high 16 bits)
-        int rk[13];
-        int maxlen = 0;
-#pragma unroll
-        for (int g = 0; g < 13; ++g) {
-            const int q1 = b[g] + 1 < NB ? (int)hist[g][b[g] + 1] : cnt;
-            rk[g] = q0[g];
-            maxlen = max(maxlen, q1 - q0[g]);
-            q0[g] |= (q1 - q0[g]) << 16;
+        if (on) {
+    #pragma unroll
+            for (int g = 0; g < 13; ++g) sl[g] = atomicAdd(&hist[g][b[g]], 1u);
         }
-        for (int j = 0; j < maxlen; ++j) {
-#pragma unroll
+        __syncthreads();
+        {
+            // exclusive scans of the 13 histograms, one wave per axis at a time,
+            // NB / 64 buckets per lane (NB <= 64: one bucket on the first lanes)
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            constexpr int per = NB >= 64 ? NB / 64 : 1;
+            for (int g = wave; g < 13; g += (int)(blockDim.x >> 6)) {
+                uint32_t v[per];
+                uint32_t loc = 0;
+    #pragma unroll
+                for (int q = 0; q < per; ++q) {
+                    v[q] = lane * per + q < NB ? hist[g][lane * per + q] : 0u;
+                    loc += v[q];
+                }
+                uint32_t inc = loc;
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t o = (uint32_t)__shfl_up((int)inc, off);
+                    if (lane >= off) inc += o;
+                }
+                uint32_t run = inc - loc;
+    #pragma unroll
+                for (int q = 0; q < per; ++q) {
+                    if (lane * per + q < NB) hist[g][lane * per + q] = run;
+                    run += v[q];
+                }
+            }
+        }
+        __syncthreads();
+        const int64_t slot0 = tile_slot(s0, c, 0);
+        int q0[13];
+        if (on) {
+    #pragma unroll
             for (int g = 0; g < 13; ++g) {
-                // every bucket holds at least this particle, so the clamped
-                // index stays in it; past its end the round counts nothing
-                const int len = q0[g] >> 16;
-                const int q = (q0[g] & 0xffff) + min(j, len - 1);
-                const int r2 = border[g][q];
-                const float k2 = bkey[g][q];
-                rk[g] += (int)(j < len) & ((int)(k2 < k[g]) | ((int)(k2 == k[g]) & (int)(r2 < r)));
+                q0[g] = (int)hist[g][b[g]];
+                border[g][q0[g] + (int)sl[g]] = (rank_t)r;
+                bkey[g][q0[g] + (int)sl[g]] = k[g];
             }
         }
-#pragma unroll
-        for (int g = 0; g < 13; ++g) {
-            const int rank = rk[g];
-            const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
-            sidx[o] = (uint16_t)r;
-            skey[o] = k[g];
-            // tile summaries: the first keys of the tiles from either end
-            const int re = cnt - 1 - rank;
-            if ((rank & 15) == 0) tiles[kTileTS(g) * tslots + slot0 + (rank >> 4)] = k[g];
-            if ((re & 15) == 0) tiles[kTileTE(g) * tslots + slot0 + (re >> 4)] = k[g];
-            if (g == kTileAxisX && ((rank & 15) == 15 || re == 0))
-                tiles[kTileTLX * tslots + slot0 + (rank >> 4)] = k[g];
+        __syncthreads();
+        if (on) {
+            // exact rank: bucket start + bucket mates with a smaller (key, rank).
+            // The 13 axes' bucket scans advance together, one mate per axis per
+            // round, so each round issues its LDS reads side by side instead of
+            // 13 dependent chains; q0 packs the bucket start (low 16 bits) and
+            // its size (high 16 bits)
+            int rk[13];
+            int maxlen = 0;
+    #pragma unroll
+            for (int g = 0; g < 13; ++g) {
+                const int q1 = b[g] + 1 < NB ? (int)hist[g][b[g] + 1] : cnt;
+                rk[g] = q0[g];
+                maxlen = max(maxlen, q1 - q0[g]);
+                q0[g] |= (q1 - q0[g]) << 16;
+            }
+            for (int j = 0; j < maxlen; ++j) {
+    #pragma unroll
+                for (int g = 0; g < 13; ++g) {
+                    // every bucket holds at least this particle, so the clamped
+                    // index stays in it; past its end the round counts nothing
+                    const int len = q0[g] >> 16;
+                    const int q = (q0[g] & 0xffff) + min(j, len - 1);
+                    const int r2 = border[g][q];
+                    const float k2 = bkey[g][q];
+                    rk[g] += (int)(j < len) & ((int)(k2 < k[g]) | ((int)(k2 == k[g]) & (int)(r2 < r)));
+                }
+            }
+    #pragma unroll
+            for (int g = 0; g < 13; ++g) {
+                const int rank = rk[g];
+                const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
+                sidx[o] = (uint16_t)r;
+                skey[o] = k[g];
+                // tile summaries: the first keys of the tiles from either end
+                const int re = cnt - 1 - rank;
+                if ((rank & 15) == 0) tiles[kTileTS(g) * tslots + slot0 + (rank >> 4)] = k[g];
+                if ((re & 15) == 0) tiles[kTileTE(g) * tslots + slot0 + (re >> 4)] = k[g];
+                if (g == kTileAxisX && ((rank & 15) == 15 || re == 0))
+                    tiles[kTileTLX * tslots + slot0 + (rank >> 4)] = k[g];
+            }
         }
+        // largest cut-off of each tile of the cell order (16 consecutive threads)
+        float hx = Hi;
+    #pragma unroll
+        for (int off = 8; off > 0; off >>= 1) hx = fmaxf(hx, __shfl_xor(hx, off, 16));
+        if (on && (r & 15) == 0) tiles[kTileBHX * tslots + slot0 + (r >> 4)] = hx;
+        if constexpr (LIST) __syncthreads();   // the next cell reuses the LDS
     }
-    // largest cut-off of each tile of the cell order (16 consecutive threads)
-    float hx = Hi;
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) hx = fmaxf(hx, __shfl_xor(hx, off, 16));
-    if (on && (r & 15) == 0) tiles[kTileBHX * tslots + slot0 + (r >> 4)] = hx;
 }
 
 // Cells above kSortSmallMax particles (listed by the cell finish): one
@@ -310,9 +317,10 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
     }
 }
 
-// One launch per size class over all cells, each taking the cells of its
-// class (at most 64 particles, 65..256, 257..512, more) and skipping the
-// others.  (Larger one-particle-per-thread classes measured slower than the
+// One launch per size class: the classes of at most 64 and 65..256
+// particles over all cells, each skipping the others; the cells of 257..512
+// and above 512 from the lists the cell finish made, so that a grid without
+// such cells launches only a few workgroups for them.  (Larger one-particle-per-thread classes measured slower than the
 // looping kernel: their LDS leaves two workgroups per compute unit.)
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell)
 {
@@ -321,21 +329,24 @@ hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t n
     // rare: the 256 class takes them, one launch over all cells fewer (the
     // 257..512 class stays: the looping kernel is slower on such cells)
     const bool dense = n >= kDenseCells * ncell;
+    int32_t *lists = c.big;
     if (!dense)
-        hipLaunchKernelGGL((k_sort13_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
+        hipLaunchKernelGGL((k_sort13_small<64, 32, false>), dim3((unsigned)ncell), dim3(64), 0, st,
                            c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
-                           c.tslots, c.tiles, 1);
-    hipLaunchKernelGGL((k_sort13_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0, st,
+                           c.tslots, c.tiles, 1, (const int32_t *)nullptr);
+    hipLaunchKernelGGL((k_sort13_small<256, 128, false>), dim3((unsigned)ncell), dim3(256), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
-                       c.tslots, c.tiles, dense ? 1 : 65);
-    hipLaunchKernelGGL((k_sort13_small<512, 256>), dim3((unsigned)ncell), dim3(512), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
-                       c.tslots, c.tiles, 257);
+                       c.tslots, c.tiles, dense ? 1 : 65, (const int32_t *)nullptr);
+    // the cells of 257..512 particles, listed by the cell finish
+    const unsigned list_wgs = (unsigned)std::min<int64_t>(ncell, kListWgs);
+    hipLaunchKernelGGL((k_sort13_small<512, 256, true>), dim3(list_wgs), dim3(512), 0, st, c.box,
+                       c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
+                       c.tiles, 257, (const int32_t *)cell_list(lists, ncell, kListMid));
     // the listed large cells, one workgroup per (cell, axis)
     const unsigned big_wgs = (unsigned)std::min<int64_t>(ncell, kSortLargeWgs);
     hipLaunchKernelGGL(k_sort13_large, dim3(big_wgs, 13), dim3(kBlock), 0, st, c.box,
                        c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
-                       c.tiles, c.big);
+                       c.tiles, (const int32_t *)cell_list(lists, ncell, kListBig));
     return hipGetLastError();
 }
 
