@@ -58,7 +58,7 @@ typedef enum {
 } pv_algo;
 
 /* Largest supported cell occupancy (particles in one cell). */
-#define PV_MAX_CELL 4096
+#define PV_MAX_CELL 8192
 /* Largest supported number of cells per axis. */
 #define PV_MAX_GRID 1024
 

@@ -438,7 +438,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
     uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m,
-    const int32_t *__restrict__ large, int32_t *__restrict__ mid, int32_t *__restrict__ big)
+    const int32_t *__restrict__ large, int32_t *__restrict__ mid, int32_t *__restrict__ big,
+    int32_t *__restrict__ huge)
 {
     __shared__ float key[PV_MAX_CELL];
     __shared__ uint16_t slot[PV_MAX_CELL];
@@ -459,9 +460,9 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
             }
             continue;
         }
-        // the per-cell sort's lists: 257..kSortSmallMax and larger
+        // the per-cell sort's lists by size class
         if (threadIdx.x == 0) {
-            int32_t *l = cnt > kSortSmallMax ? big : mid;
+            int32_t *l = cnt > kSortLargeMax ? huge : cnt > kSortSmallMax ? big : mid;
             l[1 + atomicAdd(&l[0], 1)] = c;
         }
         const BoxDesc &B = box[cell_box[c]];
@@ -697,7 +698,8 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
                        dim3(kBlock), 0, st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm,
                        c.H, c.orig, c.cell_hmax, c.cell_m,
                        (const int32_t *)cell_list(c.big, ncell, kListLarge),
-                       cell_list(c.big, ncell, kListMid), cell_list(c.big, ncell, kListBig));
+                       cell_list(c.big, ncell, kListMid), cell_list(c.big, ncell, kListBig),
+                       cell_list(c.big, ncell, kListHuge));
     return hipGetLastError();
 }
 

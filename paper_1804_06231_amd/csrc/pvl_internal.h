@@ -120,12 +120,16 @@ struct BinPlan {
 // and sorted one axis per workgroup.
 constexpr int kSortSmallMax = 512;
 
+// Largest cell of the large-cell sort's smaller LDS class.
+constexpr int kSortLargeMax = 4096;
+
 // Cell lists made during a build, each a count followed by cell indices with
 // room for every cell: the cells above 256 particles (by the 256-class cell
-// finish), then of those the cells of 257..kSortSmallMax and the cells above
-// kSortSmallMax (by the large-cell finish).  The kernels that take a list
-// run a fixed grid of at most kListWgs workgroups over it.
-constexpr int kListLarge = 0, kListMid = 1, kListBig = 2, kCellLists = 3;
+// finish), then of those the cells of 257..kSortSmallMax, of
+// kSortSmallMax+1..kSortLargeMax and larger ones (by the large-cell finish).
+// The kernels that take a list run a fixed grid of at most kListWgs
+// workgroups over it.
+constexpr int kListLarge = 0, kListMid = 1, kListBig = 2, kListHuge = 3, kCellLists = 4;
 constexpr int64_t kListWgs = 1024;
 __host__ __device__ inline int32_t *cell_list(int32_t *lists, int64_t ncell, int k)
 {

@@ -22,7 +22,9 @@
 
 namespace pvl {
 
-constexpr int kSortLdsBytes = 40 * 1024;
+// the large-cell sort's LDS for cells of at most MAXCNT particles: histogram
+// (at most MAXCNT / 4 buckets), keys and two lists of 16-bit ranks
+constexpr int sort_lds_bytes(int maxcnt) { return 4 * (maxcnt / 4) + 8 * maxcnt; }
 constexpr int64_t kSortLargeWgs = 256;   // cells in flight of the large-cell sort
 
 __device__ __forceinline__ int sort_buckets(int cnt)
@@ -193,7 +195,9 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
 // workgroup per (listed cell, axis), so that a large cell's 13 sorts run side
 // by side; a grid of at most a few hundred cells by 13 axes loops over the
 // list.  The keys, the arrival slots and the bucket-order list of the axis
-// live in LDS (at most 36 KB for PV_MAX_CELL particles).
+// live in LDS: 36 KB for the list of cells of at most kSortLargeMax
+// particles, 72 KB for the list of larger ones (up to PV_MAX_CELL).
+template <int MAXCNT>
 __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restrict__ box,
                                                     const int32_t *__restrict__ cell_box,
                                                     const int32_t *__restrict__ start,
@@ -204,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
                                                     float *__restrict__ tiles,
                                                     const int32_t *__restrict__ big)
 {
-    __shared__ __align__(16) unsigned char lds[kSortLdsBytes];
+    __shared__ __align__(16) unsigned char lds[sort_lds_bytes(MAXCNT)];
     __shared__ float ax_kmin, ax_scale;
     const int s = blockIdx.y;   // the axis of this workgroup
     const int nbig = big[0];
@@ -344,9 +348,12 @@ hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t n
                        c.tiles, 257, (const int32_t *)cell_list(lists, ncell, kListMid));
     // the listed large cells, one workgroup per (cell, axis)
     const unsigned big_wgs = (unsigned)std::min<int64_t>(ncell, kSortLargeWgs);
-    hipLaunchKernelGGL(k_sort13_large, dim3(big_wgs, 13), dim3(kBlock), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
-                       c.tiles, (const int32_t *)cell_list(lists, ncell, kListBig));
+    hipLaunchKernelGGL(k_sort13_large<kSortLargeMax>, dim3(big_wgs, 13), dim3(kBlock), 0, st,
+                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                       c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListBig));
+    hipLaunchKernelGGL(k_sort13_large<PV_MAX_CELL>, dim3(big_wgs, 13), dim3(kBlock), 0, st,
+                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                       c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListHuge));
     return hipGetLastError();
 }
 

@@ -244,13 +244,15 @@ __device__ __forceinline__ void lj_interact(float dx, float dy, float dz, float 
         if (r2 < H2) tile_interact_unit(r2, invH2, uacc);                 \
     }
 
-// Task word: bits 0-8 source tiles, 9-13 receiver block, 14-21 the item's
-// cell and direction (27 g + d: d 0..25 neighbour, 26 = own cell), 22-30
-// first source tile.
+// Task word: bits 0-9 source tiles, 10-14 receiver block, 15-22 the item's
+// cell and direction (27 g + d: d 0..25 neighbour, 26 = own cell), 23-31
+// first source tile.  A cell has at most PV_MAX_CELL / 16 tiles.
+static_assert(PV_MAX_CELL / 16 <= 512, "tile counts and first tiles fit the task word");
 __device__ __forceinline__ uint32_t pack_task(int gd, int blk, int nt, int t0)
 {
-    return (uint32_t)nt | ((uint32_t)blk << 9) | ((uint32_t)gd << 14) | ((uint32_t)t0 << 22);
+    return (uint32_t)nt | ((uint32_t)blk << 10) | ((uint32_t)gd << 15) | ((uint32_t)t0 << 23);
 }
+__device__ __forceinline__ int task_tiles(uint32_t tw) { return (int)(tw & 1023u); }
 
 __device__ __forceinline__ void nb_offset(int dir, int &dx, int &dy, int &dz)
 {
@@ -789,7 +791,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         for (int v = 0; v < kTaskLevels; ++v) below[v] = 0;
         for (int c = 0; c < ntask; c += 64) {
             const int t = c + lane;
-            const int lv = t < ntask ? min((int)(L.tasks[t] & 511u), kTaskLevels - 1) : -1;
+            const int lv = t < ntask ? min(task_tiles(L.tasks[t]), kTaskLevels - 1) : -1;
 #pragma unroll
             for (int v = 0; v < kTaskLevels; ++v) below[v] += __popcll(__ballot(lv == v));
         }
@@ -802,7 +804,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         }
         for (int c = 0; c < ntask; c += 64) {
             const int t = c + lane;
-            const int lv = t < ntask ? min((int)(L.tasks[t] & 511u), kTaskLevels - 1) : -1;
+            const int lv = t < ntask ? min(task_tiles(L.tasks[t]), kTaskLevels - 1) : -1;
             int pos = 0;
 #pragma unroll
             for (int v = 0; v < kTaskLevels; ++v) {
@@ -829,10 +831,10 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         const int t = tg * 4 + row;
         const bool row_valid = t < ntask;
         const uint32_t tw = row_valid ? L.tasks[L.torder[t]] : 0u;
-        const int nt = row_valid ? (int)(tw & 511u) : 0;
-        const int blk = (int)((tw >> 9) & 31u);
-        const int gd = (int)((tw >> 14) & 255u);
-        const int t0 = (int)(tw >> 22);
+        const int nt = row_valid ? task_tiles(tw) : 0;
+        const int blk = (int)((tw >> 10) & 31u);
+        const int gd = (int)((tw >> 15) & 255u);
+        const int t0 = (int)(tw >> 23);
         const int g = gd / 27, dir = gd - 27 * g;
         const int sa = L.gsa[g], na = L.gna[g];
         // receiver of this lane and the source list of its row

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libpvl.so")
 
 PV_OK, PV_EINVAL, PV_ENOMEM, PV_EHIP, PV_EGRID, PV_EOVERFLOW, PV_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PV_SORTED_PAIR, PV_PLAIN_CELL = 0, 1
-PV_MAX_CELL = 4096
+PV_MAX_CELL = 8192
 PV_MAX_GRID = 1024
 ALGOS = {"sorted": PV_SORTED_PAIR, "plain": PV_PLAIN_CELL}
 
