@@ -479,7 +479,9 @@ def _bench_hsolve(ctx, s, pos, m, torch):
     workloads.  On clustered ones a constant start puts thousands of
     particles in a dense cell (above the cell limit), so they start from
     their own h scaled by a seeded U(0.95, 1.05) factor per particle; an
-    iteration that still crowds a cell is reported, not timed."""
+    iteration that still crowds a cell is reported, not timed.  The context
+    keeps the solver's working set between calls: the first call (which
+    allocates it) is timed apart from a second, steady-state one."""
     from paper_1804_06231_amd import PVError
     from synth import h_for_neighbours
     if s.name.startswith("uniform"):
@@ -490,16 +492,20 @@ def _bench_hsolve(ctx, s, pos, m, torch):
         start = "the workload's h times U(0.95, 1.05) (seed 7)"
         f = np.random.Generator(np.random.PCG64(7)).uniform(0.95, 1.05, s.n).astype(np.float32)
         h = torch.from_numpy(s.h * f).to(pos.device)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    try:
-        it, res = ctx.solve_h(pos, m, h, s.box, ngb=48.0, tol=1e-6, max_iter=40)
-    except PVError as e:
-        return {"start": start, "error": str(e)}
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3
+    times = []
+    for _ in range(2):
+        hh = h.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        try:
+            it, res = ctx.solve_h(pos, m, hh, s.box, ngb=48.0, tol=1e-6, max_iter=40)
+        except PVError as e:
+            return {"start": start, "error": str(e)}
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    ms = times[1]
     return {"iterations": it, "residual": res, "ms": ms, "ms_per_iteration": ms / max(it, 1),
-            "start": start, "tol": 1e-6}
+            "first_call_ms": times[0], "start": start, "tol": 1e-6}
 
 
 def _cpu_baseline_batched(b, target_seconds):

@@ -302,8 +302,9 @@ pv_status pv_drift(pv_ctx *ctx, pv_cells *cells, const float *disp);
  * Returns PV_OK when the iterations ran (compare *resid with tol to see
  * whether it converged within max_iter), or the error of a build (PV_EGRID when
  * a cut-off outgrows a third of the box, PV_EOVERFLOW for a crowded cell).
- * Allocates temporary device memory and synchronises every iteration; not for
- * graph capture. */
+ * Synchronises every iteration; not for graph capture.  Its working set (a
+ * cell structure and 3 n floats) stays on the context for the next call and
+ * grows when a call needs more; pv_destroy frees it. */
 pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float *pos,
                      const float *mass, float *h, const double *box, float ngb, float tol,
                      int max_iter, int *iters, float *resid);

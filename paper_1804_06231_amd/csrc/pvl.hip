@@ -24,6 +24,12 @@ struct pv_ctx {
     pvl::SweepTuning tune;                  // density sweeps
     pvl::SweepTuning tune_adj;              // adjoint sweep
     pvl::SweepTuning tune_plain;            // plain cell-list sweep
+    // pv_solve_h's working set, kept for the next call: its cells, and rho,
+    // drho_dh, the next h (3 x hbuf_n floats) and the residual word
+    pv_cells *hcells = nullptr;
+    float *hbuf = nullptr;
+    int64_t hbuf_n = 0;
+    uint32_t *hres = nullptr;
 };
 
 struct pv_cells {
@@ -205,6 +211,9 @@ void pv_destroy(pv_ctx *ctx)
     }
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     else (void)hipDeviceSynchronize();
+    if (ctx->hcells) pv_free_cells(ctx, ctx->hcells);
+    if (ctx->hbuf) (void)hipFree(ctx->hbuf);
+    if (ctx->hres) (void)hipFree(ctx->hres);
     if (ctx->dflags) (void)hipFree(ctx->dflags);
     if (ctx->dcensus) (void)hipFree(ctx->dcensus);
     if (ctx->hpinned) (void)hipHostFree(ctx->hpinned);
@@ -818,15 +827,27 @@ pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float 
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const float g = pvl::kGamma;
     const float eta3 = 3.0f * ngb / (4.0f * pvl::kPi * g * g * g);
-    float *buf = nullptr;       // rho, drho_dh, h_next
-    uint32_t *dres = nullptr;
-    HIPCHK(ctx, hipMalloc((void **)&buf, sizeof(float) * 3 * (size_t)std::max<int64_t>(n, 1)));
-    if (hipMalloc((void **)&dres, sizeof(uint32_t)) != hipSuccess) {
-        (void)hipFree(buf);
+    // the working set of the last call, grown when n is larger
+    if (n > ctx->hbuf_n || !ctx->hbuf) {
+        if (ctx->hbuf) (void)hipStreamSynchronize(ctx->stream);
+        if (ctx->hbuf) (void)hipFree(ctx->hbuf);
+        ctx->hbuf = nullptr;
+        ctx->hbuf_n = 0;
+        if (hipMalloc((void **)&ctx->hbuf, sizeof(float) * 3 * (size_t)std::max<int64_t>(n, 1)) !=
+            hipSuccess) {
+            ctx->hbuf = nullptr;
+            return fail(ctx, PV_ENOMEM, "solve_h: device allocation failed");
+        }
+        ctx->hbuf_n = std::max<int64_t>(n, 1);
+    }
+    if (!ctx->hres && hipMalloc((void **)&ctx->hres, sizeof(uint32_t)) != hipSuccess) {
+        ctx->hres = nullptr;
         return fail(ctx, PV_ENOMEM, "solve_h: device allocation failed");
     }
+    float *buf = ctx->hbuf;     // rho, drho_dh, h_next
+    uint32_t *dres = ctx->hres;
     float *rho = buf, *drho = buf + n, *hnext = buf + 2 * n;
-    pv_cells *cells = nullptr;
+    pv_cells *&cells = ctx->hcells;
     pv_status st = PV_OK;
     float r = INFINITY;
     int it = 0;
@@ -859,9 +880,6 @@ pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float 
             break;
         }
     }
-    if (cells) pv_free_cells(ctx, cells);
-    (void)hipFree(buf);
-    (void)hipFree(dres);
     if (iters) *iters = it;
     if (resid) *resid = r;
     if (st == PV_OK) ctx->err.clear();
