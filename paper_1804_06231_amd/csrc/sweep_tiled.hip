@@ -153,11 +153,12 @@ __device__ __forceinline__ void tile_interact_unit(float r2, float invH2, UnitAc
 }
 
 // Both terms of the adjoint for a source j within max(H_k, H_j) of receiver
-// k (d = x_j - x_k, r2 = |d|^2 > 0).  Receiver constants: H_k^2, 1/H_k,
-// ck = G_k 8 / (pi H_k^4), m_k; source: m_j, 1/H_j, cj = G_j 8 / (pi H_j^4),
-// H_j^2.  Accumulates dL/dx_k and sum m_j (3 w + u w') over r < H_k.
+// k (d = x_j - x_k, r2 = |d|^2 > 0; in_k: r < H_k, in_j: r < H_j).  Receiver
+// constants: 1/H_k, ck = G_k 8 / (pi H_k^4), m_k; source: m_j, 1/H_j,
+// cj = G_j 8 / (pi H_j^4).  Accumulates dL/dx_k and sum m_j (3 w + u w')
+// over r < H_k.
 __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, float r2, float mj,
-                                              float invHj, float cj, float Hj2, float Hk2,
+                                              float invHj, float cj, bool in_j, bool in_k,
                                               float invHk, float ck, float mk, GradAcc &a)
 {
     float invr = __builtin_amdgcn_rsqf(r2);   // v_rsq_f32, 1 ulp
@@ -174,8 +175,8 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
     float dwj = fmaf(-6.0f, tj2, uj * fmaf(18.0f, uj, -12.0f));
     // the receiver's own cut-off decides its term and its drho_dh sum, the
     // source's cut-off the source's term
-    const float mjk = r2 < Hk2 ? mj : 0.0f;
-    const float cmj = r2 < Hj2 ? cj * mk : 0.0f;
+    const float mjk = in_k ? mj : 0.0f;
+    const float cmj = in_j ? cj * mk : 0.0f;
     float coef = fmaf(ck * mjk, dwk, cmj * dwj);
     a.dh = fmaf(mjk, fmaf(uk, dwk, 3.0f * wk), a.dh);
     // (x_k - x_j) / r = -d / r
@@ -195,8 +196,10 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
         float ij = ror16<K>(sinv);                                        \
         float cj = ror16<K>(sc);                                          \
         float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                   \
-        if ((r2 < H2 || r2 < hj2) && r2 > 0.0f)                          \
-            grad_interact(dx, dy, dz, r2, mj, ij, cj, hj2, H2, invH, ck, mi, acc); \
+        /* bitwise, not short-circuit: one lane mask per step */      \
+        const bool in_k = r2 < H2, in_j = r2 < hj2;                       \
+        if ((in_k | in_j) & (r2 > 0.0f))                                  \
+            grad_interact(dx, dy, dz, r2, mj, ij, cj, in_j, in_k, invH, ck, mi, acc); \
     }
 
 // Lennard-Jones pair term (d = x_j - x_i, 0 < r2 < H_i^2).
