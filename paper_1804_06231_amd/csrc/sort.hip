@@ -286,11 +286,20 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
             const int b = key_bucket(k, kmin, scale, NB);
             const int q0 = (int)hist[b];
             const int q1 = b + 1 < NB ? (int)hist[b + 1] : cnt;
+            // four mates at a time (clamped indices, bitwise predicates), so
+            // each group's LDS reads are in flight together
             int rank = q0;
-            for (int q = q0; q < q1; ++q) {
-                const int r2 = border[q];
-                const float k2 = key[r2];
-                rank += (k2 < k) || (k2 == k && r2 < r);
+            for (int q = q0; q < q1; q += 4) {
+                int r2[4];
+                float k2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) r2[u] = border[min(q + u, q1 - 1)];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) k2[u] = key[r2[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    rank += (int)(q + u < q1) &
+                            ((int)(k2[u] < k) | ((int)(k2[u] == k) & (int)(r2[u] < r)));
             }
             forder[rank] = (uint16_t)r;
         }
@@ -324,8 +333,9 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
 // One launch per size class: the classes of at most 64 and 65..256
 // particles over all cells, each skipping the others; the cells of 257..512
 // and above 512 from the lists the cell finish made, so that a grid without
-// such cells launches only a few workgroups for them.  (Larger one-particle-per-thread classes measured slower than the
-// looping kernel: their LDS leaves two workgroups per compute unit.)
+// such cells launches only a few workgroups for them.  (Larger
+// one-particle-per-thread classes measured slower than the looping kernel:
+// their LDS leaves two workgroups per compute unit.)
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
