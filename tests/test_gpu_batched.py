@@ -93,16 +93,20 @@ def test_batched_matches_oracle_per_box(ctx):
 
 def test_batched_equals_one_box_at_a_time(ctx):
     """A box's results do not depend on the other boxes of the batch: each
-    item of the queue is computed the same way whichever workgroup takes it.
-    Bit for bit with the tail split off (the split set is chosen by cell index
-    within the whole structure, so a cell may be split in the batch and not
-    alone, which changes the summation order); within rounding with it on."""
+    item of the queue is computed the same way whichever workgroup takes it,
+    and runs of small cells are formed within each box's own rows.  Bit for
+    bit with the tail split off and a fixed run length (the split set is
+    chosen by cell index within the whole structure, and the automatic run
+    length by its cell count, so either may differ between the batch and the
+    box alone, which changes the summation order); within rounding with the
+    split on."""
     sets, grids = _boxes()
     off, arrs, boxes = _concat(sets)
     G = _seeded_g(int(off[-1]), 32)
     for parts in (1, 2):
         for sw in ("density", "adjoint"):
             ctx.set_param("tail_parts", parts, sw)
+            ctx.set_param("group", 4, sw)
         try:
             _, out, gp, gh = _run(ctx, off, arrs, boxes, grids, G)
             for b, s in enumerate(sets):
@@ -124,6 +128,7 @@ def test_batched_equals_one_box_at_a_time(ctx):
         finally:
             for sw in ("density", "adjoint"):
                 ctx.set_param("tail_parts", 2, sw)
+                ctx.set_param("group", 0, sw)
 
 
 def test_batched_auto_grid(ctx):
