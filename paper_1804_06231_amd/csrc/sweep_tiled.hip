@@ -337,6 +337,9 @@ struct SweepLds {
     int act_cell[26 * G];
     int task_off[27 * G + 1];
     int recv_off[26 * G];
+    // first slot and particles of each (cell, direction)'s neighbour (not
+    // kept by the plain sweep, whose LDS stays within five workgroups)
+    int nb_start[G > 1 ? 26 * G : 1], nb_cnt[G > 1 ? 26 * G : 1];
     // per cell of the item: first particle, count, largest cut-off,
     // displacement bound
     int gsa[G], gna[G];
@@ -486,6 +489,10 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         float sx, sy, sz;
         int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
         int sb = A.start[b], nb = A.start[b + 1] - sb;
+        if constexpr (!PLAIN) {
+            L.nb_start[tid] = sb;
+            L.nb_cnt[tid] = nb;
+        }
         if (!ADJ && !LJ) mb = A.cell_m[b];
         int act = 0;
         if (PLAIN) {
@@ -721,7 +728,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             nb_offset(dir, dx, dy, dz);
             float sx, sy, sz;
             int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
-            int sb = A.start[b], nb = A.start[b + 1] - sb;
+            const int sb = L.nb_start[26 * g + dir], nb = L.nb_cnt[26 * g + dir];
             int sign;
             int s = dir_canon(dx, dy, dz, &sign);
             float e[3];
@@ -846,8 +853,13 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         if (dir < 26) {
             nb_offset(dir, dx, dy, dz);
             int b = neighbour(B, geom_of(g), dx, dy, dz, shx, shy, shz);
-            sb = A.start[b];
-            nb = A.start[b + 1] - sb;
+            if constexpr (PLAIN) {
+                sb = A.start[b];
+                nb = A.start[b + 1] - sb;
+            } else {
+                sb = L.nb_start[26 * g + dir];
+                nb = L.nb_cnt[26 * g + dir];
+            }
             s = dir_canon(dx, dy, dz, &sign);
         }
         const int r = blk * 16 + l16;
