@@ -134,8 +134,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # grid: the workload's own, else the finest legal one (found once, then the
-    # cell structure is rebuilt in place every step with that grid)
     # grid: the workload's own, else the autotuner's (the finest legal one
     # with --no-autotune); the cell structure is rebuilt in place every step
     grid_tune = None
