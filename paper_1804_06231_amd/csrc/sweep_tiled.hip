@@ -1080,7 +1080,8 @@ __global__ void __launch_bounds__(kBlock) k_tail_combine(SweepArgs A)
 // whose particles fit one chunk together: each row of cells along z is cut
 // into blocks of `group` cells, and one thread per block fills runs greedily
 // in cell order (empty cells join the run they fall in; a run starts and ends
-// at a non-empty cell).  Items depend only on the cell counts and the box's
+// at a non-empty cell), then reserves its items' places with one atomic per
+// kind.  Items depend only on the cell counts and the box's
 // own cell numbering, not on the other boxes of a batch.
 __global__ void k_queue_items(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
                               const int32_t *__restrict__ start, int64_t ncell, int cap, int chunk,
@@ -1096,35 +1097,57 @@ __global__ void k_queue_items(const BoxDesc *__restrict__ box, const int32_t *__
         if (zr % group != 0) return;                      // not the first of a block
         end = (int)c0 + min(group, B.g[2] - zr);
     }
-    int first = -1, last = -1, sum = 0;   // the open run
-    auto close_run = [&]() {
-        if (first < 0) return;
-        const int p = atomicAdd(&qcount[1], 1);
-        items[cap - 1 - p] = make_int2(first, last > first ? -(last - first + 1) : 0);
-        first = -1;
-    };
-    for (int c = (int)c0; c < end; ++c) {
-        const int na = start[c + 1] - start[c];
-        if (na <= 0) continue;
-        if (na > chunk) {
-            close_run();
-            const int nch = (na + chunk - 1) / chunk;
-            const int p = atomicAdd(&qcount[0], nch);
-            for (int k = 0; k < nch; ++k) items[p + k] = make_int2(c, k);
-        } else if (c >= tail_from) {
-            close_run();
-            const int p = atomicAdd(&qcount[3], 1);
-            items[cap + p] = make_int2(c, 0);
-        } else if (first >= 0 && sum + na <= chunk) {
-            sum += na;
-            last = c;
-        } else {
-            close_run();
-            first = last = c;
-            sum = na;
+    // the block's cell counts, loaded side by side
+    int na[kGroupMax];
+#pragma unroll
+    for (int u = 0; u < kGroupMax; ++u) {
+        const int c = (int)c0 + u;
+        na[u] = c < end ? start[c + 1] - start[c] : 0;
+    }
+    // the block's items: the first pass counts them, the second writes them
+    // where one atomic per kind reserved their places
+    int base_small = 0, base_chunk = 0, base_tail = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        int nsmall = 0, nchunk = 0, ntail = 0;
+        int first = -1, last = -1, sum = 0;   // the open run
+        auto close_run = [&]() {
+            if (first < 0) return;
+            if (pass)
+                items[cap - 1 - (base_small + nsmall)] =
+                    make_int2(first, last > first ? -(last - first + 1) : 0);
+            ++nsmall;
+            first = -1;
+        };
+#pragma unroll
+        for (int u = 0; u < kGroupMax; ++u) {
+            const int c = (int)c0 + u;
+            if (na[u] <= 0) continue;   // empty, or past the block
+            if (na[u] > chunk) {
+                close_run();
+                const int nch = (na[u] + chunk - 1) / chunk;
+                if (pass)
+                    for (int k = 0; k < nch; ++k) items[base_chunk + nchunk + k] = make_int2(c, k);
+                nchunk += nch;
+            } else if (c >= tail_from) {
+                close_run();
+                if (pass) items[cap + base_tail + ntail] = make_int2(c, 0);
+                ++ntail;
+            } else if (first >= 0 && sum + na[u] <= chunk) {
+                sum += na[u];
+                last = c;
+            } else {
+                close_run();
+                first = last = c;
+                sum = na[u];
+            }
+        }
+        close_run();
+        if (pass == 0) {
+            if (nsmall) base_small = atomicAdd(&qcount[1], nsmall);
+            if (nchunk) base_chunk = atomicAdd(&qcount[0], nchunk);
+            if (ntail) base_tail = atomicAdd(&qcount[3], ntail);
         }
     }
-    close_run();
 }
 
 // Entries before the tail region; the tail region holds kTailMaxCells more.
