@@ -132,3 +132,15 @@ def test_tuning_parameters_without_gpu(lib, vctx):
     t = (C.c_float * 2)()
     assert lib.pv_autotune(vctx, None, 0, None, 3, t) == -1
     assert lib.pv_autotune(None, None, 0, None, 3, t) == -1
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark measures one GPU: asked for more it exits with a message
+    (before touching a device)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
