@@ -44,9 +44,11 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
 
 // Cells of at most MAXC particles, one particle per thread (blockDim = MAXC),
 // all 13 axes at once with the axis loops unrolled so that their LDS traffic
-// overlaps.  NB buckets per axis.  The histograms and the bucket-order lists
-// of in-cell ranks and keys live in LDS (about 25 KB for MAXC = 256), so
-// several cells share a compute unit; a particle's rank counts its bucket
+// overlaps.  NB buckets per axis (as many as particles for the 256 class:
+// fewer mates per bucket, fewer rank rounds, at five workgroups per compute
+// unit instead of seven).  The histograms and the bucket-order lists of
+// in-cell ranks and keys live in LDS (30 KB for MAXC = NB = 256), so several
+// cells share a compute unit; a particle's rank counts its bucket
 // mates with a smaller (key, in-cell rank), read from the bucket-order lists
 // with one LDS load each, the 13 axes' mates a round at a time.  Each
 // particle writes its own entries of the sorted lists at its ranks, and the
@@ -348,7 +350,7 @@ hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t n
         hipLaunchKernelGGL((k_sort13_small<64, 32, false>), dim3((unsigned)ncell), dim3(64), 0, st,
                            c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
                            c.tslots, c.tiles, 1, (const int32_t *)nullptr);
-    hipLaunchKernelGGL((k_sort13_small<256, 128, false>), dim3((unsigned)ncell), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_sort13_small<256, 256, false>), dim3((unsigned)ncell), dim3(256), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
                        c.tslots, c.tiles, dense ? 1 : 65, (const int32_t *)nullptr);
     // the cells of 257..512 particles, listed by the cell finish
