@@ -37,9 +37,25 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic VALU work of the sweep: lane-operations per pair that passes the
 # projected-distance test (3 differences, 3 products for r^2, compare, key
 # test) and per pair in range (square root at quarter rate = 4, scaling, both
-# spline pieces and the select, 3 accumulations and the count).
+# spline pieces and the select, 3 accumulations and the count).  Candidates
+# are those of the method's exact per-receiver bounds: Section 3.3's bounds on
+# the 26 neighbour cells and the receiver's cut-off in x in its own cell.
 OPS_PER_CANDIDATE = 8
 OPS_PER_INTERACTION = 25
+# Algorithmic HBM bytes per particle of each stage: binning reads positions
+# and h (16); the scatter into cell order reads them with the mass and writes
+# the cell-ordered position/mass, cut-off and index (48); the 13 per-axis
+# sorts read positions (12) and write 13 two-byte index lists (26); the sweep
+# reads positions, cut-offs and the lists and writes the 4 outputs (66).
+HBM_BYTES = {"bin": 16, "scatter": 48, "sort13": 38, "sweep": 66}
+# the kernels of each stage in a kernel trace (name prefixes)
+STAGE_KERNELS = {
+    "bin": ("pvl::k_bin_local", "pvl::k_bin_columns", "pvl::k_scan", "pvl::k_tile_sums",
+            "pvl::k_tile_scan", "pvl::k_cell_box"),
+    "scatter": ("pvl::k_scatter", "pvl::k_cell_finish"),
+    "sort13": ("pvl::k_sort13",),
+    "sweep": ("pvl::k_sweep_queue<0>", "pvl::k_tail_combine<0>", "pvl::k_queue_items"),
+}
 
 
 def _args():
@@ -155,9 +171,9 @@ def main():
     # candidate census (untimed)
     ctx.set_census(True)
     ctx.density(cells, "sorted")
-    cand_sorted, inr = ctx.census()
+    cand_sorted, inr, slots_sorted = ctx.census()
     ctx.density(cells, "plain")
-    cand_plain, _ = ctx.census()
+    cand_plain, _, slots_plain = ctx.census()
     ctx.set_census(False)
 
     gen = torch.Generator(device=dev)
@@ -224,6 +240,7 @@ def main():
         cpu = _cpu_baseline(s, a.cpu_seconds)
 
     traffic = _traffic(a.workload, "pvl::k_sweep_queue<0>")
+    stage_ms = {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep}
     rec = {
         "metric": "density pair-interactions/s + ns/particle, sorted-pair vs cell-list, 1 GPU",
         "value": value,
@@ -260,15 +277,92 @@ def main():
         "verlet_reuse": reuse,
         "lennard_jones": lj,
         "wall_ms_per_step": wall,
-        "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
-                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
-                     "work": f"{OPS_PER_CANDIDATE} lane-ops per pair admitted by the per-receiver "
-                             f"bounds + {OPS_PER_INTERACTION} per pair in range "
-                             f"({alg_ops / n:.0f} per particle)"},
+        "roofline": _roofline(a.workload, n, alg_ops, cand_sorted, inr, slots_sorted, ms_sweep,
+                              traffic),
+        "roofline_path": _path_roofline(n, alg_ops, ms_sorted),
+        "hbm_fraction": _hbm_fractions(a.workload, n, stage_ms),
         "cpu_baseline": cpu,
     }
+    rec["candidates_per_particle"]["tiled_slots_sorted"] = slots_sorted / n
+    rec["candidates_per_particle"]["tiled_slots_plain"] = slots_plain / n
     print(json.dumps(rec))
+
+
+def _roofline(workload, n, alg_ops, cand, inr, slots, ms_sweep, traffic):
+    """The density sweep against the vector-ALU peak: algorithmic lane-operations
+    (exact-bound candidates and pairs in range) per launch over the launch's
+    time, measured live on the library's stream."""
+    achieved = alg_ops / (ms_sweep * 1e-3) / 1e12
+    return {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
+            "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
+            "work": f"{OPS_PER_CANDIDATE} lane-ops per candidate of the exact per-receiver "
+                    f"bounds ({cand / n:.1f} per particle) + {OPS_PER_INTERACTION} per pair in "
+                    f"range ({inr / n:.1f}) = {alg_ops / n:.0f} lane-ops per particle",
+            "executed_pair_slots_per_particle": slots / n,
+            "slot_efficiency": inr / slots if slots else None}
+
+
+def _path_roofline(n, alg_ops, ms_step):
+    """The whole step (build + sort + sweep) against its binding roof: the
+    larger of the vector-ALU floor of the sweep's algorithmic work and the HBM
+    floor of the step's algorithmic bytes."""
+    alu_ms = alg_ops / (VALU_PEAK_TOPS * 1e12) * 1e3
+    hbm_bytes = sum(HBM_BYTES.values()) * n
+    hbm_ms = hbm_bytes / (HBM_PEAK_GBS * 1e9) * 1e3
+    bound = "alu" if alu_ms >= hbm_ms else "hbm"
+    return {"bound": bound, "floor_alu_ms": alu_ms, "floor_hbm_ms": hbm_ms,
+            "hbm_bytes_per_particle": sum(HBM_BYTES.values()), "ms_per_step": ms_step,
+            "frac": max(alu_ms, hbm_ms) / ms_step,
+            "hbm_frac_whole_step": hbm_ms / ms_step}
+
+
+def _hbm_fractions(workload, n, stage_ms):
+    """Algorithmic HBM bytes over time for the bandwidth-bound stages: from
+    the stage times measured here (several launches each), and per stage from
+    the kernel durations of the committed rocprofv3 summary of this workload
+    when it was taken on the current library sources."""
+    live = {}
+    for stage, key, b in (("build (bin + scatter)", "build_cells", HBM_BYTES["bin"] +
+                           HBM_BYTES["scatter"]),
+                          ("sort13", "sort_cells", HBM_BYTES["sort13"]),
+                          ("sweep", "density_sweep", HBM_BYTES["sweep"])):
+        tbs = b * n / (stage_ms[key] * 1e-3) / 1e12
+        live[stage] = {"bytes_per_particle": b, "ms": stage_ms[key], "achieved_TB_s": tbs,
+                       "frac": tbs / (HBM_PEAK_GBS / 1e3)}
+    out = {"peak_TB_s": HBM_PEAK_GBS / 1e3, "stages_live": live, "kernels_profiled": None}
+    prof = _profile(workload)
+    if prof is not None:
+        per = {}
+        for stage, names in STAGE_KERNELS.items():
+            us = 0.0
+            used = []
+            for k, v in prof["kernels"].items():
+                if k.startswith(names):
+                    # kernels launched once per step of the profiled command
+                    us += v["avg_us"]
+                    used.append(k)
+            if us > 0:
+                tbs = HBM_BYTES[stage] * n / (us * 1e-6) / 1e12
+                per[stage] = {"kernels": sorted(used), "us": us,
+                              "bytes_per_particle": HBM_BYTES[stage], "achieved_TB_s": tbs,
+                              "frac": tbs / (HBM_PEAK_GBS / 1e3)}
+        out["kernels_profiled"] = per
+    return out
+
+
+def _profile(workload):
+    """The committed rocprofv3 summary of this workload, if it was taken on
+    the current library sources."""
+    from paper_1804_06231_amd.rocprof_summary import source_hash
+    path = os.path.join(ROOT, "profiles", f"{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec
 
 
 def bench_batched(a, b, torch, pvl, t0):
@@ -305,7 +399,7 @@ def bench_batched(a, b, torch, pvl, t0):
     pairs = int(nc.sum().item())
     ctx.set_census(True)
     ctx.density(cells, "sorted")
-    cand, inr = ctx.census()
+    cand, inr, slots = ctx.census()
     ctx.set_census(False)
     tuning = _autotune(a, ctx, cells, g_rho, ("density", "adjoint"))
 
@@ -392,13 +486,8 @@ def bench_batched(a, b, torch, pvl, t0):
         "autotune": tuning,
         "grid_autotune": grid_tune,
         "wall_ms_per_step": wall_graph,
-        "roofline": {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
-                     "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                     "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": _traffic(b.name, "pvl::k_sweep_queue<0>"),
-                     "work": f"{OPS_PER_CANDIDATE} lane-ops per pair admitted by the per-receiver "
-                             f"bounds + {OPS_PER_INTERACTION} per pair in range "
-                             f"({alg_ops / n:.0f} per particle)"},
+        "roofline": _roofline(b.name, n, alg_ops, cand, inr, slots, ms_sweep,
+                              _traffic(b.name, "pvl::k_sweep_queue<0>")),
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))
@@ -534,13 +623,8 @@ def _cpu_baseline_batched(b, target_seconds):
 def _traffic(workload, kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary of this workload, if it was taken on the current library sources."""
-    from paper_1804_06231_amd.rocprof_summary import source_hash
-    path = os.path.join(ROOT, "profiles", f"{workload}.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    if rec.get("source_hash") != source_hash():
+    rec = _profile(workload)
+    if rec is None:
         return None
     t = rec.get("traffic", {}).get(kernel)
     if not t:
@@ -548,25 +632,61 @@ def _traffic(workload, kernel):
     return t["fetch_bytes"] + t["write_bytes"]
 
 
+def _omp_threads(k):
+    """Set the OpenMP thread count of this process (the oracle's parallel
+    loops) and return the previous one."""
+    import ctypes
+    gomp = ctypes.CDLL("libgomp.so.1")
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(int(k))
+    return prev
+
+
 def _cpu_baseline(s, target_seconds):
-    """fp64 oracle (C + OpenMP cell-list brute force) on a sample of receivers."""
+    """fp64 oracle (C + OpenMP cell-list brute force) on a sample of receivers:
+    the median of 5 runs on all host threads (the paper's timing takes the
+    median of 5 runs), and one run on one thread over an eighth of the sample
+    (the paper's figures are single-thread)."""
     from oracle import Oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     o = Oracle(s.pos, s.h, s.m, s.box)
+    threads = _omp_threads(0) or 1
+    _omp_threads(threads)
     rng = np.random.Generator(np.random.PCG64(123))
+    per_run = target_seconds / 8.0     # 5 runs + the one-thread run ~ 8 runs' time
     k = 16384
     while True:
         idx = np.sort(rng.choice(s.n, min(k, s.n), replace=False))
         t0 = time.perf_counter()
         d = o.density(idx)
         dt = time.perf_counter() - t0
-        if dt > 0.4 * target_seconds or k >= s.n:
+        if dt > 0.5 * per_run or k >= s.n:
             break
-        k = min(s.n, int(k * max(2.0, 0.5 * target_seconds / max(dt, 1e-3))))
+        k = min(s.n, int(k * max(2.0, 0.7 * per_run / max(dt, 1e-3))))
     pairs = int(d["ncount"].sum())
-    return {"value": pairs / dt, "unit": "pair-interactions/s", "cores": threads, "kind": "oracle",
+    runs = [dt]
+    for _ in range(4):
+        t0 = time.perf_counter()
+        o.density(idx)
+        runs.append(time.perf_counter() - t0)
+    med = float(np.median(runs))
+    sub = idx[: max(1, idx.size // 8)]
+    prev = _omp_threads(1)
+    try:
+        t0 = time.perf_counter()
+        d1 = o.density(sub)
+        dt1 = time.perf_counter() - t0
+    finally:
+        _omp_threads(prev)
+    pairs1 = int(d1["ncount"].sum())
+    return {"value": pairs / med, "unit": "pair-interactions/s", "cores": threads,
+            "kind": "oracle",
             "sample": f"{idx.size} of {s.n} receivers (uniform random), full 27-cell fp64 "
-                      f"brute force, {dt:.2f}s", "ns_per_particle": dt * 1e9 / idx.size}
+                      f"brute force, median of 5 runs ({min(runs):.2f}-{max(runs):.2f}s)",
+            "ns_per_particle": med * 1e9 / idx.size,
+            "runs_s": runs,
+            "one_thread": {"value": pairs1 / dt1, "unit": "pair-interactions/s", "cores": 1,
+                           "sample": f"{sub.size} receivers (the first eighth of the sample), "
+                                     f"{dt1:.2f}s", "ns_per_particle": dt1 * 1e9 / sub.size}}
 
 
 if __name__ == "__main__":

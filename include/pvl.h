@@ -159,15 +159,22 @@ pv_status pv_cells_info(pv_ctx *ctx, const pv_cells *cells, int grid[3], int64_t
 pv_status pv_cells_export(pv_ctx *ctx, const pv_cells *cells, int32_t *cell_start,
                           int32_t *order, uint16_t *sorted);
 
-/* Candidate census of the last pv_density call made with census enabled:
- * counts[0] = pairs tested by the distance check, counts[1] = pairs in range
- * (non-self).  pv_set_census(ctx, 1) enables counting: the density is then
- * computed by scalar kernels that test exactly the pairs admitted by the
- * per-receiver bounds of Section 3.3 (sorted) or the 27-cell stencil (plain),
- * so counts[0] is the method's candidate count, not the tiled kernels'
- * padded one (slower). */
+/* Candidate census of the last pv_density call made with census enabled
+ * (host array of 3):
+ *   counts[0]  pairs tested by the distance check under the method's exact
+ *              per-receiver bounds: Section 3.3's bounds on the 26 neighbour
+ *              cells and, in the receiver's own cell, the particles whose x
+ *              lies within the receiver's cut-off (sorted), or every particle
+ *              of the 27-cell stencil (plain), self excluded;
+ *   counts[1]  pairs in range (self excluded);
+ *   counts[2]  pair slots the production (tiled) sweep executes: 16 x 16 per
+ *              source tile of each task of 16 receivers, including the slots
+ *              of padding lanes and of pairs the tiles' coarser bounds admit.
+ * pv_set_census(ctx, 1) enables counting: pv_density then runs scalar kernels
+ * that test exactly the pairs of counts[0], followed by the tiled sweep
+ * (whose outputs are the ones returned); slower. */
 pv_status pv_set_census(pv_ctx *ctx, int enable);
-pv_status pv_census(pv_ctx *ctx, int64_t counts[2]);
+pv_status pv_census(pv_ctx *ctx, int64_t counts[3]);
 
 /* Tuning parameters of the sweep kernels (all results are identical up to
  * floating-point summation order; only speed changes).  Values persist on

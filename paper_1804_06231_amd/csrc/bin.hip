@@ -194,9 +194,7 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, const int32_t *cou
 // offsets, k_tile_scan scans each tile from its offset.
 constexpr int kScanThreads = 1024;
 constexpr int kScanPer = 8;
-constexpr int kScanTile = kScanThreads * kScanPer;
-
-int scan_scratch_words(int64_t ncell) { return (int)(ncell / kScanTile + 2); }
+static_assert(kScanTile == kScanThreads * kScanPer, "scan tile");
 
 __device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *red, int32_t &total)
 {

@@ -81,6 +81,24 @@ __device__ __forceinline__ int next_pow2(int v)
     return p;
 }
 
+// Outputs of a sweep that does not run because an error was flagged
+// before it (a crowded cell, a cut-off above the cell edge, a drift past the
+// cells): NaN in every float output and -1 in the counts, written by the
+// whole grid, so that no output is left as it was.
+__device__ __forceinline__ void fill_error_outputs(int64_t n, float *a, int64_t na, float *b,
+                                                   float *c, int32_t *cnt)
+{
+    const float q = __builtin_nanf("");
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        if (a)
+            for (int64_t k = 0; k < na; ++k) a[na * i + k] = q;
+        if (b) b[i] = q;
+        if (c) c[i] = q;
+        if (cnt) cnt[i] = -1;
+    }
+}
+
 struct CellGeom {
     int cx, cy, cz;
     float ox, oy, oz;

@@ -18,7 +18,8 @@ struct pv_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     int *dflags = nullptr;                  // [0] sticky error bits, [1] max occupancy
-    unsigned long long *dcensus = nullptr;  // [0] pairs tested, [1] pairs in range
+    unsigned long long *dcensus = nullptr;  // [0] pairs tested, [1] pairs in range,
+                                            // [2] pair slots of the tiled sweep
     int census_on = 0;
     int *hpinned = nullptr;                 // pinned read-back area (64 bytes)
     pvl::SweepTuning tune;                  // density sweeps
@@ -183,7 +184,7 @@ pv_status pv_create(int device, void *hip_stream, pv_ctx **out)
     ctx->device = device;
     ctx->stream = (hipStream_t)hip_stream;
     if (hipMalloc((void **)&ctx->dflags, 4 * sizeof(int)) != hipSuccess ||
-        hipMalloc((void **)&ctx->dcensus, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&ctx->dcensus, 3 * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void **)&ctx->hpinned, 64, hipHostMallocDefault) != hipSuccess) {
         pv_destroy(ctx);
         return PV_ENOMEM;
@@ -193,7 +194,7 @@ pv_status pv_create(int device, void *hip_stream, pv_ctx **out)
         ctx->tune.num_cu = ctx->tune_adj.num_cu = ctx->tune_plain.num_cu =
             prop.multiProcessorCount;
     if (hipMemset(ctx->dflags, 0, 4 * sizeof(int)) != hipSuccess ||
-        hipMemset(ctx->dcensus, 0, 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(ctx->dcensus, 0, 3 * sizeof(unsigned long long)) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
         pv_destroy(ctx);
         return PV_EHIP;
@@ -407,7 +408,7 @@ pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rh
     if (algo == PV_SORTED_PAIR && !cells->sorted)
         return fail(ctx, PV_ESTATE, "pv_sort_cells must run before a sorted-pair density");
     if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
-    if (ctx->census_on) HIPCHK(ctx, pvl::launch_zero(ctx->stream, ctx->dcensus, 4));
+    if (ctx->census_on) HIPCHK(ctx, pvl::launch_zero(ctx->stream, ctx->dcensus, 6));
     HIPCHK(ctx, pvl::launch_sweep(ctx->stream, cells->d, cells->n, cells->ncell, (int)algo, rho,
                                   wcount, drho_dh, ncount, ctx->dflags,
                                   ctx->census_on ? ctx->dcensus : nullptr,
@@ -507,14 +508,16 @@ pv_status pv_set_census(pv_ctx *ctx, int enable)
     return PV_OK;
 }
 
-pv_status pv_census(pv_ctx *ctx, int64_t counts[2])
+pv_status pv_census(pv_ctx *ctx, int64_t counts[3])
 {
     if (!ctx || !counts) return PV_EINVAL;
-    unsigned long long v[2];
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    unsigned long long v[3];
     HIPCHK(ctx, hipMemcpyAsync(v, ctx->dcensus, sizeof(v), hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     counts[0] = (int64_t)v[0];
     counts[1] = (int64_t)v[1];
+    counts[2] = (int64_t)v[2];
     return PV_OK;
 }
 

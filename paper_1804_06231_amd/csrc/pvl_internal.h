@@ -164,8 +164,10 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
                       int *dflags);
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell);
 hipError_t launch_zero(hipStream_t st, void *p, int64_t words);
-// Words of scratch the cell-count scan needs for ncell cells.
-int scan_scratch_words(int64_t ncell);
+// Cells per tile of the cell-count scan, and the words of scratch the scan
+// needs for ncell cells (tile sums and offsets).
+constexpr int kScanTile = 8192;
+constexpr int64_t scan_scratch_words(int64_t ncell) { return ncell / kScanTile + 2; }
 // Sweep tuning (see pv_param).
 struct SweepTuning {
     int reach_order = 0;
@@ -187,8 +189,18 @@ constexpr int kTailMaxCells = 2048;
 constexpr int kTailMaxParts = 4;
 constexpr int kTailRecv = 256;
 
-// Entries of the work queue for n particles in ncell cells.
-int64_t queue_capacity(int64_t n, int64_t ncell);
+// Smallest receivers per work item (sizes the work queue).
+constexpr int kChunkMin = 32;
+// Entries of the work queue for n particles in ncell cells: the items, then
+// a tail region of kTailMaxCells entries.
+constexpr int64_t queue_main(int64_t n, int64_t ncell) { return ncell + n / kChunkMin + 1; }
+constexpr int64_t queue_capacity(int64_t n, int64_t ncell)
+{
+    return queue_main(n, ncell) + kTailMaxCells;
+}
+// Persistent workgroups of a queue sweep, and the cells of its split tail.
+int64_t queue_grid(const SweepTuning &tune, int64_t ncell);
+int tail_cells_of(const SweepTuning &tune, int64_t ncell);
 // Work-queue counters: large-cell chunks, single-chunk cells, the head of the
 // dynamic queue, and the split tail cells.
 constexpr int kQueueCounters = 4;
@@ -196,9 +208,12 @@ constexpr int kQueueCounters = 4;
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,
                         int *dflags, unsigned long long *census, const SweepTuning &tune);
+// slots (may be NULL): adds the pair slots the sweep executes (16 x 16 per
+// source tile of each row task)
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                              int *dflags, const SweepTuning &tune, bool plain);
+                              int *dflags, const SweepTuning &tune, bool plain,
+                              unsigned long long *slots = nullptr);
 hipError_t launch_lj_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                            float eps, float sigma, float *force, float *energy, int *dflags,
                            const SweepTuning &tune);

@@ -52,11 +52,14 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
 // mates with a smaller (key, in-cell rank), read from the bucket-order lists
 // with one LDS load each, the 13 axes' mates a round at a time.  Each
 // particle writes its own entries of the sorted lists at its ranks, and the
-// first keys of the tiles of 16 positions.  Six waves per SIMD at least (four
-// for the 512 class, which spills at six): the register bound keeps the
-// rounds' loads from costing occupancy.
+// first keys of the tiles of 16 positions.  The register bound matches the
+// occupancy the LDS allows (six waves per SIMD for the 64 class, five for
+// the 256 class with 256 buckets, 30 KB of LDS per workgroup; four for the
+// 512 class, which spills at six), so that the rounds' loads cost no
+// occupancy and no register is given up for waves that cannot run.
 template <int MAXC, int NB, bool LIST>
-__global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(MAXC > 256 ? 4 : 6)))
+__global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(
+    MAXC > 256 ? 4 : (MAXC == 256 && NB == 256 ? 5 : 6))))
 k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
                const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
                const float *__restrict__ Hc, int64_t n, uint16_t *__restrict__ sidx,

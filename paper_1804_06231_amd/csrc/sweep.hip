@@ -8,7 +8,8 @@
 //                   is below the receiver's cut-off are tested; in the sorted
 //                   list of the neighbour they form a prefix (neighbour ahead
 //                   on the axis) or a suffix (behind), found by binary search.
-//                   The receiver's own cell is swept in full.
+//                   In the receiver's own cell (x order) the particles within
+//                   H_i in x form one range, also found by binary search.
 //
 // Both kernels run one workgroup per receiver cell and finish in place: the
 // self term is added, the sums are normalised and written in the caller's
@@ -111,7 +112,10 @@ __global__ void __launch_bounds__(kBlock) k_sweep_plain(
     float *drho_dh, int32_t *ncount, const int *__restrict__ dflags,
     unsigned long long *census, int only_above)
 {
-    if (dflags[0]) return;
+    if (dflags[0]) {
+        fill_error_outputs(start[gridDim.x] - start[0], rho, 1, wcount, drho_dh, ncount);
+        return;
+    }
     const int a = blockIdx.x;
     const int sa = start[a];
     const int na = start[a + 1] - sa;
@@ -158,7 +162,10 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
     const float *__restrict__ cell_dx, int64_t n, float *rho, float *wcount, float *drho_dh,
     int32_t *ncount, const int *__restrict__ dflags, unsigned long long *census, int only_above)
 {
-    if (dflags[0]) return;
+    if (dflags[0]) {
+        fill_error_outputs(n, rho, 1, wcount, drho_dh, ncount);
+        return;
+    }
     const int a = blockIdx.x;
     const int sa = start[a];
     const int na = start[a + 1] - sa;
@@ -176,13 +183,20 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
         DensityAcc acc = {0.f, 0.f, 0.f, 0};
         unsigned long long tested = 0;
         if (act) {
-            // own cell: every other particle
-            for (int j = 0; j < na; ++j) {
+            // own cell: the cell order is x order (the x axis' sorted keys),
+            // so the particles with |x_j - x_i| < H_i form one range, found
+            // by two binary searches (widened by the rounding slack and by
+            // twice the cell's displacement bound after a drift)
+            const float *kx = skey + (size_t)kTileAxisX * n + sa;
+            const float wx = Hi + slack + 2.0f * cell_dx[a];
+            const int j0 = bsearch_keys(kx, na, pi.x - wx, true);
+            const int j1 = bsearch_keys(kx, na, pi.x + wx, false);
+            for (int j = j0; j < j1; ++j) {
                 if (j == i) continue;
                 float4 q = xyzm[sa + j];
                 density_pair(q.x - pi.x, q.y - pi.y, q.z - pi.z, q.w, H2, invH, acc);
             }
-            tested += (unsigned long long)(na - 1);
+            tested += (unsigned long long)(j1 - j0 - (i >= j0 && i < j1 ? 1 : 0));
             for (int o = 0; o < 27; ++o) {
                 if (o == 13) continue;
                 int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
@@ -235,7 +249,8 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
     if (ncell == 0 || n == 0) return hipSuccess;
     if (census) {
         // the census counts the candidates of the exact per-receiver bounds
-        // (scalar kernels: one receiver per lane, no tiles)
+        // (scalar kernels: one receiver per lane, no tiles), then the pair
+        // slots the tiled sweep executes (its outputs replace the scalar ones)
         if (algo == PV_PLAIN_CELL)
             hipLaunchKernelGGL(k_sweep_plain, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                                c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, rho, wcount,
@@ -244,11 +259,11 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
             hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
                                c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey,
                                c.cell_dx, n, rho, wcount, drho_dh, ncount, dflags, census, 0);
-    } else {
-        return launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags, tune,
-                                  algo == PV_PLAIN_CELL);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return launch_sweep_tiled(st, c, n, ncell, rho, wcount, drho_dh, ncount, dflags, tune,
+                              algo == PV_PLAIN_CELL, census ? census + 2 : nullptr);
 }
 
 }  // namespace pvl

@@ -74,7 +74,6 @@ constexpr int kModeLJ = 3;
 
 constexpr int kChunk = 256;                    // largest receivers per work item
 static_assert(kChunk == kTailRecv, "tail slots hold one chunk");
-constexpr int kChunkMin = 32;                  // smallest (sizes the queue)
 // Cells per work item that a mode's LDS holds: the plain sweep takes one cell
 // per item (its smaller LDS then leaves room for five workgroups per compute
 // unit), the others up to kGroupMax.
@@ -153,7 +152,9 @@ __device__ __forceinline__ void tile_interact_unit(float r2, float invH2, UnitAc
 }
 
 // Both terms of the adjoint for a source j within max(H_k, H_j) of receiver
-// k (d = x_j - x_k, r2 = |d|^2 > 0; in_k: r < H_k, in_j: r < H_j).  Receiver
+// k (d = x_j - x_k, r2 = |d|^2; in_k: r < H_k, in_j: r < H_j).  A source at
+// the receiver's position (r2 = 0, a distinct coincident particle) adds
+// 3 w(0) m_j to the drho_dh sum and nothing to the gradient.  Receiver
 // constants: 1/H_k, ck = G_k 8 / (pi H_k^4), m_k; source: m_j, 1/H_j,
 // cj = G_j 8 / (pi H_j^4).  Accumulates dL/dx_k and sum m_j (3 w + u w')
 // over r < H_k.
@@ -161,7 +162,7 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
                                               float invHj, float cj, bool in_j, bool in_k,
                                               float invHk, float ck, float mk, GradAcc &a)
 {
-    float invr = __builtin_amdgcn_rsqf(r2);   // v_rsq_f32, 1 ulp
+    float invr = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;   // v_rsq_f32, 1 ulp
     float r = r2 * invr;
     float uk = r * invHk;
     float uj = r * invHj;
@@ -198,7 +199,7 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
         float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                   \
         /* bitwise, not short-circuit: one lane mask per step */      \
         const bool in_k = r2 < H2, in_j = r2 < hj2;                       \
-        if ((in_k | in_j) & (r2 > 0.0f))                                  \
+        if (in_k | in_j)                                                  \
             grad_interact(dx, dy, dz, r2, mj, ij, cj, in_j, in_k, invH, ck, mi, acc); \
     }
 
@@ -323,6 +324,7 @@ struct SweepArgs {
     int reach_order;
     int task_sort;
     int chunk;           // receivers per work item: a multiple of 16 in [kChunkMin, kChunk]
+    unsigned long long *slots;   // census: pair slots executed (NULL: not counted)
 };
 
 template <int G>
@@ -889,6 +891,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         // the own cell's diagonal tile pairs each receiver with itself at K = 0
         const int diag = dir == 26 ? (r_lo >> 4) + blk : -1;
 
+        if (A.slots && row_valid && l16 == 0) atomicAdd(A.slots, 256ull * (unsigned)nt);
         int ntmax = nt;
         ntmax = max(ntmax, __shfl_xor(ntmax, 16));
         ntmax = max(ntmax, __shfl_xor(ntmax, 32));
@@ -1021,7 +1024,16 @@ __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(MODE == kModePlain ? 5 : 4, 8))) k_sweep_queue(SweepArgs A)
 {
     __shared__ SweepLds<group_cap(MODE)> L;
-    if (A.dflags[0]) return;
+    if (A.dflags[0]) {
+        // an error flagged before the sweep (pv_check reports it)
+        if constexpr (MODE == kModeAdjoint)
+            fill_error_outputs(A.n, A.grad_pos, 3, A.grad_h, nullptr, nullptr);
+        else if constexpr (MODE == kModeLJ)
+            fill_error_outputs(A.n, A.force, 3, A.energy, nullptr, nullptr);
+        else
+            fill_error_outputs(A.n, A.rho, 1, A.wcount, A.drho_dh, A.ncount);
+        return;
+    }
     const int nbig = A.qcount[0], nsmall = A.qcount[1];
     // the tail cells (a fixed set: single-chunk cells among the last
     // tail_cells cells) run after all others, as tail_parts items each, so
@@ -1053,6 +1065,8 @@ __global__ void __launch_bounds__(kBlock)
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_tail_combine(SweepArgs A)
 {
+    // the sweep did not run (its workgroups wrote the error outputs)
+    if (A.dflags[0]) return;
     const int ntail = A.qcount[3];
     const int slot = blockIdx.x;
     if (slot >= ntail) return;
@@ -1150,9 +1164,25 @@ __global__ void k_queue_items(const BoxDesc *__restrict__ box, const int32_t *__
     }
 }
 
-// Entries before the tail region; the tail region holds kTailMaxCells more.
-static int64_t queue_main(int64_t n, int64_t ncell) { return ncell + n / kChunkMin + 1; }
-int64_t queue_capacity(int64_t n, int64_t ncell) { return queue_main(n, ncell) + kTailMaxCells; }
+// Persistent workgroups of a queue sweep: a few per compute unit, never more
+// than the cells.
+int64_t queue_grid(const SweepTuning &tune, int64_t ncell)
+{
+    const int64_t wgs = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
+    return std::max<int64_t>(1, std::min<int64_t>(wgs, ncell));
+}
+
+// Cells of the split tail.  Auto: a quarter of the workgroups' worth of
+// cells, when the queue holds at least two cells per workgroup (with fewer
+// there is no tail to trim).
+int tail_cells_of(const SweepTuning &tune, int64_t ncell)
+{
+    const int64_t grid = queue_grid(tune, ncell);
+    return tune.tail_parts == 1 ? 0
+           : tune.tail_cells > 0 ? tune.tail_cells
+           : ncell >= 2 * grid  ? (int)std::min<int64_t>(grid / 4, kTailMaxCells)
+                                : 0;
+}
 
 // Queue set-up and the persistent sweep in the given mode.
 static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
@@ -1160,11 +1190,8 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
 {
     if (ncell == 0 || n == 0) return hipSuccess;
     const int cap = (int)queue_main(n, ncell);
-    // persistent workgroups: a few per compute unit, never more than the cells
     const int64_t wgs = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
-    int64_t grid = wgs;
-    if (grid > ncell) grid = ncell;
-    if (grid < 1) grid = 1;
+    const int64_t grid = queue_grid(tune, ncell);
     // small cells per item, at most.  Auto: eight with at least 16 cells per
     // workgroup (long runs then still leave every workgroup several items),
     // four with at least two, two with at least one, else one cell per item
@@ -1177,12 +1204,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     group = std::min(group, group_cap(mode));
     if (group < 1 || group > kGroupMax) return hipErrorInvalidValue;
     A.tail_parts = tune.tail_parts;
-    // auto: a quarter of the workgroups' worth of cells, when the queue holds
-    // at least two cells per workgroup (with fewer there is no tail to trim)
-    A.tail_cells = tune.tail_parts == 1 ? 0
-                   : tune.tail_cells > 0 ? tune.tail_cells
-                   : ncell >= 2 * grid  ? (int)std::min<int64_t>(grid / 4, kTailMaxCells)
-                                        : 0;
+    A.tail_cells = tail_cells_of(tune, ncell);
     // the counters (chunks, cells, head, tail cells) start at zero
     hipError_t e = launch_zero(st, c.qcount, kQueueCounters);
     if (e != hipSuccess) return e;
@@ -1236,9 +1258,11 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
 
 hipError_t launch_sweep_tiled(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                               float *rho, float *wcount, float *drho_dh, int32_t *ncount,
-                              int *dflags, const SweepTuning &tune, bool plain)
+                              int *dflags, const SweepTuning &tune, bool plain,
+                              unsigned long long *slots)
 {
     SweepArgs A = {};
+    A.slots = slots;
     A.rho = rho;
     A.wcount = wcount;
     A.drho_dh = drho_dh;

@@ -372,10 +372,13 @@ class Context:
         self._call("pv_set_census", 1 if on else 0)
 
     def census(self):
-        v = (C.c_int64 * 2)()
+        """(pairs tested under the exact per-receiver bounds, pairs in range,
+        pair slots of the tiled sweep) of the last density call made with the
+        census on."""
+        v = (C.c_int64 * 3)()
         self._sync_stream()
         self._call("pv_census", v)
-        return int(v[0]), int(v[1])
+        return int(v[0]), int(v[1]), int(v[2])
 
 
 _contexts = {}
@@ -399,6 +402,10 @@ class _DensityFn(torch.autograd.Function):
         if algo == "sorted" or pos.requires_grad or h.requires_grad:
             ctx.sort_cells(cells)
         rho, wc, dh, nc = ctx.density(cells, algo)
+        # device-detected errors (a cut-off above the cell edge of an explicit
+        # grid, a crowded cell) raise here rather than leave the context's
+        # error word set for later calls
+        ctx.check()
         fctx.cells = cells
         fctx.mark_non_differentiable(wc, dh, nc)
         return rho, wc, dh, nc
@@ -410,6 +417,7 @@ class _DensityFn(torch.autograd.Function):
         if g_rho is None:
             return None, None, None, None, None, None
         gp, gh = ctx.density_backward(cells, g_rho.contiguous().float())
+        ctx.check()
         need_p, need_h = fctx.needs_input_grad[0], fctx.needs_input_grad[1]
         return (gp if need_p else None), (gh if need_h else None), None, None, None, None
 

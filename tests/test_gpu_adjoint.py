@@ -123,3 +123,25 @@ def test_adjoint_against_finite_differences(ctx):
     allow = 1e-5 * scale + np.abs(pick(r64) - pick(r32)) + trunc
     err = np.abs(gpu - fd) / allow
     assert np.max(err) < 1.0, f"max FD err / allowance {np.max(err)}"
+
+
+def test_adjoint_with_coincident_particles(ctx):
+    """Distinct particles at one position: each is the other's neighbour at
+    r = 0, so it adds 3 w(0) m_j to drho_dh (and dL/dh = G drho_dh) but nothing
+    to dL/dx.  Copies take the original's h as well, so every pair keeps the
+    generator's distance from the cut-offs."""
+    from gpu_common import compare_density, run_density
+    s = uniform_set(6000, 12, hmode="jitter")
+    rng = np.random.Generator(np.random.PCG64(13))
+    src = rng.choice(s.n // 2, 8, replace=False)
+    dst = s.n // 2 + src
+    s.pos[dst] = s.pos[src]
+    s.h[dst] = s.h[src]
+    o = oracle_for(s)
+    ref = o.density()
+    assert np.all(ref["ncount"][dst] >= 1)
+    _, got = run_density(ctx, s)
+    compare_density(got, ref, label="coincident density")
+    G = rng.standard_normal(s.n).astype(np.float32)
+    gp, gh = _gpu_grad(ctx, s, G)
+    _check(gp, gh, o.grad(G.astype(np.float64)), label="coincident adjoint")

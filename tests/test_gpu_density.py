@@ -190,6 +190,34 @@ def test_overflow_and_grid_errors_are_reported(ctx):
     compare_density(out, oracle_for(s).density(), label="after-errors")
 
 
+def test_flagged_error_leaves_no_stale_outputs(ctx):
+    """A sweep after a device-detected error writes NaN (counts -1) instead
+    of leaving its outputs as they were; the differentiable entry point
+    raises at once, and the next call on the same context is correct."""
+    import paper_1804_06231_amd as pvl
+    s = uniform_set(3000, 43, hmode="const")
+    p, hh, mm = upload(s)
+    cells = ctx.build_cells(p, hh, mm, (1.0, 1.0, 1.0), grid=12)    # finer than the cut-off
+    ctx.sort_cells(cells)
+    out = [torch.zeros(s.n, device=dev()) for _ in range(3)] + \
+          [torch.zeros(s.n, dtype=torch.int32, device=dev())]
+    ctx.density(cells, "sorted", out)
+    torch.cuda.synchronize()
+    assert all(torch.isnan(t).all().item() for t in out[:3])
+    assert (out[3] == -1).all().item()
+    with pytest.raises(pvl.PVError, match="EGRID"):
+        ctx.check()
+    pg = p.clone().requires_grad_(True)
+    with pytest.raises(pvl.PVError, match="EGRID"):
+        pvl.density(pg, mm, hh, grid=12)
+    rho, wc, dh, nc = pvl.density(pg, mm, hh)                       # auto grid, clean again
+    (rho * rho).sum().backward()
+    ref = oracle_for(s).density()
+    compare_density([t.detach().cpu().numpy() for t in (rho, wc, dh, nc)], ref,
+                    label="after-flag")
+    assert torch.isfinite(pg.grad).all().item()
+
+
 def test_deterministic_and_permutation_invariant(ctx):
     s = uniform_set(20000, 51, hmode="lognormal")
     _, a = run_density(ctx, s, "sorted")
@@ -248,7 +276,42 @@ def test_census_sorted_vs_plain(ctx):
         cells_count[((c // 64 + dx) % 8) * 64 + ((c // 8 % 8 + dy) % 8) * 8 + (c % 8 + dz) % 8]
         for dx in (-1, 0, 1) for dy in (-1, 0, 1) for dz in (-1, 0, 1)) for c in range(512)) - n)
     assert cs[0] < 0.2 * cp[0]
-    print(f"census per particle: sorted {cs[0] / n:.1f}, plain {cp[0] / n:.1f}, in range {cs[1] / n:.1f}")
+    # the tiled sweeps execute at least the candidates of the exact bounds
+    assert cs[2] >= cs[0] and cp[2] >= cp[0]
+    # the sorted candidates by definition (fp64, no rounding slack): the 26
+    # neighbour cells' pairs with (x_j - x_i) . d/|d| < H_i, the own cell's
+    # with |x_j - x_i| < H_i; the GPU's slack of 2^-16 of the cell edges can
+    # only add the rare pairs within it of a bound
+    exact = _census_by_definition(s, 8)
+    assert exact <= cs[0] <= exact * 1.002, (exact, cs[0])
+    print(f"census per particle: sorted {cs[0] / n:.1f} (exact {exact / n:.1f}, tiled slots "
+          f"{cs[2] / n:.1f}), plain {cp[0] / n:.1f} (slots {cp[2] / n:.1f}), in range {cs[1] / n:.1f}")
+
+
+def _census_by_definition(s, g):
+    x = s.pos.astype(np.float64)
+    H = 1.825742 * s.h.astype(np.float64)
+    cid = np.floor(x * g).astype(np.int64) % g
+    flat = (cid[:, 0] * g + cid[:, 1]) * g + cid[:, 2]
+    order = np.argsort(flat, kind="stable")
+    bounds = np.searchsorted(flat[order], np.arange(g ** 3 + 1))
+    total = 0
+    for c in range(g ** 3):
+        ia = order[bounds[c]:bounds[c + 1]]
+        ca = np.array([c // (g * g), c // g % g, c % g])
+        for d in np.array(np.meshgrid([-1, 0, 1], [-1, 0, 1], [-1, 0, 1], indexing="ij")).reshape(3, -1).T:
+            cb = (ca + d) % g
+            b = (cb[0] * g + cb[1]) * g + cb[2]
+            ib = order[bounds[b]:bounds[b + 1]]
+            rel = x[ib][None, :, :] - x[ia][:, None, :]
+            rel -= np.round(rel)                     # minimum image (unit box)
+            if not d.any():
+                cand = np.abs(rel[:, :, 0]) < H[ia][:, None]
+                total += int(cand.sum()) - ia.size    # self excluded
+            else:
+                e = d / np.linalg.norm(d)
+                total += int(((rel @ e) < H[ia][:, None]).sum())
+    return total
 
 
 def test_clustered_small(ctx):
