@@ -316,6 +316,39 @@ pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float 
                      const float *mass, float *h, const double *box, float ngb, float tol,
                      int max_iter, int *iters, float *resid);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * density of one periodic box -- pv_build_cells with an explicit grid,
+ * pv_sort_cells (sorted-pair only) and pv_density -- in one call that
+ * allocates nothing and does not synchronise.  The cell structure and all
+ * scratch memory of the binning, the per-cell sorts and the work-queue sweep
+ * live in one static device array of 32 MiB, which every GPU the library runs
+ * on holds until the process ends; a context looks up its device's copy when
+ * it is created.  Inputs and outputs are the caller's, as for pv_build_cells
+ * and pv_density:
+ *   n          0 <= n <= PV_STATIC_MAX_N
+ *   pos, h, mass  device, input order (pos n x 3)
+ *   box        host, 3 doubles (> 0)
+ *   grid       host, 3 ints, required: 3..PV_MAX_GRID cells per axis and at
+ *              most PV_STATIC_MAX_CELLS cells in all
+ *   algo, rho, wcount, drho_dh, ncount   as for pv_density
+ * Results are those of pv_build_cells (same grid) + pv_sort_cells +
+ * pv_density up to floating-point summation order (the split of the work
+ * queue's last cells is limited to 512 cell parts here).  Errors:
+ * PV_EINVAL (NULL pointer, n or the cell count above the limits, no grid),
+ * PV_EGRID (fewer than 3 or more than PV_MAX_GRID cells per axis), PV_EHIP;
+ * a cut-off above the cell edge or a crowded cell is detected on the device
+ * and reported by pv_check, as for pv_build_cells.  Every call on one GPU uses
+ * that GPU's one array and leaves its contents behind: calls that overlap on
+ * one GPU (other contexts, streams or host threads on the same device) race,
+ * and the caller must serialise them. */
+#define PV_STATIC_MAX_N 131072
+#define PV_STATIC_MAX_CELLS 32768
+pv_status pv_density_static(pv_ctx *ctx, int64_t n, const float *pos, const float *h,
+                            const float *mass, const double box[3], const int grid[3],
+                            pv_algo algo, float *rho, float *wcount, float *drho_dh,
+                            int32_t *ncount);
+
 /* Release a cell structure.  NULL is accepted. */
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells);
 

@@ -11,6 +11,7 @@ calls raise.
 """
 from .pvl import (Cells, Context, PVError, context, density, load_library,  # noqa: F401
                   ALGOS, PV_MAX_CELL, PV_MAX_GRID, EXPORTS, LIB_PATH, PV_OK, PV_EINVAL,
-                  PV_ENOMEM, PV_EHIP, PV_EGRID, PV_EOVERFLOW, PV_ESTATE)
+                  PV_ENOMEM, PV_EHIP, PV_EGRID, PV_EOVERFLOW, PV_ESTATE, PV_STATIC_MAX_N,
+                  PV_STATIC_MAX_CELLS)
 
 __all__ = ["Cells", "Context", "PVError", "context", "density", "load_library"]

@@ -189,6 +189,11 @@ pv_status pv_create(int device, void *hip_stream, pv_ctx **out)
         pv_destroy(ctx);
         return PV_ENOMEM;
     }
+    // the device address of the allocation-free entry point's static scratch
+    if (pvl::static_scratch_init(device) != hipSuccess) {
+        pv_destroy(ctx);
+        return PV_EHIP;
+    }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->tune.num_cu = ctx->tune_adj.num_cu = ctx->tune_plain.num_cu =
@@ -887,6 +892,38 @@ pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float 
     if (resid) *resid = r;
     if (st == PV_OK) ctx->err.clear();
     return st;
+}
+
+pv_status pv_density_static(pv_ctx *ctx, int64_t n, const float *pos, const float *h,
+                            const float *mass, const double box[3], const int grid[3],
+                            pv_algo algo, float *rho, float *wcount, float *drho_dh,
+                            int32_t *ncount)
+{
+    if (!ctx) return PV_EINVAL;
+    if (n < 0 || n > PV_STATIC_MAX_N)
+        return fail(ctx, PV_EINVAL, "n must be 0.." + std::to_string(PV_STATIC_MAX_N) +
+                                        " (the size of the static scratch)");
+    if (n > 0 && (!pos || !h || !mass)) return fail(ctx, PV_EINVAL, "NULL particle array");
+    if (!box) return fail(ctx, PV_EINVAL, "box is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!(box[a] > 0.0) || !isfinite(box[a])) return fail(ctx, PV_EINVAL, "box edge <= 0");
+    if (!grid) return fail(ctx, PV_EINVAL, "an explicit grid is required");
+    for (int a = 0; a < 3; ++a)
+        if (grid[a] < 3 || grid[a] > PV_MAX_GRID)
+            return fail(ctx, PV_EGRID, "grid must have 3.." + std::to_string(PV_MAX_GRID) +
+                                           " cells per axis");
+    if ((int64_t)grid[0] * grid[1] * grid[2] > PV_STATIC_MAX_CELLS)
+        return fail(ctx, PV_EINVAL, "more than " + std::to_string(PV_STATIC_MAX_CELLS) +
+                                        " cells (the size of the static scratch)");
+    if (algo != PV_SORTED_PAIR && algo != PV_PLAIN_CELL) return fail(ctx, PV_EINVAL, "bad algo");
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    unsigned char *base = pvl::static_scratch(ctx->device);
+    if (!base) return fail(ctx, PV_ESTATE, "the static scratch of this device is not set up");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, pvl::launch_density_static(ctx->stream, base, n, pos, h, mass, box, grid,
+                                           (int)algo, rho, wcount, drho_dh, ncount, ctx->dflags,
+                                           algo == PV_PLAIN_CELL ? ctx->tune_plain : ctx->tune));
+    return PV_OK;
 }
 
 pv_status pv_free_cells(pv_ctx *ctx, pv_cells *cells)

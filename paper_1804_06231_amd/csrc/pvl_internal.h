@@ -224,6 +224,18 @@ hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t
                            const float *grad_rho, float *grad_pos, float *grad_h,
                            int *dflags, const SweepTuning &tune);
 
+// Allocation-free density (pv_density_static): the static scratch of
+// kStaticBytes per device, its address looked up once per device (with the
+// device current) and kept, and the launches of one call.
+constexpr int64_t kStaticBytes = 32ll << 20;
+hipError_t static_scratch_init(int device);
+unsigned char *static_scratch(int device);
+hipError_t launch_density_static(hipStream_t st, unsigned char *base, int64_t n,
+                                 const float *pos, const float *h, const float *mass,
+                                 const double box[3], const int grid[3], int algo, float *rho,
+                                 float *wcount, float *drho_dh, int32_t *ncount, int *dflags,
+                                 SweepTuning tune);
+
 hipError_t launch_drift(hipStream_t st, const DevCells &c, int64_t ncell, const float *disp);
 hipError_t launch_h_newton(hipStream_t st, int64_t n, const float *rho, const float *drho_dh,
                            const float *mass, const float *h, float eta3, float *h_next,

@@ -28,8 +28,10 @@ EXPORTS = (
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
     "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h", "pv_drift",
-    "pv_lj", "pv_autotune_grid",
+    "pv_lj", "pv_autotune_grid", "pv_density_static",
 )
+PV_STATIC_MAX_N = 131072
+PV_STATIC_MAX_CELLS = 32768
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4, "tail_parts": 5,
           "tail_cells": 6, "group": 7}
 PV_PARAM_ADJOINT = 16
@@ -85,6 +87,7 @@ def load_library(path: str = LIB_PATH):
         "pv_drift": ([P, P, P], i32),
         "pv_lj": ([P, P, C.c_float, C.c_float, P, P], i32),
         "pv_autotune_grid": ([P, i32, P, P, P, P, P, i32, P, P], i32),
+        "pv_density_static": ([P, i64, P, P, P, P, P, i32, P, P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -255,6 +258,31 @@ class Context:
             rho, wc, dh, nc = out
         self._sync_stream()
         self._call("pv_density", cells.handle, ALGOS[algo], _ptr(rho), _ptr(wc), _ptr(dh), _ptr(nc))
+        return rho, wc, dh, nc
+
+    def density_static(self, pos, h, mass, box, grid, algo: str = "sorted", out=None):
+        """(rho, wcount, drho_dh, ncount) of one box by pv_density_static: build,
+        sort and sweep in one call that allocates no device memory (the cells
+        live in the library's static scratch; n <= PV_STATIC_MAX_N, an explicit
+        grid of at most PV_STATIC_MAX_CELLS cells).  Output tensors are
+        allocated here unless given in `out`."""
+        n = int(pos.shape[0])
+        _dev_f32(pos, n, 3, "pos", self.device)
+        _dev_f32(h, n, 0, "h", self.device)
+        _dev_f32(mass, n, 0, "mass", self.device)
+        if out is None:
+            rho = torch.empty(n, dtype=torch.float32, device=self.device)
+            wc = torch.empty_like(rho)
+            dh = torch.empty_like(rho)
+            nc = torch.empty(n, dtype=torch.int32, device=self.device)
+        else:
+            rho, wc, dh, nc = out
+        bx = [float(box)] * 3 if isinstance(box, (int, float)) else [float(x) for x in box]
+        gl = [int(grid)] * 3 if isinstance(grid, int) else [int(x) for x in grid]
+        self._sync_stream()
+        self._call("pv_density_static", n, _ptr(pos), _ptr(h), _ptr(mass),
+                   (C.c_double * 3)(*bx), (C.c_int * 3)(*gl), ALGOS[algo], _ptr(rho), _ptr(wc),
+                   _ptr(dh), _ptr(nc))
         return rho, wc, dh, nc
 
     def autotune_grid(self, pos, h, mass, box=(1.0, 1.0, 1.0), reps: int = 3, offsets=None,

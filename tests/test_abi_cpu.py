@@ -145,3 +145,29 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
 
+
+def test_static_density_argument_checks_without_gpu(lib, vctx):
+    """pv_density_static checks its limits before touching a device."""
+    from paper_1804_06231_amd.pvl import PV_STATIC_MAX_N, PV_STATIC_MAX_CELLS
+    fake = C.c_void_p(0x1000)
+    box = (C.c_double * 3)(1.0, 1.0, 1.0)
+
+    def call(n, grid, b=box, ptr=fake, algo=0):
+        g = None if grid is None else (C.c_int * 3)(*grid)
+        return lib.pv_density_static(vctx, n, ptr, ptr, ptr, b, g, algo, fake, fake, fake, fake)
+
+    assert call(100, (4, 4, 4)) == -6                                      # valid: no device
+    assert call(-1, (4, 4, 4)) == -1
+    assert call(PV_STATIC_MAX_N + 1, (4, 4, 4)) == -1                      # above the scratch
+    assert b"static scratch" in lib.pv_last_error(vctx)
+    assert call(PV_STATIC_MAX_N, (4, 4, 4)) == -6
+    assert call(100, None) == -1                                            # grid required
+    assert call(100, (2, 4, 4)) == -4
+    assert call(100, (33, 32, 32)) == -1                                    # > 32768 cells
+    assert 32 * 32 * 32 == PV_STATIC_MAX_CELLS and call(100, (32, 32, 32)) == -6
+    assert call(100, (4, 4, 4), b=(C.c_double * 3)(1.0, -1.0, 1.0)) == -1
+    assert call(100, (4, 4, 4), ptr=None) == -1
+    assert call(0, (4, 4, 4), ptr=None) == -6                               # empty input
+    assert call(100, (4, 4, 4), algo=7) == -1
+    assert lib.pv_density_static(None, 10, fake, fake, fake, box, (C.c_int * 3)(4, 4, 4), 0,
+                                 None, None, None, None) == -1
