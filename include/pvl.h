@@ -322,7 +322,7 @@ pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float 
  * pv_sort_cells (sorted-pair only) and pv_density -- in one call that
  * allocates nothing and does not synchronise.  The cell structure and all
  * scratch memory of the binning, the per-cell sorts and the work-queue sweep
- * live in one static device array of 32 MiB, which every GPU the library runs
+ * live in one static device array of 21 MiB, which every GPU the library runs
  * on holds until the process ends; a context looks up its device's copy when
  * it is created.  Inputs and outputs are the caller's, as for pv_build_cells
  * and pv_density:

@@ -29,7 +29,7 @@ constexpr int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 struct StaticLayout {
     int64_t box, box_hmax, bin_blocks, qcount, dx_all;
     int64_t cell_box, cell_start, cell_hmax, cell_dx, cell_m, big, binm, scan_tmp;
-    int64_t cellid, slot, stage, xyzm, H, orig, sidx, skey, tiles, items, partial;
+    int64_t cellid, slot, stage, xyzm, H, orig, sidx, tiles, items, partial;
     int64_t total;
 };
 
@@ -62,7 +62,6 @@ constexpr StaticLayout static_layout()
     o.H = take(4 * kSN);
     o.orig = take(4 * kSN);
     o.sidx = take(2 * 13 * kSN);
-    o.skey = take(4 * 13 * kSN);
     o.tiles = take(4 * kTileArrays * (kSN / 16 + kSC + 1));
     o.items = take(8 * queue_capacity(kSN, kSC));
     o.partial = take(16 * (int64_t)kSTailSlots * kTailRecv);
@@ -149,7 +148,6 @@ hipError_t launch_density_static(hipStream_t st, unsigned char *base, int64_t n,
     d.H = (float *)(base + o.H);
     d.orig = (int32_t *)(base + o.orig);
     d.sidx = (uint16_t *)(base + o.sidx);
-    d.skey = (float *)(base + o.skey);
     d.tiles = (float *)(base + o.tiles);
     d.tslots = tile_slots(kSN, kSC);
     d.items = (int2 *)(base + o.items);

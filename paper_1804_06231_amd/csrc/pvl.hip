@@ -74,7 +74,7 @@ hipError_t dev_alloc(T **p, int64_t count)
 void free_dev(DevCells &d)
 {
     void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cellid, d.slot, d.stage,
-                    d.xyzm, d.H, d.orig, d.sidx, d.skey, d.gcell, d.box_hmax,
+                    d.xyzm, d.H, d.orig, d.sidx, d.gcell, d.box_hmax,
                     d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks, d.cell_dx, d.dx_all,
                     d.partial, d.cell_m, d.tiles, d.big};
     for (void *p : ptrs)
@@ -110,7 +110,6 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.H, N);
     ALLOC(d.orig, N);
     ALLOC(d.sidx, 13 * N);
-    ALLOC(d.skey, 13 * N);
     ALLOC(d.gcell, N);
     ALLOC(d.items, pvl::queue_capacity(N, C));
     ALLOC(d.qcount, pvl::kQueueCounters);

@@ -84,7 +84,6 @@ struct DevCells {
     float *H = nullptr;           // n: cut-off radius
     int32_t *orig = nullptr;      // n: original index
     uint16_t *sidx = nullptr;     // 13 x n: in-cell rank lists, ascending key
-    float *skey = nullptr;        // 13 x n: the keys in that order
     float *gcell = nullptr;       // n: upstream gradient in cell order (adjoint)
     int2 *items = nullptr;        // work queue of (cell, receiver chunk)
     float4 *partial = nullptr;    // per-part sums of the split tail cells
@@ -227,7 +226,7 @@ hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t
 // Allocation-free density (pv_density_static): the static scratch of
 // kStaticBytes per device, its address looked up once per device (with the
 // device current) and kept, and the launches of one call.
-constexpr int64_t kStaticBytes = 32ll << 20;
+constexpr int64_t kStaticBytes = 21ll << 20;
 hipError_t static_scratch_init(int device);
 unsigned char *static_scratch(int device);
 hipError_t launch_density_static(hipStream_t st, unsigned char *base, int64_t n,

@@ -14,7 +14,9 @@
 // (key, in-cell rank) pair.  Equal keys keep in-cell order, so the result is
 // deterministic, and the work is linear in the occupancy unless a bucket is
 // crowded.
-// Output per axis: the in-cell ranks (uint16) in key order and the keys (fp32).
+// Output per axis: the in-cell ranks (uint16) in key order, and the first
+// keys of every 16 positions from either end (the tile summaries the sweep's
+// bounds read); a key itself is recomputed from the position where needed.
 #include "device_util.h"
 
 #include <algorithm>
@@ -63,7 +65,7 @@ __global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(
 k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
                const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
                const float *__restrict__ Hc, int64_t n, uint16_t *__restrict__ sidx,
-               float *__restrict__ skey, int64_t tslots, float *__restrict__ tiles, int min_cnt,
+               int64_t tslots, float *__restrict__ tiles, int min_cnt,
                const int32_t *__restrict__ list)
 {
     __shared__ uint32_t hist[13][NB];
@@ -178,7 +180,6 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
                 const int rank = rk[g];
                 const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
                 sidx[o] = (uint16_t)r;
-                skey[o] = k[g];
                 // tile summaries: the first keys of the tiles from either end
                 const int re = cnt - 1 - rank;
                 if ((rank & 15) == 0) tiles[kTileTS(g) * tslots + slot0 + (rank >> 4)] = k[g];
@@ -209,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
                                                     const float4 *__restrict__ xyzm,
                                                     const float *__restrict__ Hc, int64_t n,
                                                     uint16_t *__restrict__ sidx,
-                                                    float *__restrict__ skey, int64_t tslots,
+                                                    int64_t tslots,
                                                     float *__restrict__ tiles,
                                                     const int32_t *__restrict__ big)
 {
@@ -316,7 +317,6 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
             const int r = forder[q];
             const float kq = key[r];
             sidx[o + q] = (uint16_t)r;
-            skey[o + q] = kq;
             const int re = cnt - 1 - q;
             if ((q & 15) == 0) tiles[kTileTS(s) * tslots + slot0 + (q >> 4)] = kq;
             if ((re & 15) == 0) tiles[kTileTE(s) * tslots + slot0 + (re >> 4)] = kq;
@@ -351,23 +351,23 @@ hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t n
     int32_t *lists = c.big;
     if (!dense)
         hipLaunchKernelGGL((k_sort13_small<64, 32, false>), dim3((unsigned)ncell), dim3(64), 0, st,
-                           c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                           c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
                            c.tslots, c.tiles, 1, (const int32_t *)nullptr);
     hipLaunchKernelGGL((k_sort13_small<256, 256, false>), dim3((unsigned)ncell), dim3(256), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
                        c.tslots, c.tiles, dense ? 1 : 65, (const int32_t *)nullptr);
     // the cells of 257..512 particles, listed by the cell finish
     const unsigned list_wgs = (unsigned)std::min<int64_t>(ncell, kListWgs);
     hipLaunchKernelGGL((k_sort13_small<512, 256, true>), dim3(list_wgs), dim3(512), 0, st, c.box,
-                       c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey, c.tslots,
+                       c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.tslots,
                        c.tiles, 257, (const int32_t *)cell_list(lists, ncell, kListMid));
     // the listed large cells, one workgroup per (cell, axis)
     const unsigned big_wgs = (unsigned)std::min<int64_t>(ncell, kSortLargeWgs);
     hipLaunchKernelGGL(k_sort13_large<kSortLargeMax>, dim3(big_wgs, 13), dim3(kBlock), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
                        c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListBig));
     hipLaunchKernelGGL(k_sort13_large<PV_MAX_CELL>, dim3(big_wgs, 13), dim3(kBlock), 0, st,
-                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.skey,
+                       c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
                        c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListHuge));
     return hipGetLastError();
 }

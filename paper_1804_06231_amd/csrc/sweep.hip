@@ -2,14 +2,14 @@
 //
 //   k_sweep_plain   the plain cell list of the paper's Listing 1: each receiver
 //                   tests every particle of the 27 surrounding cells.
-//   k_sweep_sorted  the pseudo-Verlet loop of Listing 2 with the loop bounds of
-//                   Section 3.3: for each of the 26 neighbour cells only the
+//   k_sweep_sorted  the pairs the pseudo-Verlet loop of Listing 2 tests under
+//                   the loop bounds of Section 3.3, taken one receiver at a
+//                   time: for each of the 26 neighbour cells only the
 //                   particles whose projected separation on the cell-pair axis
-//                   is below the receiver's cut-off are tested; in the sorted
-//                   list of the neighbour they form a prefix (neighbour ahead
-//                   on the axis) or a suffix (behind), found by binary search.
-//                   In the receiver's own cell (x order) the particles within
-//                   H_i in x form one range, also found by binary search.
+//                   is below the receiver's cut-off, in the receiver's own
+//                   cell those within its cut-off in x.  The predicate is
+//                   evaluated on every particle of the 27 cells (no sorted
+//                   lists), so the count is the bounds' by definition.
 //
 // Both kernels run one workgroup per receiver cell and finish in place: the
 // self term is added, the sums are normalised and written in the caller's
@@ -91,20 +91,6 @@ __device__ __forceinline__ PairFrame pair_frame(float xi, float yi, float zi, in
     return f;
 }
 
-// First index in keys[0, n) whose key is >= t (strict = false) or > t (strict = true).
-__device__ __forceinline__ int bsearch_keys(const float *__restrict__ keys, int n, float t,
-                                            bool strict)
-{
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        float k = keys[mid];
-        bool left = strict ? (k <= t) : (k < t);
-        if (left) lo = mid + 1; else hi = mid;
-    }
-    return lo;
-}
-
 __global__ void __launch_bounds__(kBlock) k_sweep_plain(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
@@ -158,7 +144,6 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
     const float *__restrict__ Hc, const int32_t *__restrict__ orig,
-    const uint16_t *__restrict__ sidx, const float *__restrict__ skey,
     const float *__restrict__ cell_dx, int64_t n, float *rho, float *wcount, float *drho_dh,
     int32_t *ncount, const int *__restrict__ dflags, unsigned long long *census, int only_above)
 {
@@ -183,20 +168,17 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
         DensityAcc acc = {0.f, 0.f, 0.f, 0};
         unsigned long long tested = 0;
         if (act) {
-            // own cell: the cell order is x order (the x axis' sorted keys),
-            // so the particles with |x_j - x_i| < H_i form one range, found
-            // by two binary searches (widened by the rounding slack and by
-            // twice the cell's displacement bound after a drift)
-            const float *kx = skey + (size_t)kTileAxisX * n + sa;
+            // own cell: the particles with |x_j - x_i| < H_i (widened by the
+            // rounding slack and by twice the cell's displacement bound after
+            // a drift)
             const float wx = Hi + slack + 2.0f * cell_dx[a];
-            const int j0 = bsearch_keys(kx, na, pi.x - wx, true);
-            const int j1 = bsearch_keys(kx, na, pi.x + wx, false);
-            for (int j = j0; j < j1; ++j) {
+            for (int j = 0; j < na; ++j) {
                 if (j == i) continue;
                 float4 q = xyzm[sa + j];
+                if (!(fabsf(q.x - pi.x) < wx)) continue;
+                ++tested;
                 density_pair(q.x - pi.x, q.y - pi.y, q.z - pi.z, q.w, H2, invH, acc);
             }
-            tested += (unsigned long long)(j1 - j0 - (i >= j0 && i < j1 ? 1 : 0));
             for (int o = 0; o < 27; ++o) {
                 if (o == 13) continue;
                 int dx = o / 9 - 1, dy = (o / 3) % 3 - 1, dz = o % 3 - 1;
@@ -210,27 +192,20 @@ __global__ void __launch_bounds__(kBlock) k_sweep_sorted(
                 dir_axis(s, e);
                 float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
                 float ki = proj_key(pi.x, pi.y, pi.z, s);
-                // sorted keys may predate a drift: widen by both cells' bounds
+                // both cells' displacement bounds after a drift
                 const float mg = cell_dx[a] + cell_dx[b];
-                const float *kb = skey + (size_t)s * n + sb;
-                const uint16_t *ib = sidx + (size_t)s * n + sb;
+                const float reach = Hi + slack + mg;
                 PairFrame f = pair_frame(pi.x, pi.y, pi.z, dx, dy, dz, sx, sy, sz);
-                int j0, j1;
-                if (sign > 0) {
-                    // neighbour ahead: key_j + se - key_i < H_i  ->  prefix
-                    j0 = 0;
-                    j1 = bsearch_keys(kb, nb, (ki - se) + Hi + slack + mg, false);
-                } else {
-                    // neighbour behind: key_i - (key_j + se) < H_i  ->  suffix
-                    j0 = bsearch_keys(kb, nb, (ki - se) - Hi - slack - mg, true);
-                    j1 = nb;
-                }
-                for (int j = j0; j < j1; ++j) {
-                    float4 q = xyzm[sb + ib[j]];
+                for (int j = 0; j < nb; ++j) {
+                    float4 q = xyzm[sb + j];
+                    const float kj = proj_key(q.x, q.y, q.z, s) + se;
+                    // neighbour ahead on the axis: key_j - key_i < H_i; behind:
+                    // key_i - key_j < H_i
+                    if (!((sign > 0 ? kj - ki : ki - kj) < reach)) continue;
+                    ++tested;
                     density_pair((q.x + f.ux) - f.tx, (q.y + f.uy) - f.ty, (q.z + f.uz) - f.tz, q.w,
                                  H2, invH, acc);
                 }
-                tested += (unsigned long long)(j1 - j0);
             }
             write_density(acc, Hi, pi.w, orig[sa + i], rho, wcount, drho_dh, ncount);
         }
@@ -257,7 +232,7 @@ hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t nc
                                drho_dh, ncount, dflags, census, 0);
         else
             hipLaunchKernelGGL(k_sweep_sorted, dim3((unsigned)ncell), dim3(kBlock), 0, st, c.box,
-                               c.cell_box, c.cell_start, c.xyzm, c.H, c.orig, c.sidx, c.skey,
+                               c.cell_box, c.cell_start, c.xyzm, c.H, c.orig,
                                c.cell_dx, n, rho, wcount, drho_dh, ncount, dflags, census, 0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -96,6 +96,10 @@ __device__ __forceinline__ float ror16(float v)
         return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x120 + K, 0xf, 0xf, true));
 }
 
+// x clamped to [0, 1] (one instruction: the clamp bit of the producing
+// operation)
+__device__ __forceinline__ float clamp01(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+
 struct TileAcc {
     float rho, wc, dh, cnt;
 };
@@ -111,11 +115,12 @@ __device__ __forceinline__ void tile_interact(float r2, float mj, float invH2, T
     float u = __builtin_amdgcn_sqrtf(u2);   // v_sqrt_f32, 1 ulp
     // inner piece (u < 1/2): w = 1 - 6u^2 + 6u^3, u w' = 18u^3 - 12u^2.
     // The outer piece differs from it by t^3 in w and by -6 u t^2 in u w'
-    // with t = 1 - 2u, so with t = min(0, 1 - 2u) one expression covers both:
+    // with t = 1 - 2u, so with t = min(0, 1 - 2u) (formed as -clamp(2u - 1)
+    // to [0, 1], the same for 0 <= u <= 1) one expression covers both:
     // w = 2 (1-u)^3 and u w' = -6 u (1-u)^2 for u >= 1/2.  The sum of
     // m_j (3w + u w') behind drho_dh is 3 (the density sum) + the sum of
     // m_j u w', so only the latter is accumulated.
-    float t = fminf(fmaf(-2.0f, u, 1.0f), 0.0f);
+    float t = -clamp01(fmaf(2.0f, u, -1.0f));
     float t2 = t * t;
     float w = fmaf(t2, t, fmaf(u2, fmaf(6.0f, u, -6.0f), 1.0f));
     float uw = fmaf(-6.0f * u, t2, u2 * fmaf(18.0f, u, -12.0f));
@@ -141,7 +146,7 @@ __device__ __forceinline__ void tile_interact_unit(float r2, float invH2, UnitAc
     float u2 = r2 * invH2;
     float u = __builtin_amdgcn_sqrtf(u2);   // v_sqrt_f32, 1 ulp
     float v = 1.0f - u;
-    float s = fmaxf(fmaf(-2.0f, u, 1.0f), 0.0f);
+    float s = clamp01(fmaf(-2.0f, u, 1.0f));
     float v2 = v * v;
     float s2 = s * s;
     a.v3 = fmaf(v2, v, a.v3);
@@ -167,9 +172,11 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
     float uk = r * invHk;
     float uj = r * invHj;
     // w' = -12u + 18u^2 (u < 1/2), -6 (1-u)^2 (u >= 1/2): the outer piece is
-    // the inner one minus 6 t^2 with t = min(0, 1 - 2u); w as in the forward
-    float tk = fminf(fmaf(-2.0f, uk, 1.0f), 0.0f);
-    float tj = fminf(fmaf(-2.0f, uj, 1.0f), 0.0f);
+    // the inner one minus 6 t^2 with t = min(0, 1 - 2u) (for u <= 1; a
+    // receiver or source beyond its cut-off gets t = -1 and a zero mass
+    // factor); w as in the forward
+    float tk = -clamp01(fmaf(2.0f, uk, -1.0f));
+    float tj = -clamp01(fmaf(2.0f, uj, -1.0f));
     float tk2 = tk * tk, tj2 = tj * tj;
     float dwk = fmaf(-6.0f, tk2, uk * fmaf(18.0f, uk, -12.0f));
     float wk = fmaf(tk2, tk, fmaf(uk * uk, fmaf(6.0f, uk, -6.0f), 1.0f));
@@ -300,7 +307,6 @@ struct SweepArgs {
     const uint32_t *cell_hmax;
     const int32_t *orig;
     const uint16_t *sidx;
-    const float *skey;
     int64_t n;
     float *rho, *wcount, *drho_dh;
     int32_t *ncount;
@@ -339,9 +345,8 @@ struct SweepLds {
     int act_cell[26 * G];
     int task_off[27 * G + 1];
     int recv_off[26 * G];
-    // first slot and particles of each (cell, direction)'s neighbour (not
-    // kept by the plain sweep, whose LDS stays within five workgroups)
-    int nb_start[G > 1 ? 26 * G : 1], nb_cnt[G > 1 ? 26 * G : 1];
+    // first slot and particles of each (cell, direction)'s neighbour
+    int nb_start[26 * G], nb_cnt[26 * G];
     // per cell of the item: first particle, count, largest cut-off,
     // displacement bound
     int gsa[G], gna[G];
@@ -446,7 +451,6 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     asm volatile("" : "+v"(tid));
     const int wave = tid >> 6, lane = tid & 63;
     const uint16_t *sidx = A.sidx;
-    const float *skey = A.skey;
     const int64_t ts = A.tslots;
     const float *tiles = A.tiles;
     // cell g of the item: g steps along z in the first cell's row
@@ -491,10 +495,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         float sx, sy, sz;
         int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
         int sb = A.start[b], nb = A.start[b + 1] - sb;
-        if constexpr (!PLAIN) {
-            L.nb_start[tid] = sb;
-            L.nb_cnt[tid] = nb;
-        }
+        L.nb_start[tid] = sb;
+        L.nb_cnt[tid] = nb;
         if (!ADJ && !LJ) mb = A.cell_m[b];
         int act = 0;
         if (PLAIN) {
@@ -578,7 +580,6 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 int dx, dy, dz, sign;
                 nb_offset(d, dx, dy, dz);
                 const int s = dir_canon(dx, dy, dz, &sign);
-                const float *ka = skey + (size_t)s * n + sa;
                 const uint16_t *il = sidx + (size_t)s * n + sa;
                 uint16_t *out = L.rlist + L.recv_off[gd];
                 const bool face = (dx != 0) + (dy != 0) + (dz != 0) == 1;
@@ -587,8 +588,13 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                     continue;
                 }
                 if (act == 0) continue;
-                const float lo = sign > 0 ? ka[0] : -ka[na - 1];
-                const float hi = (sign > 0 ? ka[na - 1] : -ka[0]) + hmax_a;
+                // the cell's smallest and largest keys on the axis (its tiles'
+                // first keys from either end)
+                const int64_t slot_a = tile_slot(sa, a + g, 0);
+                const float kmin = tiles[kTileTS(s) * ts + slot_a];
+                const float kmax = tiles[kTileTE(s) * ts + slot_a];
+                const float lo = sign > 0 ? kmin : -kmax;
+                const float hi = (sign > 0 ? kmax : -kmin) + hmax_a;
                 const float scale = (float)kReachBuckets / fmaxf(hi - lo, 1e-30f);
                 constexpr int R = kChunk / 64;
                 int bk[R], pos[R];
@@ -603,7 +609,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                     if (c < nc && q < act) {
                         const int qs = sign > 0 ? na - 1 - q : q;
                         const int ia = il[qs];
-                        const float k = ka[qs];
+                        const float4 pq = A.xyzm[sa + ia];
+                        const float k = proj_key(pq.x, pq.y, pq.z, s);
                         const float H = A.Hc[sa + ia];
                         const float T = sign > 0 ? k + H : H - k;
                         const int b = (int)((hi - T) * scale);
@@ -736,44 +743,34 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             float e[3];
             dir_axis(s, e);
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
-            const float *ka = skey + (size_t)s * n + sa;
             const uint16_t *il = sidx + (size_t)s * n + sa;
             const int r0 = blk * 16, r1 = min(r0 + 16, L.n_act[gd]);
             const float hmax_b = __uint_as_float(A.cell_hmax[b]);
             const float mg = dx_a + A.cell_dx[b];
-            // block reach: the largest key + H (ahead) or smallest key - H (behind);
-            // the block's receivers are loaded eight at a time (clamped indices,
-            // so every load of a group is issued before the first is needed)
+            // block reach: the largest key + H (ahead) or smallest key - H
+            // (behind), keys projected from the receivers' positions.  The
+            // block's 16 ranks are loaded at once (clamped indices), then
+            // their positions and cut-offs: two round trips to memory.
+            int iv[16];
+            if (listed) {
+                const uint16_t *rl = L.rlist + L.recv_off[26 * g + dir];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) iv[u] = rl[min(r0 + u, r1 - 1)];
+            } else {
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int r = min(r0 + u, r1 - 1);
+                    iv[u] = il[sign > 0 ? na - 1 - r : r];
+                }
+            }
             float T = sign > 0 ? -INFINITY : INFINITY;
-#pragma unroll 1
-            for (int g0 = r0; g0 < r1; g0 += 8) {
-                float kv[8], hv[8];
-                if (listed) {
-                    const uint16_t *rl = L.rlist + L.recv_off[26 * g + dir];
 #pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int ia = rl[min(g0 + u, r1 - 1)];
-                        const float4 p = A.xyzm[sa + ia];
-                        kv[u] = proj_key(p.x, p.y, p.z, s);
-                        hv[u] = A.Hc[sa + ia];
-                    }
-                } else {
-                    int iv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int r = min(g0 + u, r1 - 1);
-                        const int q = sign > 0 ? na - 1 - r : r;
-                        kv[u] = ka[q];
-                        iv[u] = il[q];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) hv[u] = A.Hc[sa + iv[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const float H = ADJ ? fmaxf(hv[u], hmax_b) : hv[u];
-                    T = sign > 0 ? fmaxf(T, kv[u] + H) : fminf(T, kv[u] - H);
-                }
+            for (int u = 0; u < 16; ++u) {
+                const float4 p = A.xyzm[sa + iv[u]];
+                const float hv = A.Hc[sa + iv[u]];
+                const float kv = proj_key(p.x, p.y, p.z, s);
+                const float H = ADJ ? fmaxf(hv, hmax_b) : hv;
+                T = sign > 0 ? fmaxf(T, kv + H) : fminf(T, kv - H);
             }
             // source tiles with a key below the reach (ahead), or above it
             // (behind, counted from the end): from the tiles' first keys
@@ -834,169 +831,260 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         (&L.acc[0][0])[t] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
 
-    // tasks in groups of 4 (one per row); the part's groups (every nparts-th)
-    // are dealt to the waves in turn
+    // Row phase.  Tasks run in groups of 4, one per 16-lane row; the part's
+    // groups (every nparts-th) are dealt to the waves in turn, and a wave
+    // runs each group for its longest row's tile count.  The loads are
+    // software-pipelined over the wave's whole sequence of groups: while a
+    // tile is computed, the next tile's source data (with, at the start of
+    // a group, the row's receiver) and the source index of the tile after
+    // it are in flight, so a new group starts without waiting for memory.
     const int row = lane >> 4;
     const int l16 = lane & 15;
-    for (int gp = wave; (part + nparts * gp) * 4 < ntask; gp += 4) {
-        const int tg = part + nparts * gp;
-        const int t = tg * 4 + row;
-        const bool row_valid = t < ntask;
-        const uint32_t tw = row_valid ? L.tasks[L.torder[t]] : 0u;
-        const int nt = row_valid ? task_tiles(tw) : 0;
-        const int blk = (int)((tw >> 10) & 31u);
-        const int gd = (int)((tw >> 15) & 255u);
-        const int t0 = (int)(tw >> 23);
-        const int g = gd / 27, dir = gd - 27 * g;
-        const int sa = L.gsa[g], na = L.gna[g];
-        // receiver of this lane and the source list of its row
-        int dx = 0, dy = 0, dz = 0, sb = sa, nb = na, sign = 1, s = kSelfAxis;
-        float shx = 0.f, shy = 0.f, shz = 0.f;
+    auto group_of = [&](int q) { return part + nparts * (wave + 4 * q); };
+    // source index of this lane in tile `it` of a task (-1: none)
+    auto src_index = [&](int nt, int t0, int sb, int nb, int s, int sign, bool direct,
+                         int it) -> int {
+        const int j = (t0 + it) * 16 + l16;
+        if (it >= nt || j >= nb) return -1;
+        return direct ? j : (int)sidx[(size_t)s * n + sb + (sign > 0 ? j : nb - 1 - j)];
+    };
+    // task word of this row in the wave's group q (0: none)
+    auto task_word = [&](int q, bool &ok) -> uint32_t {
+        const int t = group_of(q) * 4 + row;
+        ok = t < ntask;
+        return ok ? L.tasks[L.torder[t]] : 0u;
+    };
+    // neighbour geometry of (cell g, direction dir): first slot, count, shift
+    // into the frame of cell g, axis and sign
+    auto task_geom = [&](int g, int dir, int &sb, int &nb, int &s, int &sign, int &dx, int &dy,
+                         int &dz, float &shx, float &shy, float &shz) {
+        dx = dy = dz = 0;
+        shx = shy = shz = 0.0f;
+        sb = L.gsa[g];
+        nb = L.gna[g];
+        sign = 1;
+        s = kSelfAxis;
         if (dir < 26) {
             nb_offset(dir, dx, dy, dz);
-            int b = neighbour(B, geom_of(g), dx, dy, dz, shx, shy, shz);
-            if constexpr (PLAIN) {
-                sb = A.start[b];
-                nb = A.start[b + 1] - sb;
-            } else {
-                sb = L.nb_start[26 * g + dir];
-                nb = L.nb_cnt[26 * g + dir];
-            }
+            (void)neighbour(B, geom_of(g), dx, dy, dz, shx, shy, shz);
+            sb = L.nb_start[26 * g + dir];
+            nb = L.nb_cnt[26 * g + dir];
             s = dir_canon(dx, dy, dz, &sign);
         }
-        const int r = blk * 16 + l16;
-        const bool recv_ok = row_valid && r < L.n_act[gd];
-        int ia = 0;
-        if (recv_ok) {
-            if (PLAIN || dir == 26) ia = r_lo + r;
-            else if (listed) ia = L.rlist[L.recv_off[26 * g + dir] + r];
-            else if (sign > 0) ia = sidx[(size_t)s * n + sa + (na - 1 - r)];
-            else ia = sidx[(size_t)s * n + sa + r];
-        }
-        const int pr = sa + ia;      // the receiver's position in the cell order
-        const int ai = pr - base;    // and in the item's sums
-        const float4 pi = recv_ok ? A.xyzm[pr] : make_float4(0.f, 0.f, 0.f, 0.f);
-        const float Hi = recv_ok ? A.Hc[pr] : 0.0f;
-        const float H2 = Hi * Hi;
-        const float invH = recv_ok ? 1.0f / Hi : 0.0f;
-        const float invH2 = invH * invH;
-        // pair frame: receiver moved for +1 offsets, source for -1 offsets
-        const float tx = dx > 0 ? pi.x - shx : pi.x;
-        const float ty = dy > 0 ? pi.y - shy : pi.y;
-        const float tz = dz > 0 ? pi.z - shz : pi.z;
-        const float ux = dx < 0 ? shx : 0.0f;
-        const float uy = dy < 0 ? shy : 0.0f;
-        const float uz = dz < 0 ? shz : 0.0f;
-        const uint16_t *lb = sidx + (size_t)s * n + sb;
-        // the own cell's diagonal tile pairs each receiver with itself at K = 0
-        const int diag = dir == 26 ? (r_lo >> 4) + blk : -1;
+    };
 
-        if (A.slots && row_valid && l16 == 0) atomicAdd(A.slots, 256ull * (unsigned)nt);
-        int ntmax = nt;
-        ntmax = max(ntmax, __shfl_xor(ntmax, 16));
-        ntmax = max(ntmax, __shfl_xor(ntmax, 32));
-        // source of this lane in tile `it` of the row (-1: none).  The loads are
-        // software-pipelined: while a tile is computed, the next tile's
-        // source data and the index of the one after are in flight.
-        auto src_of = [&](int it) -> int {
-            const int j = (t0 + it) * 16 + l16;
-            if (it >= nt || j >= nb) return -1;
-            return (PLAIN || dir == 26) ? j : (int)lb[sign > 0 ? j : nb - 1 - j];
-        };
-        float4 res;
-        if constexpr (ADJ) {
-            // receiver constants; a lane without a receiver sits far away so
-            // that no source is within its own or the source's cut-off
-            const float far = recv_ok ? 0.0f : 1e30f;
-            const float tfx = tx + far, tfy = ty + far, tfz = tz + far;
-            const float Gi = recv_ok ? A.gcell[pr] : 0.0f;
-            const float ck = Gi * ((8.0f / kPi) * (invH * invH) * (invH * invH));
-            const float mi = pi.w;
-            GradAcc acc = {0.f, 0.f, 0.f, 0.f};
-            float4 qn;
-            float hn, gn;
-            auto load_src = [&](int p) {
-                qn = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-                hn = gn = 0.0f;
-                if (p >= 0) {
-                    qn = A.xyzm[sb + p];
-                    hn = A.Hc[sb + p];
-                    gn = A.gcell[sb + p];
-                }
-            };
-            int pn = src_of(0);
-            load_src(pn);
-            pn = src_of(1);
-            for (int it = 0; it < ntmax; ++it) {
-                const int tile = t0 + it;
-                const float4 q = qn;
-                const float hj = hn, gj = gn;
-                load_src(pn);
-                pn = src_of(it + 2);
-                const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
+    // the cursor: the (group, tile) position two tiles ahead of the
+    // computation, with what its source indices need
+    int cq = 0, ci = 0, cmax = 0;
+    bool cvalid = false;
+    int c_nt = 0, c_t0 = 0, c_sb = 0, c_nb = 0, c_s = 0, c_sign = 1;
+    bool c_direct = true;
+    // index stage (two tiles ahead, at the cursor): source index; at a group
+    // start the receiver's rank, loaded by cursor_enter
+    bool e2_valid = false, e2_start = false, e2_rok = false;
+    int e2_src = -1, e2_sb = 0, e2_ria = 0, e2_sa = 0, e2_q = 0;
+    // first group at or after q with a source tile on any row (groups
+    // without one add nothing); issues the load of the row's receiver rank
+    // straight into the index stage
+    auto cursor_enter = [&](int q) {
+        cvalid = false;
+        while (group_of(q) * 4 < ntask) {
+            bool ok;
+            const uint32_t tw = task_word(q, ok);
+            const int nt = ok ? task_tiles(tw) : 0;
+            int m = max(nt, __shfl_xor(nt, 16));
+            m = max(m, __shfl_xor(m, 32));
+            if (m == 0) {
+                ++q;
+                continue;
+            }
+            if (A.slots && ok && l16 == 0) atomicAdd(A.slots, 256ull * (unsigned)nt);
+            const int blk = (int)((tw >> 10) & 31u);
+            const int gd = (int)((tw >> 15) & 255u);
+            const int g = gd / 27, dir = gd - 27 * g;
+            int dx, dy, dz;
+            float shx, shy, shz;
+            task_geom(g, dir, c_sb, c_nb, c_s, c_sign, dx, dy, dz, shx, shy, shz);
+            c_nt = nt;
+            c_t0 = (int)(tw >> 23);
+            c_direct = PLAIN || dir == 26;
+            e2_sa = L.gsa[g];
+            const int r = blk * 16 + l16;
+            e2_rok = ok && r < L.n_act[gd];
+            e2_ria = 0;
+            if (e2_rok) {
+                if (c_direct) e2_ria = r_lo + r;
+                else if (listed) e2_ria = L.rlist[L.recv_off[26 * g + dir] + r];
+                else e2_ria = sidx[(size_t)c_s * n + e2_sa + (c_sign > 0 ? L.gna[g] - 1 - r : r)];
+            }
+            cq = q;
+            ci = 0;
+            cmax = m;
+            cvalid = true;
+            return;
+        }
+    };
+    auto cursor_next = [&]() {
+        if (++ci >= cmax) cursor_enter(cq + 1);
+    };
+
+    auto stage_index = [&]() {
+        e2_valid = cvalid;
+        e2_start = cvalid && ci == 0;
+        e2_q = cq;
+        e2_src = cvalid ? src_index(c_nt, c_t0, c_sb, c_nb, c_s, c_sign, c_direct, ci) : -1;
+        e2_sb = c_sb;
+    };
+    // data stage (one tile ahead): source data; at a group start the receiver
+    bool e1_valid = false, e1_start = false, e1_rok = false;
+    int e1_pr = 0, e1_q = 0;
+    float4 e1_s = make_float4(1e30f, 1e30f, 1e30f, 0.f), e1_r = e1_s;
+    float e1_sh = 0.0f, e1_sg = 0.0f, e1_rh = 0.0f, e1_rg = 0.0f;
+    auto stage_data = [&]() {
+        e1_valid = e2_valid;
+        e1_start = e2_start;
+        e1_q = e2_q;
+        e1_s = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+        e1_sh = e1_sg = 0.0f;
+        if (e2_src >= 0) {
+            const int p = e2_sb + e2_src;
+            e1_s = A.xyzm[p];
+            if constexpr (ADJ) {
+                e1_sh = A.Hc[p];
+                e1_sg = A.gcell[p];
+            }
+        }
+        if (e2_start) {
+            e1_rok = e2_rok;
+            e1_pr = e2_sa + e2_ria;
+            if (e1_rok) {
+                e1_r = A.xyzm[e1_pr];
+                e1_rh = A.Hc[e1_pr];
+                if constexpr (ADJ) e1_rg = A.gcell[e1_pr];
+            }
+        }
+    };
+
+    cursor_enter(0);
+    stage_index();
+    stage_data();
+    cursor_next();
+    stage_index();
+
+    // the computation's group: task, receiver, pair frame and sums
+    int nt = 0, t0 = 0, it = 0, ntmax = 0, diag = -1, ai = 0;
+    bool recv_ok = false;
+    float tx = 0.f, ty = 0.f, tz = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, H2 = 0.f, invH = 0.f,
+          invH2 = 0.f, ck = 0.f, mi = 0.f;
+    TileAcc acc = {0.f, 0.f, 0.f, 0.f};
+    UnitAcc uacc = {0.f, 0.f, 0.f, 0.f, 0.f};
+    GradAcc gacc = {0.f, 0.f, 0.f, 0.f};
+    const float sig2 = A.lj_sigma2, eps = A.lj_eps;
+    const bool unit = !LJ && !ADJ && mass == mass;
+    while (e1_valid) {   // wave-uniform
+        const float4 q = e1_s;
+        const float qh = e1_sh, qg = e1_sg;
+        if (e1_start) {
+            // a new group: this row's task, receiver and pair frame
+            bool ok;
+            const uint32_t tw = task_word(e1_q, ok);
+            nt = ok ? task_tiles(tw) : 0;
+            ntmax = max(nt, __shfl_xor(nt, 16));
+            ntmax = max(ntmax, __shfl_xor(ntmax, 32));
+            t0 = (int)(tw >> 23);
+            const int blk = (int)((tw >> 10) & 31u);
+            const int gd = (int)((tw >> 15) & 255u);
+            const int g = gd / 27, dir = gd - 27 * g;
+            int sb, nb, s, sign, dx, dy, dz;
+            float shx, shy, shz;
+            task_geom(g, dir, sb, nb, s, sign, dx, dy, dz, shx, shy, shz);
+            recv_ok = e1_rok;
+            ai = e1_pr - base;
+            const float4 pi = recv_ok ? e1_r : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float Hi = recv_ok ? e1_rh : 0.0f;
+            H2 = Hi * Hi;
+            invH = recv_ok ? 1.0f / Hi : 0.0f;
+            invH2 = invH * invH;
+            // pair frame: receiver moved for +1 offsets, source for -1 offsets
+            tx = dx > 0 ? pi.x - shx : pi.x;
+            ty = dy > 0 ? pi.y - shy : pi.y;
+            tz = dz > 0 ? pi.z - shz : pi.z;
+            ux = dx < 0 ? shx : 0.0f;
+            uy = dy < 0 ? shy : 0.0f;
+            uz = dz < 0 ? shz : 0.0f;
+            // the own cell's diagonal tile pairs each receiver with itself at K = 0
+            diag = dir == 26 ? (r_lo >> 4) + blk : -1;
+            it = 0;
+            if constexpr (ADJ) {
+                // a lane without a receiver sits far away, so that no source
+                // is within its own or the source's cut-off
+                const float far = recv_ok ? 0.0f : 1e30f;
+                tx += far;
+                ty += far;
+                tz += far;
+                ck = (recv_ok ? e1_rg : 0.0f) * ((8.0f / kPi) * (invH * invH) * (invH * invH));
+                mi = pi.w;
+            }
+        }
+        stage_data();
+        cursor_next();
+        stage_index();
+
+        const int tile = t0 + it;
+        const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
+        if (it < nt) {
+            if constexpr (ADJ) {
+                const float hj = qh, gj = qg;
                 const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
                 const float sh2 = hj * hj;
                 const float sc = gj * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
-                if (it < nt) {
-                    const float tx = tfx, ty = tfy, tz = tfz;
-                    if (tile != diag) PVL_GRAD_STEP(0)
-                    PVL_GRAD_STEP(1) PVL_GRAD_STEP(2) PVL_GRAD_STEP(3) PVL_GRAD_STEP(4)
-                    PVL_GRAD_STEP(5) PVL_GRAD_STEP(6) PVL_GRAD_STEP(7) PVL_GRAD_STEP(8)
-                    PVL_GRAD_STEP(9) PVL_GRAD_STEP(10) PVL_GRAD_STEP(11) PVL_GRAD_STEP(12)
-                    PVL_GRAD_STEP(13) PVL_GRAD_STEP(14) PVL_GRAD_STEP(15)
-                }
+                GradAcc &acc = gacc;
+                if (tile != diag) PVL_GRAD_STEP(0)
+                PVL_GRAD_STEP(1) PVL_GRAD_STEP(2) PVL_GRAD_STEP(3) PVL_GRAD_STEP(4)
+                PVL_GRAD_STEP(5) PVL_GRAD_STEP(6) PVL_GRAD_STEP(7) PVL_GRAD_STEP(8)
+                PVL_GRAD_STEP(9) PVL_GRAD_STEP(10) PVL_GRAD_STEP(11) PVL_GRAD_STEP(12)
+                PVL_GRAD_STEP(13) PVL_GRAD_STEP(14) PVL_GRAD_STEP(15)
+            } else if constexpr (LJ) {
+                if (tile != diag) PVL_LJ_STEP(0)
+                PVL_LJ_STEP(1) PVL_LJ_STEP(2) PVL_LJ_STEP(3) PVL_LJ_STEP(4)
+                PVL_LJ_STEP(5) PVL_LJ_STEP(6) PVL_LJ_STEP(7) PVL_LJ_STEP(8)
+                PVL_LJ_STEP(9) PVL_LJ_STEP(10) PVL_LJ_STEP(11) PVL_LJ_STEP(12)
+                PVL_LJ_STEP(13) PVL_LJ_STEP(14) PVL_LJ_STEP(15)
+            } else if (unit) {
+                if (tile != diag) PVL_TILE_STEP_U(0)
+                PVL_TILE_STEP_U(1) PVL_TILE_STEP_U(2) PVL_TILE_STEP_U(3) PVL_TILE_STEP_U(4)
+                PVL_TILE_STEP_U(5) PVL_TILE_STEP_U(6) PVL_TILE_STEP_U(7) PVL_TILE_STEP_U(8)
+                PVL_TILE_STEP_U(9) PVL_TILE_STEP_U(10) PVL_TILE_STEP_U(11) PVL_TILE_STEP_U(12)
+                PVL_TILE_STEP_U(13) PVL_TILE_STEP_U(14) PVL_TILE_STEP_U(15)
+            } else {
+                if (tile != diag) PVL_TILE_STEP(0)
+                PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
+                PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
+                PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
+                PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
             }
-            res = make_float4(acc.gx, acc.gy, acc.gz, acc.dh);
-        } else {
-            TileAcc acc = {0.f, 0.f, 0.f, 0.f};
-            UnitAcc uacc = {0.f, 0.f, 0.f, 0.f, 0.f};
-            const float sig2 = A.lj_sigma2, eps = A.lj_eps;
-            const bool unit = !LJ && mass == mass;
-            auto load_src = [&](int p) {
-                return p >= 0 ? A.xyzm[sb + p] : make_float4(1e30f, 1e30f, 1e30f, 0.f);
-            };
-            int pn = src_of(0);
-            float4 qn = load_src(pn);
-            pn = src_of(1);
-            for (int it = 0; it < ntmax; ++it) {
-                const int tile = t0 + it;
-                const float4 q = qn;
-                qn = load_src(pn);
-                pn = src_of(it + 2);
-                const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
-                if (it < nt) {
-                    if constexpr (LJ) {
-                        if (tile != diag) PVL_LJ_STEP(0)
-                        PVL_LJ_STEP(1) PVL_LJ_STEP(2) PVL_LJ_STEP(3) PVL_LJ_STEP(4)
-                        PVL_LJ_STEP(5) PVL_LJ_STEP(6) PVL_LJ_STEP(7) PVL_LJ_STEP(8)
-                        PVL_LJ_STEP(9) PVL_LJ_STEP(10) PVL_LJ_STEP(11) PVL_LJ_STEP(12)
-                        PVL_LJ_STEP(13) PVL_LJ_STEP(14) PVL_LJ_STEP(15)
-                    } else if (unit) {
-                        if (tile != diag) PVL_TILE_STEP_U(0)
-                        PVL_TILE_STEP_U(1) PVL_TILE_STEP_U(2) PVL_TILE_STEP_U(3) PVL_TILE_STEP_U(4)
-                        PVL_TILE_STEP_U(5) PVL_TILE_STEP_U(6) PVL_TILE_STEP_U(7) PVL_TILE_STEP_U(8)
-                        PVL_TILE_STEP_U(9) PVL_TILE_STEP_U(10) PVL_TILE_STEP_U(11) PVL_TILE_STEP_U(12)
-                        PVL_TILE_STEP_U(13) PVL_TILE_STEP_U(14) PVL_TILE_STEP_U(15)
-                    } else {
-                        if (tile != diag) PVL_TILE_STEP(0)
-                        PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
-                        PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
-                        PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
-                        PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
-                    }
-                }
-            }
-            res = make_float4(acc.rho, acc.wc, acc.dh, acc.cnt);
-            if (!LJ && unit)
+        }
+        if (++it == ntmax) {
+            // the group's last tile: the row's sums go to its wave's array
+            float4 res;
+            if constexpr (ADJ) {
+                res = make_float4(gacc.gx, gacc.gy, gacc.gz, gacc.dh);
+                gacc = GradAcc{0.f, 0.f, 0.f, 0.f};
+            } else if (!LJ && unit) {
                 res = make_float4(0.0f, fmaf(2.0f, uacc.v3, -uacc.s3),
                                   6.0f * (uacc.us2 - uacc.uv2), uacc.cnt);
-        }
-        if (recv_ok) {
-            float *dst = reinterpret_cast<float *>(&L.acc[wave][ai]);
-            atomicAdd(dst + 0, res.x);
-            atomicAdd(dst + 1, res.y);
-            atomicAdd(dst + 2, res.z);
-            atomicAdd(dst + 3, res.w);
+                uacc = UnitAcc{0.f, 0.f, 0.f, 0.f, 0.f};
+            } else {
+                res = make_float4(acc.rho, acc.wc, acc.dh, acc.cnt);
+                acc = TileAcc{0.f, 0.f, 0.f, 0.f};
+            }
+            if (recv_ok) {
+                float *dst = reinterpret_cast<float *>(&L.acc[wave][ai]);
+                atomicAdd(dst + 0, res.x);
+                atomicAdd(dst + 1, res.y);
+                atomicAdd(dst + 2, res.z);
+                atomicAdd(dst + 3, res.w);
+            }
         }
     }
     __syncthreads();
@@ -1219,7 +1307,6 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.cell_hmax = c.cell_hmax;
     A.orig = c.orig;
     A.sidx = c.sidx;
-    A.skey = c.skey;
     A.n = n;
     A.cell_m = c.cell_m;
     A.tiles = c.tiles;

@@ -8,6 +8,9 @@
 --trace    a `rocprofv3 --kernel-trace --stats --output-format csv` directory
 --fetch    a `rocprofv3 --pmc FETCH_SIZE --output-format csv` directory
 --write    a `rocprofv3 --pmc WRITE_SIZE --output-format csv` directory
+--sq       a `rocprofv3 --pmc SQ_INSTS_VALU SQ_ACTIVE_INST_VALU
+           SQ_THREAD_CYCLES_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_WAVES
+           --output-format csv` directory (vector-ALU use per kernel)
 
 The byte counters are calibrated against the device copy of --copy-mib MiB
 that `bench.py --copy-probe-mb` performs in the same run: the factor
@@ -81,11 +84,41 @@ def counter_per_dispatch(pmc_dir, counter):
     return {k: list(v.values()) for k, v in per.items()}
 
 
+SQ_COUNTERS = ("SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_THREAD_CYCLES_VALU", "SQ_INSTS_SALU",
+               "SQ_INSTS_LDS", "SQ_WAVES")
+# MI355X: 256 compute units x 4 SIMDs, 2.4 GHz peak engine clock; a wave64
+# vector instruction occupies a 16-lane SIMD for 4 cycles
+SIMDS = 1024
+CLOCK_HZ = 2.4e9
+
+
+def sq_summary(sq_dir, stats):
+    """Per kernel: counter averages per dispatch and two derived figures,
+    the vector-ALU issue fraction (VALU instructions x 4 cycles over the
+    SIMD-cycles of the kernel's average duration at the peak clock) and the
+    active-lane fraction of a VALU instruction (SQ_THREAD_CYCLES_VALU over
+    64 x SQ_ACTIVE_INST_VALU, the definition of rocprof's VALUUtilization)."""
+    dur = {x["kernel"]: x["avg_us"] for x in stats}
+    out = {}
+    per = {c: counter_per_dispatch(sq_dir, c) for c in SQ_COUNTERS}
+    for k in set().union(*[set(v) for v in per.values()]):
+        avg = {c: (sum(per[c][k]) / len(per[c][k]) if per[c].get(k) else 0.0) for c in SQ_COUNTERS}
+        rec = dict(avg)
+        if k in dur and dur[k] > 0:
+            rec["valu_issue_frac"] = avg["SQ_INSTS_VALU"] * 4.0 / (SIMDS * dur[k] * 1e-6 * CLOCK_HZ)
+        if avg["SQ_ACTIVE_INST_VALU"] > 0:
+            rec["valu_lane_frac"] = avg["SQ_THREAD_CYCLES_VALU"] / (64.0 * avg["SQ_ACTIVE_INST_VALU"])
+        out[k] = rec
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
+    ap.add_argument("--sq")
+    ap.add_argument("--sq-command", default="")
     ap.add_argument("--copy-mib", type=float, default=256.0)
     ap.add_argument("--workload", required=True)
     ap.add_argument("--command", required=True)
@@ -134,6 +167,24 @@ def main(argv=None):
         name = s["kernel"] if len(s["kernel"]) < 64 else s["kernel"][:61] + "..."
         lines.append(f"| `{name}` | {s['calls']} | {s['avg_us']:.1f} | {s['min_us']:.1f} | "
                      f"{s['max_us']:.1f} | {s['share']:.1f}% | {rd} | {wr} |")
+    sq = sq_summary(a.sq, stats) if a.sq else {}
+    if sq:
+        lines += ["", "Vector-ALU use (one `--pmc` run with the counters "
+                  + ", ".join(SQ_COUNTERS) + (f": `{a.sq_command}`" if a.sq_command else "")
+                  + "). Issue fraction: VALU instructions x 4 cycles over 1024 SIMDs x the "
+                  "kernel's average duration at 2.4 GHz. Lane fraction: SQ_THREAD_CYCLES_VALU / "
+                  "(64 x SQ_ACTIVE_INST_VALU).", "",
+                  "| kernel | VALU instr / launch | SALU instr | LDS instr | waves | VALU issue | active lanes |",
+                  "|---|---|---|---|---|---|---|"]
+        for st in stats:
+            r = sq.get(st["kernel"])
+            if not r or r["SQ_INSTS_VALU"] < 1e5:
+                continue
+            name = st["kernel"] if len(st["kernel"]) < 64 else st["kernel"][:61] + "..."
+            lines.append(f"| `{name}` | {r['SQ_INSTS_VALU'] / 1e6:.1f}M | "
+                         f"{r['SQ_INSTS_SALU'] / 1e6:.1f}M | {r['SQ_INSTS_LDS'] / 1e6:.2f}M | "
+                         f"{r['SQ_WAVES']:.0f} | {100 * r.get('valu_issue_frac', 0):.1f}% | "
+                         f"{100 * r.get('valu_lane_frac', 0):.1f}% |")
     lines += ["", f"Library source hash: `{source_hash()}`", ""]
     os.makedirs(os.path.dirname(os.path.abspath(a.out_md)), exist_ok=True)
     with open(a.out_md, "w") as f:
@@ -141,7 +192,7 @@ def main(argv=None):
     if a.out_json:
         rec = dict(workload=a.workload, command=a.command, source_hash=source_hash(),
                    kernels={s["kernel"]: dict(avg_us=s["avg_us"], calls=s["calls"]) for s in stats},
-                   traffic=traffic)
+                   traffic=traffic, sq=sq)
         with open(a.out_json, "w") as f:
             json.dump(rec, f, indent=1, sort_keys=True)
     print("\n".join(lines))

@@ -29,6 +29,9 @@ def test_select_free_form_matches_spline():
     for u in _grid():
         w, dw = kernel_w(u)
         t = min(0.0, 1.0 - 2.0 * u)
+        # the sweep forms t as -clamp(2u - 1, 0, 1) and s as clamp(1 - 2u, 0, 1)
+        assert t == -min(1.0, max(0.0, 2.0 * u - 1.0)), u
+        assert max(0.0, 1.0 - 2.0 * u) == min(1.0, max(0.0, 1.0 - 2.0 * u)), u
         assert abs((1.0 - 6.0 * u * u + 6.0 * u ** 3 + t ** 3) - w) < 1e-12, u
         assert abs((18.0 * u ** 3 - 12.0 * u * u - 6.0 * u * t * t) - u * dw) < 1e-12, u
 
