@@ -46,34 +46,33 @@ __device__ __forceinline__ int key_bucket(float k, float kmin, float scale, int 
 
 // Cells of at most MAXC particles, one particle per thread (blockDim = MAXC),
 // all 13 axes at once with the axis loops unrolled so that their LDS traffic
-// overlaps.  NB buckets per axis (as many as particles for the 256 class:
-// fewer mates per bucket, fewer rank rounds, at five workgroups per compute
-// unit instead of seven).  The histograms and the bucket-order lists of
-// in-cell ranks and keys live in LDS (30 KB for MAXC = NB = 256), so several
-// cells share a compute unit; a particle's rank counts its bucket
-// mates with a smaller (key, in-cell rank), read from the bucket-order lists
-// with one LDS load each, the 13 axes' mates a round at a time.  Each
-// particle writes its own entries of the sorted lists at its ranks, and the
-// first keys of the tiles of 16 positions.  The register bound matches the
-// occupancy the LDS allows (six waves per SIMD for the 64 class, five for
-// the 256 class with 256 buckets, 30 KB of LDS per workgroup; four for the
-// 512 class, which spills at six), so that the rounds' loads cost no
-// occupancy and no register is given up for waves that cannot run.
+// overlaps.  Each key is quantised, monotonically, to QB bits of its axis'
+// range within the cell and packed with the particle's in-cell rank into one
+// 32-bit word, unique within the cell: ordering the words orders the keys
+// (keys closer than 2^-QB of the range keep in-cell order, a swap far below
+// the slack of every bound that reads the sorted lists).  NB equal buckets per
+// axis.  The cell order is x order, so the x axis' list is the identity and
+// is written without sorting.  The histograms and the bucket-order lists
+// of words live in LDS (26 KB for MAXC = NB = 256); a particle's rank is its
+// bucket's start plus the bucket mates with a smaller word, one LDS load and
+// one compare per mate, the 13 axes' mates a round at a time.  Each particle
+// writes its own entries of the sorted lists at its ranks, and the first keys
+// of the tiles of 16 positions.  Five waves per SIMD at least (four for the
+// 512 class): the register bound keeps the 13 axes' words, bucket places and
+// ranks in registers without spilling.
 template <int MAXC, int NB, bool LIST>
-__global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(
-    MAXC > 256 ? 4 : (MAXC == 256 && NB == 256 ? 5 : 6))))
+__global__ void __launch_bounds__(MAXC) __attribute__((amdgpu_waves_per_eu(MAXC > 256 ? 4 : 5)))
 k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
                const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
                const float *__restrict__ Hc, int64_t n, uint16_t *__restrict__ sidx,
                int64_t tslots, float *__restrict__ tiles, int min_cnt,
                const int32_t *__restrict__ list)
 {
+    constexpr int RB = MAXC <= 64 ? 6 : (MAXC <= 256 ? 8 : 9);   // bits of the in-cell rank
+    constexpr int QB = 32 - RB < 24 ? 32 - RB : 24;                // bits of the quantised key
+    constexpr float QMAX = (float)((1u << QB) - 1u);               // exact in fp32
     __shared__ uint32_t hist[13][NB];
-    // in-cell ranks in bucket order: bytes while they fit (smaller LDS, more
-    // cells per compute unit)
-    using rank_t = typename std::conditional<MAXC <= 256, uint8_t, uint16_t>::type;
-    __shared__ rank_t border[13][MAXC];
-    __shared__ float bkey[13][MAXC];
+    __shared__ uint32_t bword[13][MAXC];
     // one cell (blockIdx.x), or LIST: the listed cells, a grid's worth at a time
     const int nitem = LIST ? list[0] : 1;
     for (int item = LIST ? (int)blockIdx.x : 0; item < nitem; item += LIST ? (int)gridDim.x : 1) {
@@ -88,26 +87,29 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
         const float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
         const float Hi = on ? Hc[s0 + r] : 0.0f;
         __syncthreads();
-        float k[13];
         int b[13];
-        uint32_t sl[13];
+        uint32_t w[13], sl[13];
     #pragma unroll
         for (int g = 0; g < 13; ++g) {
-            // the cell's key range on axis g cut into NB buckets (any monotone map
-            // of the key will do: each key's bucket is computed once)
+            // the key's place t in [0, 1] across the cell's key range on axis g
+            if (g == kTileAxisX) continue;
             float e[3];
             dir_axis(g, e);
             const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
                                fminf(e[2], 0.f) * B.edge[2];
             const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
                                fmaxf(e[2], 0.f) * B.edge[2];
-            const float scale = (float)NB * __builtin_amdgcn_rcpf(kmax - kmin);
-            k[g] = proj_key(p.x, p.y, p.z, g);
-            b[g] = key_bucket(k[g], kmin, scale, NB);
+            const float kg = proj_key(p.x, p.y, p.z, g);
+            const float t = __builtin_amdgcn_fmed3f((kg - kmin) * __builtin_amdgcn_rcpf(kmax - kmin),
+                                                    0.0f, 1.0f);
+            w[g] = ((uint32_t)(t * QMAX) << RB) | (uint32_t)r;
+            const int bb = (int)(t * (float)NB);
+            b[g] = bb < NB ? bb : NB - 1;
         }
         if (on) {
     #pragma unroll
-            for (int g = 0; g < 13; ++g) sl[g] = atomicAdd(&hist[g][b[g]], 1u);
+            for (int g = 0; g < 13; ++g)
+                if (g != kTileAxisX) sl[g] = atomicAdd(&hist[g][b[g]], 1u);
         }
         __syncthreads();
         {
@@ -116,6 +118,7 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
             const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
             constexpr int per = NB >= 64 ? NB / 64 : 1;
             for (int g = wave; g < 13; g += (int)(blockDim.x >> 6)) {
+                if (g == kTileAxisX) continue;
                 uint32_t v[per];
                 uint32_t loc = 0;
     #pragma unroll
@@ -142,22 +145,25 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
         if (on) {
     #pragma unroll
             for (int g = 0; g < 13; ++g) {
+                if (g == kTileAxisX) continue;
                 q0[g] = (int)hist[g][b[g]];
-                border[g][q0[g] + (int)sl[g]] = (rank_t)r;
-                bkey[g][q0[g] + (int)sl[g]] = k[g];
+                bword[g][q0[g] + (int)sl[g]] = w[g];
             }
         }
         __syncthreads();
         if (on) {
-            // exact rank: bucket start + bucket mates with a smaller (key, rank).
-            // The 13 axes' bucket scans advance together, one mate per axis per
-            // round, so each round issues its LDS reads side by side instead of
-            // 13 dependent chains; q0 packs the bucket start (low 16 bits) and
-            // its size (high 16 bits)
+            // rank: bucket start + bucket mates with a smaller word.  The 13
+            // axes' bucket scans advance together, one mate per axis per
+            // round, so each round issues its LDS reads side by side; q0
+            // packs the bucket start (low 16 bits) and its size (high 16)
             int rk[13];
             int maxlen = 0;
     #pragma unroll
             for (int g = 0; g < 13; ++g) {
+                if (g == kTileAxisX) {
+                    rk[g] = r;   // the cell order
+                    continue;
+                }
                 const int q1 = b[g] + 1 < NB ? (int)hist[g][b[g] + 1] : cnt;
                 rk[g] = q0[g];
                 maxlen = max(maxlen, q1 - q0[g]);
@@ -166,13 +172,12 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
             for (int j = 0; j < maxlen; ++j) {
     #pragma unroll
                 for (int g = 0; g < 13; ++g) {
+                    if (g == kTileAxisX) continue;
                     // every bucket holds at least this particle, so the clamped
                     // index stays in it; past its end the round counts nothing
                     const int len = q0[g] >> 16;
                     const int q = (q0[g] & 0xffff) + min(j, len - 1);
-                    const int r2 = border[g][q];
-                    const float k2 = bkey[g][q];
-                    rk[g] += (int)(j < len) & ((int)(k2 < k[g]) | ((int)(k2 == k[g]) & (int)(r2 < r)));
+                    rk[g] += (int)(j < len) & (int)(bword[g][q] < w[g]);
                 }
             }
     #pragma unroll
@@ -181,11 +186,13 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
                 const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
                 sidx[o] = (uint16_t)r;
                 // tile summaries: the first keys of the tiles from either end
+                // (the key recomputed as before: same operations, same value)
+                const float kg = proj_key(p.x, p.y, p.z, g);
                 const int re = cnt - 1 - rank;
-                if ((rank & 15) == 0) tiles[kTileTS(g) * tslots + slot0 + (rank >> 4)] = k[g];
-                if ((re & 15) == 0) tiles[kTileTE(g) * tslots + slot0 + (re >> 4)] = k[g];
+                if ((rank & 15) == 0) tiles[kTileTS(g) * tslots + slot0 + (rank >> 4)] = kg;
+                if ((re & 15) == 0) tiles[kTileTE(g) * tslots + slot0 + (re >> 4)] = kg;
                 if (g == kTileAxisX && ((rank & 15) == 15 || re == 0))
-                    tiles[kTileTLX * tslots + slot0 + (rank >> 4)] = k[g];
+                    tiles[kTileTLX * tslots + slot0 + (rank >> 4)] = kg;
             }
         }
         // largest cut-off of each tile of the cell order (16 consecutive threads)
