@@ -218,6 +218,15 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[3]);
  *                         receivers' sums are taken in another order.  The
  *                         plain sweep always takes one cell per item.
  *                         Default 0.
+ *   PV_PARAM_SYM_SELF     1: the receiver's own cell by the symmetric pair
+ *                         update (Section 3.3's update of both particles of
+ *                         a pair from one distance test): each unordered
+ *                         pair of the cell is tested once and adds to both
+ *                         particles, in items of whole cells (cells of at
+ *                         most PV_PARAM_CHUNK particles); the adjoint sweep,
+ *                         and the density sweep where masses are equal;
+ *                         0: every receiver gathers from its own cell.
+ *                         Default 0.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,
@@ -227,6 +236,7 @@ typedef enum {
     PV_PARAM_TAIL_PARTS = 5,
     PV_PARAM_TAIL_CELLS = 6,
     PV_PARAM_GROUP = 7,
+    PV_PARAM_SYM_SELF = 8,
     PV_PARAM_ADJOINT = 16,
     PV_PARAM_PLAIN = 32
 } pv_param;

@@ -66,11 +66,52 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     return LIB
 
 
+# Host code built with AddressSanitizer (device code as usual), for the CPU
+# tests of the C ABI: load it with the sanitizer runtime preloaded.
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_LIB = os.path.join(ASAN_DIR, "libpvl.so")
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's AddressSanitizer runtime (empty if absent)."""
+    r = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    p = r.stdout.strip()
+    return p if r.returncode == 0 and os.path.isabs(p) and os.path.exists(p) else ""
+
+
+def build_asan(jobs: int = 8) -> str:
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    flags = [f if f != "-O3" else "-O1" for f in CFLAGS] + ["-g"] + ASAN_FLAGS
+
+    def one(src):
+        obj = os.path.join(ASAN_DIR, os.path.basename(src) + ".o")
+        r = subprocess.run([HIPCC, *flags, "-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+        return obj
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(one, sources()))
+    tmp = ASAN_LIB + f".tmp{os.getpid()}"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *ASAN_FLAGS, "-o", tmp, *objs]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=8)
+    ap.add_argument("--asan", action="store_true",
+                    help="also build the host-sanitizer library for the CPU tests")
     a = ap.parse_args(argv)
     build(a.jobs, verbose=True)
+    if a.asan:
+        print(f"built {build_asan(a.jobs)}")
 
 
 if __name__ == "__main__":

@@ -572,6 +572,7 @@ pv_status pv_set_param(pv_ctx *ctx, int param, int value)
             return fail(ctx, PV_EINVAL, "group must be 0..8");
         t.group = value;
         return PV_OK;
+    case PV_PARAM_SYM_SELF: t.sym_self = value ? 1 : 0; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -588,6 +589,7 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value)
     case PV_PARAM_TAIL_PARTS: *value = t.tail_parts; return PV_OK;
     case PV_PARAM_TAIL_CELLS: *value = t.tail_cells; return PV_OK;
     case PV_PARAM_GROUP: *value = t.group; return PV_OK;
+    case PV_PARAM_SYM_SELF: *value = t.sym_self; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }

@@ -176,6 +176,7 @@ struct SweepTuning {
     int tail_parts = 2;         // the queue's last cells run as this many items (1, 2, 4)
     int tail_cells = 0;         // how many cells (0: automatic)
     int group = 0;              // small cells per work item, at most (1..8; 0: automatic)
+    int sym_self = 0;           // own cells by the symmetric pair update
     int num_cu = 256;           // compute units of the device
 };
 

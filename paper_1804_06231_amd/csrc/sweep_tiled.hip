@@ -74,6 +74,7 @@ constexpr int kModeLJ = 3;
 
 constexpr int kChunk = 256;                    // largest receivers per work item
 static_assert(kChunk == kTailRecv, "tail slots hold one chunk");
+static_assert(kChunk <= 256, "an item's receiver ranks fit a byte");
 // Cells per work item that a mode's LDS holds: the plain sweep takes one cell
 // per item (its smaller LDS then leaves room for five workgroups per compute
 // unit), the others up to kGroupMax.
@@ -210,6 +211,130 @@ __device__ __forceinline__ void grad_interact(float dx, float dy, float dz, floa
             grad_interact(dx, dy, dz, r2, mj, ij, cj, in_j, in_k, invH, ck, mi, acc); \
     }
 
+// Symmetric pair update in the receiver's own cell (Section 3.3's update of
+// both particles of a pair from one distance test).  A tile of sources j
+// against the row's receivers k is swept once for the unordered pairs: the
+// receiver's sums as in the gathered step, the source's in registers that
+// move one lane per step with the source they belong to (lane l holds the
+// sums of the source it meets at step K), so that after 16 steps each lane
+// holds its own source's sums again.
+//
+// Density, equal masses: both sides add to the four cubic sums of their own
+// cut-off (v = clamp(1 - u), s = clamp(1 - 2u) vanish for u >= 1, so a pair
+// beyond one particle's cut-off adds nothing to it) and to its count.
+__device__ __forceinline__ void unit_pair_sym(float r2, float invHk, float invHj, bool in_k,
+                                              bool in_j, bool src_on, UnitAcc &a, UnitAcc &b)
+{
+    const float r = __builtin_amdgcn_sqrtf(r2);   // v_sqrt_f32, 1 ulp
+    const float uk = r * invHk, uj = r * invHj;
+    const float vk = clamp01(1.0f - uk), sk = clamp01(fmaf(-2.0f, uk, 1.0f));
+    const float vk2 = vk * vk, sk2 = sk * sk;
+    a.v3 = fmaf(vk2, vk, a.v3);
+    a.s3 = fmaf(sk2, sk, a.s3);
+    a.uv2 = fmaf(uk, vk2, a.uv2);
+    a.us2 = fmaf(uk, sk2, a.us2);
+    a.cnt += in_k ? 1.0f : 0.0f;
+    const float on = src_on ? 1.0f : 0.0f;
+    const float vj = on * clamp01(1.0f - uj), sj = on * clamp01(fmaf(-2.0f, uj, 1.0f));
+    const float vj2 = vj * vj, sj2 = sj * sj;
+    b.v3 = fmaf(vj2, vj, b.v3);
+    b.s3 = fmaf(sj2, sj, b.s3);
+    b.uv2 = fmaf(uj, vj2, b.uv2);
+    b.us2 = fmaf(uj, sj2, b.us2);
+    b.cnt += (in_j & src_on) ? 1.0f : 0.0f;
+}
+
+// Adjoint: the force term of a pair is antisymmetric (the bracket
+// G_k m_j W_r(r, H_k) + G_j m_k W_r(r, H_j) times the unit vector between
+// them), so the source gets the receiver's term with the opposite sign; its
+// drho_dh sum takes m_k (3 w + u w') of its own cut-off.
+__device__ __forceinline__ void grad_pair_sym(float dx, float dy, float dz, float r2, float mj,
+                                              float invHj, float cj, bool in_j, bool in_k,
+                                              float invHk, float ck, float mk, bool src_on,
+                                              GradAcc &a, GradAcc &b)
+{
+    float invr = r2 > 0.0f ? __builtin_amdgcn_rsqf(r2) : 0.0f;   // v_rsq_f32, 1 ulp
+    float r = r2 * invr;
+    float uk = r * invHk;
+    float uj = r * invHj;
+    float tk = -clamp01(fmaf(2.0f, uk, -1.0f));
+    float tj = -clamp01(fmaf(2.0f, uj, -1.0f));
+    float tk2 = tk * tk, tj2 = tj * tj;
+    float dwk = fmaf(-6.0f, tk2, uk * fmaf(18.0f, uk, -12.0f));
+    float wk = fmaf(tk2, tk, fmaf(uk * uk, fmaf(6.0f, uk, -6.0f), 1.0f));
+    float dwj = fmaf(-6.0f, tj2, uj * fmaf(18.0f, uj, -12.0f));
+    float wj = fmaf(tj2, tj, fmaf(uj * uj, fmaf(6.0f, uj, -6.0f), 1.0f));
+    const float mjk = in_k ? mj : 0.0f;
+    const float cmj = in_j ? cj * mk : 0.0f;
+    float coef = fmaf(ck * mjk, dwk, cmj * dwj);
+    a.dh = fmaf(mjk, fmaf(uk, dwk, 3.0f * wk), a.dh);
+    float c = -coef * invr;
+    a.gx = fmaf(c, dx, a.gx);
+    a.gy = fmaf(c, dy, a.gy);
+    a.gz = fmaf(c, dz, a.gz);
+    const float cs = src_on ? -c : 0.0f;
+    const float mkj = (in_j & src_on) ? mk : 0.0f;
+    b.dh = fmaf(mkj, fmaf(uj, dwj, 3.0f * wj), b.dh);
+    b.gx = fmaf(cs, dx, b.gx);
+    b.gy = fmaf(cs, dy, b.gy);
+    b.gz = fmaf(cs, dz, b.gz);
+}
+
+// The source sums one lane on (row_ror:1), so that they stay with the source
+// the next step meets.
+__device__ __forceinline__ void rotate_sums(UnitAcc &b)
+{
+    b.v3 = ror16<1>(b.v3);
+    b.s3 = ror16<1>(b.s3);
+    b.uv2 = ror16<1>(b.uv2);
+    b.us2 = ror16<1>(b.us2);
+    b.cnt = ror16<1>(b.cnt);
+}
+__device__ __forceinline__ void rotate_sums(GradAcc &b)
+{
+    b.gx = ror16<1>(b.gx);
+    b.gy = ror16<1>(b.gy);
+    b.gz = ror16<1>(b.gz);
+    b.dh = ror16<1>(b.dh);
+}
+
+// One symmetric step K of a tile (every lane-crossing read before the branch:
+// a DPP read from a lane outside the branch gives zero).  On the diagonal tile (the receivers' own
+// block) each unordered pair meets twice: steps 1..7 take both sides, step 8
+// (lane l with l + 8, and l + 8 with l) the receiver's side only, steps 0
+// (the particle itself) and 9..15 nothing.
+#define PVL_SYM_STEP_U(K)                                                   \
+    {                                                                       \
+        const bool rk = (K == 0 || K > 8) ? !on_diag : true;                \
+        const bool sk = (K == 0 || K > 7) ? !on_diag : true;                \
+        float dx = ror16<K>(sx) - tx;                                       \
+        float dy = ror16<K>(sy) - ty;                                       \
+        float dz = ror16<K>(sz) - tz;                                       \
+        const float hj2 = ror16<K>(sh2), ij = ror16<K>(sinv);               \
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                     \
+        const bool in_k = r2 < H2, in_j = r2 < hj2;                         \
+        if ((in_k | in_j) & rk)                                             \
+            unit_pair_sym(r2, invH, ij, in_k, in_j, sk, uacc, usrc);        \
+        rotate_sums(usrc);                                                  \
+    }
+
+#define PVL_SYM_STEP_G(K)                                                   \
+    {                                                                       \
+        const bool rk = (K == 0 || K > 8) ? !on_diag : true;                \
+        const bool sk = (K == 0 || K > 7) ? !on_diag : true;                \
+        float dx = ror16<K>(sx) - tx;                                       \
+        float dy = ror16<K>(sy) - ty;                                       \
+        float dz = ror16<K>(sz) - tz;                                       \
+        const float mj = ror16<K>(sm), hj2 = ror16<K>(sh2);                 \
+        const float ij = ror16<K>(sinv), cj = ror16<K>(sc);                 \
+        float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));                     \
+        const bool in_k = r2 < H2, in_j = r2 < hj2;                         \
+        if ((in_k | in_j) & rk)                                             \
+            grad_pair_sym(dx, dy, dz, r2, mj, ij, cj, in_j, in_k, invH, ck, mi, sk, gacc, \
+                          gsrc);                                            \
+        rotate_sums(gsrc);                                                  \
+    }
+
 // Lennard-Jones pair term (d = x_j - x_i, 0 < r2 < H_i^2).
 __device__ __forceinline__ void lj_interact(float dx, float dy, float dz, float r2, float sig2,
                                             float eps, TileAcc &a)
@@ -336,9 +461,14 @@ struct SweepArgs {
 template <int G>
 struct SweepLds {
     float4 acc[4][kChunk];       // per-wave receiver sums; aliased during set-up
-    uint16_t rlist[kMaxRecv];    // receivers per direction (compacted or reach-ordered)
+    // receivers per direction (compacted or reach-ordered): in-cell ranks less
+    // the item's first rank r_lo, below the chunk size, so one byte each
+    uint8_t rlist[kMaxRecv];
     uint32_t tasks[max_tasks(G)];
-    uint16_t torder[max_tasks(G)];  // also each task's (cell, direction) (bytes) until ordered
+    // the task order (0xffff: a gap that keeps the symmetric own-cell tasks
+    // in groups of their own); also each task's (cell, direction) (bytes)
+    // until ordered
+    uint16_t torder[max_tasks(G) + 4];
     // per (cell g of the item, direction d): entry 27 g + d (26 g + d for the
     // neighbour directions alone)
     int n_act[27 * G];
@@ -353,6 +483,7 @@ struct SweepLds {
     float ghmax[G], gdx[G];
     int mbad[4];         // per wave: a mass differs from the first cell's
     int item;
+    int ntask_eff;       // entries of the task order, gaps included
 };
 
 // Outputs of receiver p (cell order) from its sums over all sources: the
@@ -423,7 +554,7 @@ __device__ __forceinline__ int wave_scan(int m, int lane, V value, E emit)
 // along z, each swept whole (small cells whose particles fit one chunk
 // together).  The item's receivers are numbered in cell order from the
 // first receiver's position.
-template <int MODE>
+template <int MODE, bool SYM>
 __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int a, int chunk,
                            int part, int nparts, int slot)
 {
@@ -547,6 +678,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         if ((L.mbad[0] | L.mbad[1] | L.mbad[2] | L.mbad[3]) == 0 && ma == ma && ma != INFINITY)
             mass = ma;
     }
+    // own cells by the symmetric update: items of whole cells, in the
+    // adjoint and in the equal-mass density
+    const bool symitem = SYM && whole && (ADJ || (!LJ && !PLAIN && mass == mass));
 
     // active receivers of this item, per (cell, direction): n_act[27 g + d]
     bool listed = false;   // receivers taken from L.rlist
@@ -581,10 +715,11 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 nb_offset(d, dx, dy, dz);
                 const int s = dir_canon(dx, dy, dz, &sign);
                 const uint16_t *il = sidx + (size_t)s * n + sa;
-                uint16_t *out = L.rlist + L.recv_off[gd];
+                uint8_t *out = L.rlist + L.recv_off[gd];
                 const bool face = (dx != 0) + (dy != 0) + (dz != 0) == 1;
                 if (!face) {
-                    for (int q = lane; q < act; q += 64) out[q] = il[sign > 0 ? na - 1 - q : q];
+                    for (int q = lane; q < act; q += 64)
+                        out[q] = (uint8_t)il[sign > 0 ? na - 1 - q : q];
                     continue;
                 }
                 if (act == 0) continue;
@@ -634,7 +769,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 }
 #pragma unroll
                 for (int c = 0; c < R; ++c)
-                    if (c < nc && bk[c] < kReachBuckets) out[pos[c]] = iav[c];
+                    if (c < nc && bk[c] < kReachBuckets) out[pos[c]] = (uint8_t)iav[c];
             }
         }
     } else {
@@ -653,7 +788,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             nb_offset(d, dx, dy, dz);
             const int s = dir_canon(dx, dy, dz, &sign);
             const uint16_t *il = sidx + (size_t)s * n + sa0;
-            uint16_t *out = L.rlist + d * A.chunk;
+            uint8_t *out = L.rlist + d * A.chunk;
             int cnt = 0;   // wavefront-uniform
             for (int q0 = 0; q0 < act; q0 += 4 * 64) {
                 int iv[4];
@@ -669,7 +804,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                     if (keep)
                         out[cnt + (int)__builtin_amdgcn_mbcnt_hi(
                                       (uint32_t)(m >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] = (uint16_t)iv[u];
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                            (uint8_t)(iv[u] - r_lo);
                     cnt += __popcll(m);
                 }
             }
@@ -726,12 +862,21 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             const int jb = (r_lo >> 4) + blk;
             const float *first_x = tiles + kTileTS(kSelfAxis) * ts + slot_a;
             const float *last_x = tiles + kTileTLX * ts + slot_a;
-            // the adjoint's pairs reach max(H_i, H_j) <= the cell's largest cut-off
-            const float hb = ADJ ? hmax_a : tiles[kTileBHX * ts + slot_a + jb];
-            const float lo_k = first_x[jb] - hb - slack - 2.0f * dx_a;
-            const float hi_k = last_x[jb] + hb + slack + 2.0f * dx_a;
-            t0 = prefix_count<1>(last_x, ntile_a, lo_k);
-            nt = prefix_count<0>(first_x, ntile_a, hi_k) - t0;
+            if (symitem) {
+                // symmetric update: each unordered pair once, from the block
+                // of the one with the smaller x; a pair counts for either
+                // particle's cut-off, at most the cell's largest
+                const float hi_k = last_x[jb] + hmax_a + slack + 2.0f * dx_a;
+                t0 = jb;
+                nt = prefix_count<0>(first_x, ntile_a, hi_k) - jb;
+            } else {
+                // the adjoint's pairs reach max(H_i, H_j) <= the cell's largest cut-off
+                const float hb = ADJ ? hmax_a : tiles[kTileBHX * ts + slot_a + jb];
+                const float lo_k = first_x[jb] - hb - slack - 2.0f * dx_a;
+                const float hi_k = last_x[jb] + hb + slack + 2.0f * dx_a;
+                t0 = prefix_count<1>(last_x, ntile_a, lo_k);
+                nt = prefix_count<0>(first_x, ntile_a, hi_k) - t0;
+            }
         } else {
             int dx, dy, dz;
             nb_offset(dir, dx, dy, dz);
@@ -753,9 +898,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             // their positions and cut-offs: two round trips to memory.
             int iv[16];
             if (listed) {
-                const uint16_t *rl = L.rlist + L.recv_off[26 * g + dir];
+                const uint8_t *rl = L.rlist + L.recv_off[26 * g + dir];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) iv[u] = rl[min(r0 + u, r1 - 1)];
+                for (int u = 0; u < 16; ++u) iv[u] = r_lo + rl[min(r0 + u, r1 - 1)];
             } else {
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
@@ -791,8 +936,21 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     // stable counting sort on the tile count (kTaskLevels levels, longer
     // counts share the top one) made of ballots on one wavefront; ties keep
     // task order, so the order is deterministic
-    if (!A.task_sort) {
+    // With symmetric own cells their tasks take the top half of the levels
+    // (by half their tile count) and the others the bottom half, and the
+    // order leaves a gap of up to 3 entries after the last symmetric task, so
+    // that no group of four mixes the two kinds.
+    auto level_of = [&](int t) {
+        const uint32_t tw = L.tasks[t];
+        const int nt = task_tiles(tw);
+        if (!symitem) return min(nt, kTaskLevels - 1);
+        const bool own = (int)((tw >> 15) & 255u) % 27 == 26;
+        return own ? kTaskLevels / 2 + min(nt >> 1, kTaskLevels / 2 - 1)
+                   : min(nt, kTaskLevels / 2 - 1);
+    };
+    if (!A.task_sort && !symitem) {
         for (int t = tid; t < ntask; t += blockDim.x) L.torder[t] = (uint16_t)t;
+        if (tid == 0) L.ntask_eff = ntask;
     } else if (wave == 0) {
         int below[kTaskLevels];   // tasks of each level in the chunks so far
         int start[kTaskLevels];
@@ -800,20 +958,26 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         for (int v = 0; v < kTaskLevels; ++v) below[v] = 0;
         for (int c = 0; c < ntask; c += 64) {
             const int t = c + lane;
-            const int lv = t < ntask ? min(task_tiles(L.tasks[t]), kTaskLevels - 1) : -1;
+            const int lv = t < ntask ? level_of(t) : -1;
 #pragma unroll
             for (int v = 0; v < kTaskLevels; ++v) below[v] += __popcll(__ballot(lv == v));
         }
-        int run = 0;
+        int run = 0, gap = 0;
 #pragma unroll
         for (int v = kTaskLevels - 1; v >= 0; --v) {
+            if (symitem && v == kTaskLevels / 2 - 1) {
+                gap = ((run + 3) & ~3) - run;
+                if (lane < gap) L.torder[run + lane] = 0xffffu;
+                run += gap;
+            }
             start[v] = run;
             run += below[v];
             below[v] = 0;
         }
+        if (lane == 0) L.ntask_eff = ntask + gap;
         for (int c = 0; c < ntask; c += 64) {
             const int t = c + lane;
-            const int lv = t < ntask ? min(task_tiles(L.tasks[t]), kTaskLevels - 1) : -1;
+            const int lv = t < ntask ? level_of(t) : -1;
             int pos = 0;
 #pragma unroll
             for (int v = 0; v < kTaskLevels; ++v) {
@@ -849,10 +1013,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         return direct ? j : (int)sidx[(size_t)s * n + sb + (sign > 0 ? j : nb - 1 - j)];
     };
     // task word of this row in the wave's group q (0: none)
+    const int ntask_eff = L.ntask_eff;
     auto task_word = [&](int q, bool &ok) -> uint32_t {
         const int t = group_of(q) * 4 + row;
-        ok = t < ntask;
-        return ok ? L.tasks[L.torder[t]] : 0u;
+        const int k = t < ntask_eff ? (int)L.torder[t] : 0xffff;
+        ok = k != 0xffff;
+        return ok ? L.tasks[k] : 0u;
     };
     // neighbour geometry of (cell g, direction dir): first slot, count, shift
     // into the frame of cell g, axis and sign
@@ -888,7 +1054,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     // straight into the index stage
     auto cursor_enter = [&](int q) {
         cvalid = false;
-        while (group_of(q) * 4 < ntask) {
+        while (group_of(q) * 4 < ntask_eff) {
             bool ok;
             const uint32_t tw = task_word(q, ok);
             const int nt = ok ? task_tiles(tw) : 0;
@@ -914,7 +1080,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             e2_ria = 0;
             if (e2_rok) {
                 if (c_direct) e2_ria = r_lo + r;
-                else if (listed) e2_ria = L.rlist[L.recv_off[26 * g + dir] + r];
+                else if (listed) e2_ria = r_lo + L.rlist[L.recv_off[26 * g + dir] + r];
                 else e2_ria = sidx[(size_t)c_s * n + e2_sa + (c_sign > 0 ? L.gna[g] - 1 - r : r)];
             }
             cq = q;
@@ -952,6 +1118,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             if constexpr (ADJ) {
                 e1_sh = A.Hc[p];
                 e1_sg = A.gcell[p];
+            } else if (symitem) {
+                e1_sh = A.Hc[p];
             }
         }
         if (e2_start) {
@@ -979,6 +1147,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     TileAcc acc = {0.f, 0.f, 0.f, 0.f};
     UnitAcc uacc = {0.f, 0.f, 0.f, 0.f, 0.f};
     GradAcc gacc = {0.f, 0.f, 0.f, 0.f};
+    // symmetric own-cell groups: the sources' sums of the current tile, and
+    // the row's cell (for the sources' places in the item)
+    UnitAcc usrc = {0.f, 0.f, 0.f, 0.f, 0.f};
+    GradAcc gsrc = {0.f, 0.f, 0.f, 0.f};
+    bool symg = false;
+    int cell_off = 0, cell_n = 0;
     const float sig2 = A.lj_sigma2, eps = A.lj_eps;
     const bool unit = !LJ && !ADJ && mass == mass;
     while (e1_valid) {   // wave-uniform
@@ -1015,13 +1189,19 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             // the own cell's diagonal tile pairs each receiver with itself at K = 0
             diag = dir == 26 ? (r_lo >> 4) + blk : -1;
             it = 0;
+            // a lane without a receiver sits far away, so that no source is
+            // within its own or the source's cut-off (the symmetric update
+            // and the adjoint also add to the source)
+            if (!recv_ok) {
+                tx += 1e30f;
+                ty += 1e30f;
+                tz += 1e30f;
+            }
+            // groups of symmetric own-cell tasks hold nothing else
+            symg = symitem && __ballot(ok && dir == 26) != 0;
+            cell_off = L.gsa[g] - base;
+            cell_n = L.gna[g];
             if constexpr (ADJ) {
-                // a lane without a receiver sits far away, so that no source
-                // is within its own or the source's cut-off
-                const float far = recv_ok ? 0.0f : 1e30f;
-                tx += far;
-                ty += far;
-                tz += far;
                 ck = (recv_ok ? e1_rg : 0.0f) * ((8.0f / kPi) * (invH * invH) * (invH * invH));
                 mi = pi.w;
             }
@@ -1032,7 +1212,46 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
 
         const int tile = t0 + it;
         const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
-        if (it < nt) {
+        if (SYM && symg) {
+            // the own cell, each unordered pair once
+            if (it < nt && (ADJ || !LJ)) {
+                const bool on_diag = tile == diag;
+                const float hj = qh;
+                const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
+                const float sh2 = hj * hj;
+                if constexpr (ADJ) {
+                    const float sc = qg * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
+                    PVL_SYM_STEP_G(0) PVL_SYM_STEP_G(1) PVL_SYM_STEP_G(2) PVL_SYM_STEP_G(3)
+                    PVL_SYM_STEP_G(4) PVL_SYM_STEP_G(5) PVL_SYM_STEP_G(6) PVL_SYM_STEP_G(7)
+                    PVL_SYM_STEP_G(8) PVL_SYM_STEP_G(9) PVL_SYM_STEP_G(10) PVL_SYM_STEP_G(11)
+                    PVL_SYM_STEP_G(12) PVL_SYM_STEP_G(13) PVL_SYM_STEP_G(14) PVL_SYM_STEP_G(15)
+                } else {
+                    PVL_SYM_STEP_U(0) PVL_SYM_STEP_U(1) PVL_SYM_STEP_U(2) PVL_SYM_STEP_U(3)
+                    PVL_SYM_STEP_U(4) PVL_SYM_STEP_U(5) PVL_SYM_STEP_U(6) PVL_SYM_STEP_U(7)
+                    PVL_SYM_STEP_U(8) PVL_SYM_STEP_U(9) PVL_SYM_STEP_U(10) PVL_SYM_STEP_U(11)
+                    PVL_SYM_STEP_U(12) PVL_SYM_STEP_U(13) PVL_SYM_STEP_U(14) PVL_SYM_STEP_U(15)
+                }
+                // the tile's sources (back on their own lanes after 16 steps)
+                // add their sums to the wave's array
+                const int j = tile * 16 + l16;
+                float4 res;
+                if constexpr (ADJ) {
+                    res = make_float4(gsrc.gx, gsrc.gy, gsrc.gz, gsrc.dh);
+                    gsrc = GradAcc{0.f, 0.f, 0.f, 0.f};
+                } else {
+                    res = make_float4(0.0f, fmaf(2.0f, usrc.v3, -usrc.s3),
+                                      6.0f * (usrc.us2 - usrc.uv2), usrc.cnt);
+                    usrc = UnitAcc{0.f, 0.f, 0.f, 0.f, 0.f};
+                }
+                if (j < cell_n) {
+                    float *dst = reinterpret_cast<float *>(&L.acc[wave][cell_off + j]);
+                    atomicAdd(dst + 0, res.x);
+                    atomicAdd(dst + 1, res.y);
+                    atomicAdd(dst + 2, res.z);
+                    atomicAdd(dst + 3, res.w);
+                }
+            }
+        } else if (it < nt) {
             if constexpr (ADJ) {
                 const float hj = qh, gj = qg;
                 const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
@@ -1107,7 +1326,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     }
 }
 
-template <int MODE>
+template <int MODE, bool SYM = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(MODE == kModePlain ? 5 : 4, 8))) k_sweep_queue(SweepArgs A)
 {
@@ -1133,12 +1352,12 @@ __global__ void __launch_bounds__(kBlock)
     while (item < nitems) {
         if (item < nwhole) {
             const int2 w = item < nbig ? A.items[item] : A.items[A.cap - nsmall + (item - nbig)];
-            sweep_item<MODE>(A, L, w.x, w.y, 0, 1, 0);
+            sweep_item<MODE, SYM>(A, L, w.x, w.y, 0, 1, 0);
         } else {
             const int j = item - nwhole;
             const int slot = j / A.tail_parts;
             const int2 w = A.items[A.cap + slot];
-            sweep_item<MODE>(A, L, w.x, 0, j - slot * A.tail_parts, A.tail_parts, slot);
+            sweep_item<MODE, SYM>(A, L, w.x, 0, j - slot * A.tail_parts, A.tail_parts, slot);
         }
         __syncthreads();
         if (threadIdx.x == 0) L.item = (int)gridDim.x + atomicAdd(A.head, 1);
@@ -1323,10 +1542,16 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.chunk = tune.chunk;
     if (mode == kModePlain)
         hipLaunchKernelGGL(k_sweep_queue<kModePlain>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    else if (mode == kModeAdjoint && tune.sym_self)
+        hipLaunchKernelGGL((k_sweep_queue<kModeAdjoint, true>), dim3((unsigned)grid), dim3(kBlock), 0,
+                           st, A);
     else if (mode == kModeAdjoint)
         hipLaunchKernelGGL(k_sweep_queue<kModeAdjoint>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     else if (mode == kModeLJ)
         hipLaunchKernelGGL(k_sweep_queue<kModeLJ>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    else if (tune.sym_self)
+        hipLaunchKernelGGL((k_sweep_queue<kModeSorted, true>), dim3((unsigned)grid), dim3(kBlock), 0,
+                           st, A);
     else
         hipLaunchKernelGGL(k_sweep_queue<kModeSorted>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
     if (A.tail_cells > 0) {

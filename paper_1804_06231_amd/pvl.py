@@ -14,7 +14,9 @@ from typing import Optional, Sequence
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpvl.so")
+# the in-tree build; PVL_LIBRARY names another build of the same library (the
+# host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("PVL_LIBRARY") or os.path.join(_PKG, "libpvl.so")
 
 PV_OK, PV_EINVAL, PV_ENOMEM, PV_EHIP, PV_EGRID, PV_EOVERFLOW, PV_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PV_SORTED_PAIR, PV_PLAIN_CELL = 0, 1
@@ -33,7 +35,7 @@ EXPORTS = (
 PV_STATIC_MAX_N = 131072
 PV_STATIC_MAX_CELLS = 32768
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4, "tail_parts": 5,
-          "tail_cells": 6, "group": 7}
+          "tail_cells": 6, "group": 7, "sym_self": 8}
 PV_PARAM_ADJOINT = 16
 PV_PARAM_PLAIN = 32
 TUNE_TARGETS = {"density": 0, "adjoint": 1, "plain": 2}

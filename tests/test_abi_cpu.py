@@ -97,7 +97,7 @@ def test_tuning_parameters_without_gpu(lib, vctx):
     from paper_1804_06231_amd.pvl import PARAMS, PV_PARAM_ADJOINT, PV_PARAM_PLAIN
     v = C.c_int()
     defaults = {"reach_order": 0, "task_sort": 1, "queue_wgs": 4, "chunk": 256,
-                "tail_parts": 2, "tail_cells": 0, "group": 0}
+                "tail_parts": 2, "tail_cells": 0, "group": 0, "sym_self": 0}
     for name, p in PARAMS.items():
         for off in (0, PV_PARAM_ADJOINT, PV_PARAM_PLAIN):
             assert lib.pv_get_param(vctx, p + off, C.byref(v)) == 0

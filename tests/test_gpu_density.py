@@ -461,3 +461,63 @@ def test_autotune(ctx, clustered_ref):
             c2.autotune(c2.build_cells(pos, h, m, s.box), "density")   # not sorted
     finally:
         c2.close()
+
+
+@pytest.mark.parametrize("group,chunk,parts", [(0, 256, 2), (1, 256, 1), (8, 256, 4), (0, 64, 2)])
+def test_symmetric_own_cell_keeps_results(ctx, clustered_ref, group, chunk, parts):
+    """The own cell by the symmetric pair update (each unordered pair tested
+    once, both particles updated; cells larger than the chunk keep the
+    gathered form) gives the oracle's density and adjoint, with the exact
+    neighbour counts, bit-identically from run to run, in single-cell items,
+    runs of small cells and split tail items."""
+    s, ref, G, gref = clustered_ref
+    for sw in ("density", "adjoint"):
+        ctx.set_param("sym_self", 1, sw)
+        ctx.set_param("group", group, sw)
+        ctx.set_param("chunk", chunk, sw)
+        ctx.set_param("tail_parts", parts, sw)
+    try:
+        _flush(f"symmetric own cell group={group} chunk={chunk} parts={parts}")
+        c1, out = run_density(ctx, s, "sorted")
+        compare_density(out, ref, label=f"sym group {group} chunk {chunk}")
+        _, out2 = run_density(ctx, s, "sorted", cells=c1)
+        for x, y in zip(out, out2):
+            assert np.array_equal(x, y)
+        g = torch.from_numpy(G).to(dev())
+        gp, gh = ctx.density_backward(c1, g)
+        gp2, gh2 = ctx.density_backward(c1, g)
+        ctx.check()
+        gp, gh = gp.cpu().numpy(), gh.cpu().numpy()
+        assert np.array_equal(gp, gp2.cpu().numpy()) and np.array_equal(gh, gh2.cpu().numpy())
+        ex = np.max(np.abs(gp - gref["gx"]) / np.maximum(gref["gx_abs"], 1e-300))
+        eh = np.max(np.abs(gh - gref["gh"]) / np.maximum(gref["gh_abs"], 1e-300))
+        assert ex < 1e-5 and eh < 1e-5, (ex, eh)
+        # translation invariance of the adjoint (the symmetric update adds
+        # opposite forces to the two particles of a pair)
+        tot = np.abs(gp.astype(np.float64).sum(0))
+        assert np.all(tot < 1e-5 * gref["gx_abs"].sum(0))
+    finally:
+        for sw in ("density", "adjoint"):
+            ctx.set_param("sym_self", 0, sw)
+            ctx.set_param("group", 0, sw)
+            ctx.set_param("chunk", 256, sw)
+            ctx.set_param("tail_parts", 2, sw)
+
+
+@pytest.mark.parametrize("hmode", ["lognormal", "const"])
+def test_symmetric_own_cell_uniform_and_mixed_masses(ctx, hmode):
+    """Uniform sets (one cell per item) with the symmetric own cell: exact
+    counts and oracle parity; with mixed masses the density keeps the
+    gathered own cell and still matches."""
+    s = uniform_set(60000, 91, hmode=hmode)
+    ref = oracle_for(s).density()
+    ctx.set_param("sym_self", 1, "density")
+    try:
+        _, out = run_density(ctx, s, "sorted")
+        compare_density(out, ref, label=f"sym uniform {hmode}")
+        rng = np.random.Generator(np.random.PCG64(92))
+        s.m = (s.m * rng.uniform(0.5, 1.5, s.n)).astype(np.float32)
+        _, out = run_density(ctx, s, "sorted")
+        compare_density(out, oracle_for(s).density(), label=f"sym mixed masses {hmode}")
+    finally:
+        ctx.set_param("sym_self", 0, "density")
