@@ -14,7 +14,8 @@
 //
 //   k_box_hmax    max cut-off per box (auto grid)
 //   k_bin_local   cell of every particle, per-chunk cell counts, cut-off check
-//   k_bin_columns per cell: offsets of the chunks' shares, particle count
+//   k_bin_columns per cell: owning box, offsets of the chunks' shares, particle
+//                 count, the lists of the cells above 256 particles
 //   k_scan        exclusive scan of the counts -> cell_start; occupancy check
 //                 (k_tile_sums / k_scan / k_tile_scan when there are many cells)
 //   k_scatter     particles -> scatter-ordered staging records
@@ -78,9 +79,18 @@ constexpr int kBinThreads = 1024;
 __global__ void __launch_bounds__(kBinThreads) k_bin_local(
     const BoxDesc *__restrict__ box, const int4 *__restrict__ blocks,
     const float *__restrict__ pos, const float *__restrict__ h, int32_t *__restrict__ cellid,
-    int32_t *__restrict__ slot, int32_t *__restrict__ binm, int *__restrict__ dflags)
+    int32_t *__restrict__ slot, int32_t *__restrict__ binm, int *__restrict__ dflags,
+    int64_t ncell, int32_t *__restrict__ lists, uint32_t *__restrict__ dx_all)
 {
     __shared__ uint32_t hist[kBinSeg];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // per-build state read later: the largest occupancy (raised by the
+        // scan), the cell lists of the finish, the structure's displacement
+        // bound
+        dflags[1] = 0;
+        for (int k = 0; k < kCellLists; ++k) cell_list(lists, ncell, k)[0] = 0;
+        *dx_all = 0u;
+    }
     const int4 blk = blocks[blockIdx.x];
     const BoxDesc &B = box[blk.x];
     const int ncb = B.g[0] * B.g[1] * B.g[2];
@@ -119,30 +129,55 @@ __global__ void __launch_bounds__(kBinThreads) k_bin_local(
     if (bad) atomicOr(dflags, kErrGrid);
 }
 
-// Per cell: the chunks' counts become exclusive offsets (in place) and the
-// cell's particle count goes to count[c].  Reads and writes are coalesced
-// across the cells of a box.
-__global__ void k_bin_columns(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
-                              int64_t ncell, int32_t *__restrict__ binm, int32_t *__restrict__ count)
+// Per cell: the owning box (cell_box) and a cleared displacement bound; the
+// chunks' counts become exclusive offsets (in place) and the cell's particle
+// count goes to count[c]; a cell above 256 particles goes on the cell lists
+// of its size class.  Reads and writes are coalesced across the cells of a
+// box.
+__global__ void __launch_bounds__(256) k_bin_columns(const BoxDesc *__restrict__ box, int nbox,
+                                                     int64_t ncell, int32_t *__restrict__ binm,
+                                                     int32_t *count, int32_t *__restrict__ cell_box,
+                                                     float *__restrict__ cell_dx,
+                                                     int32_t *__restrict__ lists)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncell) return;
-    const BoxDesc &B = box[cell_box[c]];
-    const int64_t ncb = (int64_t)B.g[0] * B.g[1] * B.g[2];
-    int32_t *col = binm + B.moff + (c - B.cell_off);
-    int32_t run = 0;
-    // eight independent loads in flight per step
-    for (int j0 = 0; j0 < B.nblk; j0 += 8) {
-        int32_t v[8];
+    if (c < ncell) {
+        int lo = 0, hi = nbox - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (box[mid].cell_off <= c) lo = mid; else hi = mid - 1;
+        }
+        cell_box[c] = lo;
+        cell_dx[c] = 0.0f;
+        const BoxDesc &B = box[lo];
+        const int64_t ncb = (int64_t)B.g[0] * B.g[1] * B.g[2];
+        int32_t *col = binm + B.moff + (c - B.cell_off);
+        int32_t run = 0;
+        // eight independent loads in flight per step
+        for (int j0 = 0; j0 < B.nblk; j0 += 8) {
+            int32_t v[8];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) v[k] = j0 + k < B.nblk ? col[(j0 + k) * ncb] : 0;
+            for (int k = 0; k < 8; ++k) v[k] = j0 + k < B.nblk ? col[(j0 + k) * ncb] : 0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (j0 + k < B.nblk) col[(j0 + k) * ncb] = run;
-            run += v[k];
+            for (int k = 0; k < 8; ++k) {
+                if (j0 + k < B.nblk) col[(j0 + k) * ncb] = run;
+                run += v[k];
+            }
+        }
+        count[c] = run;
+        // the rare size classes' cell lists: the finish above 256 particles,
+        // the sorts of 257..kSortSmallMax, up to kSortLargeMax and larger
+        if (run > 256) {
+            int32_t *l = cell_list(lists, ncell, kListLarge);
+            l[1 + atomicAdd(&l[0], 1)] = (int32_t)c;
+            if (run <= PV_MAX_CELL) {
+                l = cell_list(lists, ncell,
+                              run > kSortLargeMax ? kListHuge
+                                                  : (run > kSortSmallMax ? kListBig : kListMid));
+                l[1 + atomicAdd(&l[0], 1)] = (int32_t)c;
+            }
         }
     }
-    count[c] = run;
 }
 
 // Single workgroup: exclusive scan of count[0..ncell) into start[0..ncell]
@@ -330,8 +365,7 @@ __global__ void __launch_bounds__(MAXC) k_cell_finish_small(
     const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
-    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int min_cnt,
-    int32_t *__restrict__ large)
+    uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m, int min_cnt)
 {
     __shared__ float key[MAXC];
     __shared__ int32_t okey[MAXC];
@@ -342,12 +376,7 @@ __global__ void __launch_bounds__(MAXC) k_cell_finish_small(
     const int c = blockIdx.x;
     const int s0 = start[c];
     const int cnt = start[c + 1] - s0;
-    if (cnt > MAXC) {
-        // listed for k_cell_finish_large
-        if (large && threadIdx.x == 0) large[1 + atomicAdd(&large[0], 1)] = c;
-        return;
-    }
-    if (cnt < min_cnt) return;
+    if (cnt > MAXC || cnt < min_cnt) return;   // another class (cells above 256: listed)
     if (cnt == 0) {
         if (threadIdx.x == 0) {
             cell_hmax[c] = 0u;
@@ -436,8 +465,7 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     const int32_t *__restrict__ start, const float4 *__restrict__ stage,
     float4 *__restrict__ xyzm, float *__restrict__ Hout, int32_t *__restrict__ orig,
     uint32_t *__restrict__ cell_hmax, float *__restrict__ cell_m,
-    const int32_t *__restrict__ large, int32_t *__restrict__ mid, int32_t *__restrict__ big,
-    int32_t *__restrict__ huge)
+    const int32_t *__restrict__ large)
 {
     __shared__ float key[PV_MAX_CELL];
     __shared__ uint16_t slot[PV_MAX_CELL];
@@ -445,7 +473,8 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
     __shared__ uint32_t hist[kFinishMaxBuckets];
     __shared__ uint32_t hred[kBlock / 64];
     __shared__ float2 mred[kBlock / 64];
-    // the cells listed by the 256-class finish, a grid's worth at a time
+    // the cells above 256 particles (listed by the column pass), a grid's
+    // worth at a time
     const int nlarge = large[0];
     for (int item = blockIdx.x; item < nlarge; item += gridDim.x) {
         const int c = large[1 + item];
@@ -457,11 +486,6 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
                 cell_m[c] = __builtin_nanf("");
             }
             continue;
-        }
-        // the per-cell sort's lists by size class
-        if (threadIdx.x == 0) {
-            int32_t *l = cnt > kSortLargeMax ? huge : cnt > kSortSmallMax ? big : mid;
-            l[1 + atomicAdd(&l[0], 1)] = c;
         }
         const BoxDesc &B = box[cell_box[c]];
         const int local = c - B.cell_off;
@@ -549,30 +573,6 @@ __global__ void __launch_bounds__(kBlock) k_cell_finish_large(
         reduce_cell_mass(mmin, mmax, mred, (int)(blockDim.x >> 6), cell_m + c);
         __syncthreads();   // the next cell reuses the LDS
     }
-}
-
-// Owning box of every cell; also clears the per-build state: the cells'
-// accumulated displacement bounds, the structure's largest one and the
-// largest occupancy (dflags[1]) that the binning raises.
-__global__ void k_cell_box(const BoxDesc *__restrict__ box, int nbox, int64_t ncell,
-                           int32_t *__restrict__ cell_box, float *__restrict__ cell_dx,
-                           uint32_t *__restrict__ dx_all, int *__restrict__ dflags,
-                           int32_t *__restrict__ big)
-{
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c == 0) {
-        *dx_all = 0u;
-        dflags[1] = 0;
-        for (int k = 0; k < kCellLists; ++k) cell_list(big, ncell, k)[0] = 0;
-    }
-    if (c >= ncell) return;
-    cell_dx[c] = 0.0f;
-    int lo = 0, hi = nbox - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (box[mid].cell_off <= c) lo = mid; else hi = mid - 1;
-    }
-    cell_box[c] = lo;
 }
 
 // One workgroup per cell: add each particle's displacement (input order) to
@@ -667,12 +667,11 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
                       int64_t ncell, const float *pos, const float *h, const float *mass,
                       int *dflags)
 {
-    hipLaunchKernelGGL(k_cell_box, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box, nbox,
-                       ncell, c.cell_box, c.cell_dx, c.dx_all, dflags, c.big);
     hipLaunchKernelGGL(k_bin_local, dim3((unsigned)plan.nblocks), dim3(kBinThreads), 0, st, c.box,
-                       c.bin_blocks, pos, h, c.cellid, c.slot, c.binm, dflags);
-    hipLaunchKernelGGL(k_bin_columns, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box,
-                       c.cell_box, ncell, c.binm, c.cell_start);
+                       c.bin_blocks, pos, h, c.cellid, c.slot, c.binm, dflags, ncell, c.big,
+                       c.dx_all);
+    hipLaunchKernelGGL(k_bin_columns, dim3(blocks_for(ncell, 256)), dim3(256), 0, st, c.box, nbox,
+                       ncell, c.binm, c.cell_start, c.cell_box, c.cell_dx, c.big);
     launch_scan(st, ncell, c.cell_start, c.cell_start, c.scan_tmp, dflags);
     if (n > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n, 256)), dim3(256), 0, st, c.box, nbox, n,
@@ -687,17 +686,15 @@ hipError_t launch_bin(hipStream_t st, const DevCells &c, const BinPlan &plan, in
     if (!dense)
         hipLaunchKernelGGL((k_cell_finish_small<64, 32>), dim3((unsigned)ncell), dim3(64), 0, st,
                            c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
-                           c.cell_hmax, c.cell_m, 0, (int32_t *)nullptr);
+                           c.cell_hmax, c.cell_m, 0);
     hipLaunchKernelGGL((k_cell_finish_small<256, 128>), dim3((unsigned)ncell), dim3(256), 0,
                        st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm, c.H, c.orig,
-                       c.cell_hmax, c.cell_m, dense ? 0 : 65, cell_list(c.big, ncell, kListLarge));
-    // the cells above 256 particles, listed by the 256-class finish
+                       c.cell_hmax, c.cell_m, dense ? 0 : 65);
+    // the cells above 256 particles, listed by the column pass
     hipLaunchKernelGGL(k_cell_finish_large, dim3((unsigned)std::min<int64_t>(ncell, kListWgs)),
                        dim3(kBlock), 0, st, c.box, c.cell_box, c.cell_start, c.stage, c.xyzm,
                        c.H, c.orig, c.cell_hmax, c.cell_m,
-                       (const int32_t *)cell_list(c.big, ncell, kListLarge),
-                       cell_list(c.big, ncell, kListMid), cell_list(c.big, ncell, kListBig),
-                       cell_list(c.big, ncell, kListHuge));
+                       (const int32_t *)cell_list(c.big, ncell, kListLarge));
     return hipGetLastError();
 }
 

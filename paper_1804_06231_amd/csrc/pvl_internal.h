@@ -122,10 +122,10 @@ constexpr int kSortSmallMax = 512;
 // Largest cell of the large-cell sort's smaller LDS class.
 constexpr int kSortLargeMax = 4096;
 
-// Cell lists made during a build, each a count followed by cell indices with
-// room for every cell: the cells above 256 particles (by the 256-class cell
-// finish), then of those the cells of 257..kSortSmallMax, of
-// kSortSmallMax+1..kSortLargeMax and larger ones (by the large-cell finish).
+// Cell lists made during a build (by the binning's column pass), each a count
+// followed by cell indices with room for every cell: the cells above 256
+// particles, then of those the cells of 257..kSortSmallMax, of
+// kSortSmallMax+1..kSortLargeMax and larger ones up to PV_MAX_CELL.
 // The kernels that take a list run a fixed grid of at most kListWgs
 // workgroups over it.
 constexpr int kListLarge = 0, kListMid = 1, kListBig = 2, kListHuge = 3, kCellLists = 4;
