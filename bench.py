@@ -48,13 +48,17 @@ OPS_PER_INTERACTION = 25
 # sorts read positions (12) and write 13 two-byte index lists (26); the sweep
 # reads positions, cut-offs and the lists and writes the 4 outputs (66).
 HBM_BYTES = {"bin": 16, "scatter": 48, "sort13": 38, "sweep": 66}
+# the timed density sweep's name in a kernel trace (the census launch, which
+# also counts pair slots, is an instantiation of its own)
+SWEEP_KERNEL = "pvl::k_sweep_queue<0, false, false>"
 # the kernels of each stage in a kernel trace (name prefixes)
 STAGE_KERNELS = {
     "bin": ("pvl::k_bin_local", "pvl::k_bin_columns", "pvl::k_scan", "pvl::k_tile_sums",
             "pvl::k_tile_scan", "pvl::k_cell_box"),
     "scatter": ("pvl::k_scatter", "pvl::k_cell_finish"),
     "sort13": ("pvl::k_sort13",),
-    "sweep": ("pvl::k_sweep_queue<0>", "pvl::k_tail_combine<0>", "pvl::k_queue_items"),
+    "sweep": ("pvl::k_sweep_queue<0, false, false>", "pvl::k_tail_combine<0>",
+              "pvl::k_queue_items"),
 }
 
 
@@ -239,7 +243,7 @@ def main():
         print("[bench] timing the fp64 CPU oracle on a sample", file=sys.stderr, flush=True)
         cpu = _cpu_baseline(s, a.cpu_seconds)
 
-    traffic = _traffic(a.workload, "pvl::k_sweep_queue<0>")
+    traffic = _traffic(a.workload, SWEEP_KERNEL)
     stage_ms = {"build_cells": ms_build, "sort_cells": ms_sort, "density_sweep": ms_sweep}
     rec = {
         "metric": "density pair-interactions/s + ns/particle, sorted-pair vs cell-list, 1 GPU",
@@ -293,7 +297,7 @@ def _roofline(workload, n, alg_ops, cand, inr, slots, ms_sweep, traffic):
     (exact-bound candidates and pairs in range) per launch over the launch's
     time, measured live on the library's stream."""
     achieved = alg_ops / (ms_sweep * 1e-3) / 1e12
-    return {"kernel": "k_sweep_queue<0> (sorted-pair density sweep)", "bound": "alu",
+    return {"kernel": f"{SWEEP_KERNEL} (sorted-pair density sweep)", "bound": "alu",
             "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
             "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic,
             "work": f"{OPS_PER_CANDIDATE} lane-ops per candidate of the exact per-receiver "
@@ -487,7 +491,7 @@ def bench_batched(a, b, torch, pvl, t0):
         "grid_autotune": grid_tune,
         "wall_ms_per_step": wall_graph,
         "roofline": _roofline(b.name, n, alg_ops, cand, inr, slots, ms_sweep,
-                              _traffic(b.name, "pvl::k_sweep_queue<0>")),
+                              _traffic(b.name, SWEEP_KERNEL)),
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec))

@@ -1326,7 +1326,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     }
 }
 
-template <int MODE, bool SYM = false>
+// CENSUS only names the launch that counts pair slots (A.slots set), so that
+// a kernel trace keeps it apart from the timed launches.
+template <int MODE, bool SYM = false, bool CENSUS = false>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(MODE == kModePlain ? 5 : 4, 8))) k_sweep_queue(SweepArgs A)
 {
@@ -1540,8 +1542,14 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.reach_order = tune.reach_order;
     A.task_sort = tune.task_sort;
     A.chunk = tune.chunk;
-    if (mode == kModePlain)
+    if (mode == kModePlain && A.slots)
+        hipLaunchKernelGGL((k_sweep_queue<kModePlain, false, true>), dim3((unsigned)grid),
+                           dim3(kBlock), 0, st, A);
+    else if (mode == kModePlain)
         hipLaunchKernelGGL(k_sweep_queue<kModePlain>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    else if (mode == kModeSorted && A.slots && !tune.sym_self)
+        hipLaunchKernelGGL((k_sweep_queue<kModeSorted, false, true>), dim3((unsigned)grid),
+                           dim3(kBlock), 0, st, A);
     else if (mode == kModeAdjoint && tune.sym_self)
         hipLaunchKernelGGL((k_sweep_queue<kModeAdjoint, true>), dim3((unsigned)grid), dim3(kBlock), 0,
                            st, A);
