@@ -74,7 +74,7 @@ def _args():
                          "density launches would mix into a profile of the sweep)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default sweep parameters instead of the autotuned ones")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="target CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="also run one device copy of this many MiB (a reference kernel "

@@ -380,6 +380,14 @@ __device__ __forceinline__ void lj_interact(float dx, float dy, float dz, float 
         if (r2 < H2) tile_interact_unit(r2, invH2, uacc);                 \
     }
 
+// Neighbour count (bits 0-15), sorted list's axis (16-19), direction sign
+// (bit 20: -1) and own cell (bit 21) of a (cell, direction) entry.
+__device__ __forceinline__ int pack_geo(int nb, int s, int sign, bool own)
+{
+    return nb | (s << 16) | ((sign < 0) << 20) | ((int)own << 21);
+}
+static_assert(PV_MAX_CELL < 65536, "neighbour counts fit 16 bits");
+
 // Task word: bits 0-9 source tiles, 10-14 receiver block, 15-22 the item's
 // cell and direction (27 g + d: d 0..25 neighbour, 26 = own cell), 23-31
 // first source tile.  A cell has at most PV_MAX_CELL / 16 tiles.
@@ -475,8 +483,15 @@ struct SweepLds {
     int act_cell[26 * G];
     int task_off[27 * G + 1];
     int recv_off[26 * G];
-    // first slot and particles of each (cell, direction)'s neighbour
-    int nb_start[26 * G], nb_cnt[26 * G];
+    // per (cell g, direction d), entry 27 g + d (d = 26: the own cell), as
+    // the set-up finds them: the pair frame's shifts (geo_r: the receiver's,
+    // for +1 offsets; geo_u: the source's, for -1 offsets; one of the two is
+    // zero on each axis and their sum is the neighbour's origin less the
+    // cell's), the neighbour's first slot (geo_r.w) and cell (geo_u.w, both
+    // as integer bits), and its particle count with the sorted list's axis
+    // and direction sign (nb_pk, see pack_geo)
+    float4 geo_r[27 * G], geo_u[27 * G];
+    int nb_pk[27 * G];
     // per cell of the item: first particle, count, largest cut-off,
     // displacement bound
     int gsa[G], gna[G];
@@ -601,6 +616,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         const float dxc = A.cell_dx[c];
         L.gsa[tid] = s0;
         L.gna[tid] = A.start[c + 1] - s0;
+        L.geo_r[27 * tid + 26] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(s0));
+        L.geo_u[27 * tid + 26] = make_float4(0.0f, 0.0f, 0.0f, __int_as_float(c));
+        L.nb_pk[27 * tid + 26] = pack_geo(A.start[c + 1] - s0, kSelfAxis, 1, true);
         L.ghmax[tid] = hm;
         L.gdx[tid] = dxc;
         // Section 2: sorted lists stay usable after the particles move, with
@@ -626,15 +644,18 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         float sx, sy, sz;
         int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
         int sb = A.start[b], nb = A.start[b + 1] - sb;
-        L.nb_start[tid] = sb;
-        L.nb_cnt[tid] = nb;
+        int sign;
+        const int s = dir_canon(dx, dy, dz, &sign);
+        L.geo_r[tid + g] = make_float4(dx > 0 ? sx : 0.0f, dy > 0 ? sy : 0.0f, dz > 0 ? sz : 0.0f,
+                                       __int_as_float(sb));
+        L.geo_u[tid + g] = make_float4(dx < 0 ? sx : 0.0f, dy < 0 ? sy : 0.0f, dz < 0 ? sz : 0.0f,
+                                       __int_as_float(b));
+        L.nb_pk[tid + g] = pack_geo(nb, s, sign, false);
         if (!ADJ && !LJ) mb = A.cell_m[b];
         int act = 0;
         if (PLAIN) {
             act = nb > 0 ? na : 0;
         } else if (nb > 0 && na > 0) {
-            int sign;
-            int s = dir_canon(dx, dy, dz, &sign);
             float e[3];
             dir_axis(s, e);
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
@@ -845,14 +866,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         const float hmax_a = L.ghmax[g], dx_a = L.gdx[g];
         int nt, t0 = 0;
         if (PLAIN) {
-            int nb = na;
-            if (dir < 26) {
-                int dx, dy, dz;
-                nb_offset(dir, dx, dy, dz);
-                float sx, sy, sz;
-                int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
-                nb = A.start[b + 1] - A.start[b];
-            }
+            const int nb = L.nb_pk[gd] & 0xffff;
             nt = (nb + 15) >> 4;
         } else if (dir == 26) {
             // two-sided window in x over the whole cell: |x_j - x_i| < H_i.
@@ -878,13 +892,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 nt = prefix_count<0>(first_x, ntile_a, hi_k) - t0;
             }
         } else {
-            int dx, dy, dz;
-            nb_offset(dir, dx, dy, dz);
-            float sx, sy, sz;
-            int b = neighbour(B, geom_of(g), dx, dy, dz, sx, sy, sz);
-            const int sb = L.nb_start[26 * g + dir], nb = L.nb_cnt[26 * g + dir];
-            int sign;
-            int s = dir_canon(dx, dy, dz, &sign);
+            const float4 gr = L.geo_r[gd], gu = L.geo_u[gd];
+            const int pk = L.nb_pk[gd];
+            const int sb = __float_as_int(gr.w), b = __float_as_int(gu.w), nb = pk & 0xffff;
+            const int s = (pk >> 16) & 15, sign = (pk >> 20) & 1 ? -1 : 1;
+            // the neighbour's origin less the cell's (one term is zero)
+            const float sx = gr.x + gu.x, sy = gr.y + gu.y, sz = gr.z + gu.z;
             float e[3];
             dir_axis(s, e);
             float se = fmaf(sx, e[0], fmaf(sy, e[1], sz * e[2]));
@@ -1020,23 +1033,14 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         ok = k != 0xffff;
         return ok ? L.tasks[k] : 0u;
     };
-    // neighbour geometry of (cell g, direction dir): first slot, count, shift
-    // into the frame of cell g, axis and sign
-    auto task_geom = [&](int g, int dir, int &sb, int &nb, int &s, int &sign, int &dx, int &dy,
-                         int &dz, float &shx, float &shy, float &shz) {
-        dx = dy = dz = 0;
-        shx = shy = shz = 0.0f;
-        sb = L.gsa[g];
-        nb = L.gna[g];
-        sign = 1;
-        s = kSelfAxis;
-        if (dir < 26) {
-            nb_offset(dir, dx, dy, dz);
-            (void)neighbour(B, geom_of(g), dx, dy, dz, shx, shy, shz);
-            sb = L.nb_start[26 * g + dir];
-            nb = L.nb_cnt[26 * g + dir];
-            s = dir_canon(dx, dy, dz, &sign);
-        }
+    // the sources of entry gd = 27 g + dir: first slot, count, sorted list's
+    // axis and sign
+    auto task_src = [&](int gd, int &sb, int &nb, int &s, int &sign) {
+        sb = __float_as_int(L.geo_r[gd].w);
+        const int pk = L.nb_pk[gd];
+        nb = pk & 0xffff;
+        s = (pk >> 16) & 15;
+        sign = (pk >> 20) & 1 ? -1 : 1;
     };
 
     // the cursor: the (group, tile) position two tiles ahead of the
@@ -1068,9 +1072,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             const int blk = (int)((tw >> 10) & 31u);
             const int gd = (int)((tw >> 15) & 255u);
             const int g = gd / 27, dir = gd - 27 * g;
-            int dx, dy, dz;
-            float shx, shy, shz;
-            task_geom(g, dir, c_sb, c_nb, c_s, c_sign, dx, dy, dz, shx, shy, shz);
+            task_src(gd, c_sb, c_nb, c_s, c_sign);
             c_nt = nt;
             c_t0 = (int)(tw >> 23);
             c_direct = PLAIN || dir == 26;
@@ -1169,9 +1171,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             const int blk = (int)((tw >> 10) & 31u);
             const int gd = (int)((tw >> 15) & 255u);
             const int g = gd / 27, dir = gd - 27 * g;
-            int sb, nb, s, sign, dx, dy, dz;
-            float shx, shy, shz;
-            task_geom(g, dir, sb, nb, s, sign, dx, dy, dz, shx, shy, shz);
+            const float4 gr = L.geo_r[gd], gu = L.geo_u[gd];
             recv_ok = e1_rok;
             ai = e1_pr - base;
             const float4 pi = recv_ok ? e1_r : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1180,12 +1180,13 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             invH = recv_ok ? 1.0f / Hi : 0.0f;
             invH2 = invH * invH;
             // pair frame: receiver moved for +1 offsets, source for -1 offsets
-            tx = dx > 0 ? pi.x - shx : pi.x;
-            ty = dy > 0 ? pi.y - shy : pi.y;
-            tz = dz > 0 ? pi.z - shz : pi.z;
-            ux = dx < 0 ? shx : 0.0f;
-            uy = dy < 0 ? shy : 0.0f;
-            uz = dz < 0 ? shz : 0.0f;
+            // (x - 0 is x: the unshifted side keeps its bits)
+            tx = pi.x - gr.x;
+            ty = pi.y - gr.y;
+            tz = pi.z - gr.z;
+            ux = gu.x;
+            uy = gu.y;
+            uz = gu.z;
             // the own cell's diagonal tile pairs each receiver with itself at K = 0
             diag = dir == 26 ? (r_lo >> 4) + blk : -1;
             it = 0;
