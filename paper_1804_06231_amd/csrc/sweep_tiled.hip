@@ -1046,13 +1046,15 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     // the cursor: the (group, tile) position two tiles ahead of the
     // computation, with what its source indices need
     int cq = 0, ci = 0, cmax = 0;
+    uint32_t c_tw = 0;   // the row's task word at the cursor's group (0: none)
     bool cvalid = false;
     int c_nt = 0, c_t0 = 0, c_sb = 0, c_nb = 0, c_s = 0, c_sign = 1;
     bool c_direct = true;
     // index stage (two tiles ahead, at the cursor): source index; at a group
     // start the receiver's rank, loaded by cursor_enter
     bool e2_valid = false, e2_start = false, e2_rok = false;
-    int e2_src = -1, e2_sb = 0, e2_ria = 0, e2_sa = 0, e2_q = 0;
+    int e2_src = -1, e2_sb = 0, e2_ria = 0, e2_sa = 0, e2_m = 0;
+    uint32_t e2_tw = 0;
     // first group at or after q with a source tile on any row (groups
     // without one add nothing); issues the load of the row's receiver rank
     // straight into the index stage
@@ -1088,6 +1090,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             cq = q;
             ci = 0;
             cmax = m;
+            c_tw = ok ? tw : 0u;
             cvalid = true;
             return;
         }
@@ -1099,19 +1102,22 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     auto stage_index = [&]() {
         e2_valid = cvalid;
         e2_start = cvalid && ci == 0;
-        e2_q = cq;
+        e2_tw = c_tw;
+        e2_m = cmax;
         e2_src = cvalid ? src_index(c_nt, c_t0, c_sb, c_nb, c_s, c_sign, c_direct, ci) : -1;
         e2_sb = c_sb;
     };
     // data stage (one tile ahead): source data; at a group start the receiver
     bool e1_valid = false, e1_start = false, e1_rok = false;
-    int e1_pr = 0, e1_q = 0;
+    int e1_pr = 0, e1_m = 0;
+    uint32_t e1_tw = 0;
     float4 e1_s = make_float4(1e30f, 1e30f, 1e30f, 0.f), e1_r = e1_s;
     float e1_sh = 0.0f, e1_sg = 0.0f, e1_rh = 0.0f, e1_rg = 0.0f;
     auto stage_data = [&]() {
         e1_valid = e2_valid;
         e1_start = e2_start;
-        e1_q = e2_q;
+        e1_tw = e2_tw;
+        e1_m = e2_m;
         e1_s = make_float4(1e30f, 1e30f, 1e30f, 0.f);
         e1_sh = e1_sg = 0.0f;
         if (e2_src >= 0) {
@@ -1161,12 +1167,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         const float4 q = e1_s;
         const float qh = e1_sh, qg = e1_sg;
         if (e1_start) {
-            // a new group: this row's task, receiver and pair frame
-            bool ok;
-            const uint32_t tw = task_word(e1_q, ok);
-            nt = ok ? task_tiles(tw) : 0;
-            ntmax = max(nt, __shfl_xor(nt, 16));
-            ntmax = max(ntmax, __shfl_xor(ntmax, 32));
+            // a new group: this row's task (carried from the cursor: a row
+            // without one has word 0, no tiles, direction 0), receiver and
+            // pair frame
+            const uint32_t tw = e1_tw;
+            nt = task_tiles(tw);
+            ntmax = e1_m;
             t0 = (int)(tw >> 23);
             const int blk = (int)((tw >> 10) & 31u);
             const int gd = (int)((tw >> 15) & 255u);
@@ -1199,7 +1205,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 tz += 1e30f;
             }
             // groups of symmetric own-cell tasks hold nothing else
-            symg = symitem && __ballot(ok && dir == 26) != 0;
+            symg = symitem && __ballot(dir == 26) != 0;
             cell_off = L.gsa[g] - base;
             cell_n = L.gna[g];
             if constexpr (ADJ) {
