@@ -8,6 +8,8 @@ not built, loading fails with an error -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes as C
+import json
+import math
 import os
 from typing import Optional, Sequence
 
@@ -386,17 +388,33 @@ class Context:
     def params(self, sweep: str = "density") -> dict:
         return {k: self.get_param(k, sweep) for k in PARAMS}
 
-    def autotune(self, cells: Cells, target: str = "density", grad_rho=None, reps: int = 3):
+    def autotune(self, cells: Cells, target: str = "density", grad_rho=None, reps: int = 3,
+                 cache: Optional["TuneCache"] = None):
         """Pick the fastest parameters of one sweep ("density", "adjoint" or
         "plain") for these cells (pv_autotune).  Returns (ms before, ms after,
-        chosen parameters)."""
+        chosen parameters).  With a cache, parameters already tuned for the
+        same device architecture and size class (see tune_key) are applied
+        without timing (both times are then NaN), and new results are stored."""
         if target == "adjoint":
             _dev_f32(grad_rho, cells.n, 0, "grad_rho", self.device)
+        key = None
+        if cache is not None:
+            info = cells.info()
+            arch = torch.cuda.get_device_properties(self.device).gcnArchName
+            key = tune_key(arch, target, info["n"], info["ncell"], info["nbox"])
+            hit = cache.get(key)
+            if hit is not None:
+                for name, v in hit.items():
+                    self.set_param(name, v, target)
+                return float("nan"), float("nan"), self.params(target)
         t = (C.c_float * 2)()
         self._sync_stream()
         self._call("pv_autotune", cells.handle, TUNE_TARGETS[target],
                    _ptr(grad_rho) if target == "adjoint" else None, int(reps), t)
-        return float(t[0]), float(t[1]), self.params(target)
+        chosen = self.params(target)
+        if cache is not None:
+            cache.put(key, chosen)
+        return float(t[0]), float(t[1]), chosen
 
     def set_census(self, on: bool) -> None:
         self._call("pv_set_census", 1 if on else 0)
@@ -409,6 +427,42 @@ class Context:
         self._sync_stream()
         self._call("pv_census", v)
         return int(v[0]), int(v[1]), int(v[2])
+
+
+def tune_key(arch: str, target: str, n: int, ncell: int, nbox: int) -> str:
+    """Size class of a tuned sweep: the device architecture, the sweep, the
+    particle count and the particles per cell, each to the nearest power of
+    two (the tuned settings follow the work per item and the items per
+    workgroup), and whether the structure holds one box or several."""
+    def p2(x: float) -> int:
+        return int(round(math.log2(x))) if x > 0 else -1
+    return f"{arch}|{target}|n{p2(n)}|ppc{p2(n / max(ncell, 1))}|{'one' if nbox == 1 else 'many'}"
+
+
+class TuneCache:
+    """Tuned sweep parameters kept in a JSON file across processes, keyed by
+    tune_key.  Entries hold the parameter names of PARAMS and their values;
+    the file is rewritten whole on every store."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self._data = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                self._data = json.load(f)
+
+    def get(self, key: str):
+        v = self._data.get(key)
+        if v is None or set(v) - set(PARAMS):
+            return None
+        return {k: int(x) for k, x in v.items()}
+
+    def put(self, key: str, params: dict) -> None:
+        self._data[key] = {k: int(v) for k, v in params.items() if k in PARAMS}
+        tmp = f"{self.path}.tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(self._data, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
 
 
 _contexts = {}

@@ -463,6 +463,31 @@ def test_autotune(ctx, clustered_ref):
         c2.close()
 
 
+def test_autotune_cache(ctx, clustered_ref, tmp_path):
+    """A tuned setting stored in the cache is applied by a later context
+    without timing, for the same size class."""
+    import paper_1804_06231_amd as pvl
+    from paper_1804_06231_amd.pvl import TuneCache
+    s, ref, G, gref = clustered_ref
+    path = str(tmp_path / "tune.json")
+    c1, c2 = pvl.Context(0), pvl.Context(0)
+    try:
+        pos, h, m = upload(s)
+        cells = c1.build_cells(pos, h, m, s.box)
+        c1.sort_cells(cells)
+        before, after, p1 = c1.autotune(cells, "density", reps=1, cache=TuneCache(path))
+        assert after <= before
+        cells2 = c2.build_cells(pos, h, m, s.box)
+        c2.sort_cells(cells2)
+        b2, a2, p2 = c2.autotune(cells2, "density", reps=1, cache=TuneCache(path))
+        assert np.isnan(b2) and np.isnan(a2) and p2 == p1
+        out = [t.cpu().numpy() for t in c2.density(cells2, "sorted")]
+        compare_density(out, ref, label="cached setting")
+    finally:
+        c1.close()
+        c2.close()
+
+
 @pytest.mark.parametrize("group,chunk,parts", [(0, 256, 2), (1, 256, 1), (8, 256, 4), (0, 64, 2)])
 def test_symmetric_own_cell_keeps_results(ctx, clustered_ref, group, chunk, parts):
     """The own cell by the symmetric pair update (each unordered pair tested
