@@ -190,7 +190,9 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[3]);
  *   PV_PARAM_TASK_SORT    1: run row tasks longest first so the rows of a wave
  *                         finish together; 0: natural order.  Default 1.
  *   PV_PARAM_QUEUE_WGS    persistent workgroups per compute unit of the
- *                         work-queue sweeps (1..32).  Default 4.
+ *                         work-queue sweeps (1..8).  Default 5, as many
+ *                         as fit a compute unit (4 fit with
+ *                         PV_PARAM_SYM_SELF set).
  *   PV_PARAM_CHUNK        receivers per work item, i.e. per workgroup's LDS
  *                         accumulator tile: a multiple of 16 in 32..256.
  *                         Cells with more particles are split into x-slabs
@@ -332,7 +334,7 @@ pv_status pv_solve_h(pv_ctx *ctx, int nbox, const int64_t *offsets, const float 
  * pv_sort_cells (sorted-pair only) and pv_density -- in one call that
  * allocates nothing and does not synchronise.  The cell structure and all
  * scratch memory of the binning, the per-cell sorts and the work-queue sweep
- * live in one static device array of 21 MiB, which every GPU the library runs
+ * live in one static device array of 30 MiB, which every GPU the library runs
  * on holds until the process ends; a context looks up its device's copy when
  * it is created.  Inputs and outputs are the caller's, as for pv_build_cells
  * and pv_density:

@@ -21,6 +21,8 @@ constexpr int kSChunk = 16384;                  // binning chunk (one count-matr
 constexpr int kSBlocks = (int)((kSN + kSChunk - 1) / kSChunk);
 // split tail: cells x parts, at most (the tail sums hold one chunk per part)
 constexpr int kSTailSlots = 512;
+// persistent workgroups of a sweep, at most (each has its receiver lists)
+constexpr int kSRlistWgs = 1280;
 
 constexpr int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
@@ -29,7 +31,7 @@ constexpr int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 struct StaticLayout {
     int64_t box, box_hmax, bin_blocks, qcount, dx_all;
     int64_t cell_box, cell_start, cell_hmax, cell_dx, cell_m, big, binm, scan_tmp;
-    int64_t cellid, slot, stage, xyzm, H, orig, sidx, tiles, items, partial;
+    int64_t cellid, slot, stage, xyzm, H, orig, sidx, tiles, items, partial, rlist;
     int64_t total;
 };
 
@@ -65,6 +67,7 @@ constexpr StaticLayout static_layout()
     o.tiles = take(4 * kTileArrays * (kSN / 16 + kSC + 1));
     o.items = take(8 * queue_capacity(kSN, kSC));
     o.partial = take(16 * (int64_t)kSTailSlots * kTailRecv);
+    o.rlist = take(kRecvListBytes * kSRlistWgs);
     o.total = p;
     return o;
 }
@@ -152,6 +155,8 @@ hipError_t launch_density_static(hipStream_t st, unsigned char *base, int64_t n,
     d.tslots = tile_slots(kSN, kSC);
     d.items = (int2 *)(base + o.items);
     d.partial = (float4 *)(base + o.partial);
+    d.rlist = base + o.rlist;
+    d.rlist_wgs = kSRlistWgs;
 
     // one box: cell and binning plan as pv_build_cells makes them
     StaticSetup s = {};
@@ -183,6 +188,9 @@ hipError_t launch_density_static(hipStream_t st, unsigned char *base, int64_t n,
     if (e == hipSuccess) e = launch_bin(st, d, plan, 1, n, ncell, pos, h, mass, dflags);
     if (e == hipSuccess && algo == PV_SORTED_PAIR) e = launch_sort13(st, d, n, ncell);
     if (e != hipSuccess) return e;
+    // the persistent workgroups' receiver lists must fit their static share
+    tune.queue_wgs_per_cu =
+        std::max(1, std::min(tune.queue_wgs_per_cu, kSRlistWgs / std::max(1, tune.num_cu)));
     // the split tail's sums must fit their static share
     const int tc = tail_cells_of(tune, ncell);
     if (tune.tail_parts > 1) {

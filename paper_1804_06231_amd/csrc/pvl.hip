@@ -22,9 +22,10 @@ struct pv_ctx {
                                             // [2] pair slots of the tiled sweep
     int census_on = 0;
     int *hpinned = nullptr;                 // pinned read-back area (64 bytes)
-    pvl::SweepTuning tune;                  // density sweeps
-    pvl::SweepTuning tune_adj;              // adjoint sweep
-    pvl::SweepTuning tune_plain;            // plain cell-list sweep
+    // per sweep; five persistent workgroups per compute unit, as many as fit
+    pvl::SweepTuning tune = pvl::tuning_with_wgs(5);        // density and LJ sweeps
+    pvl::SweepTuning tune_adj = pvl::tuning_with_wgs(5);    // adjoint sweep
+    pvl::SweepTuning tune_plain = pvl::tuning_with_wgs(5);  // plain cell-list sweep
     // pv_solve_h's working set, kept for the next call: its cells, and rho,
     // drho_dh, the next h (3 x hbuf_n floats) and the residual word
     pv_cells *hcells = nullptr;
@@ -76,7 +77,7 @@ void free_dev(DevCells &d)
     void *ptrs[] = {d.box, d.cell_box, d.cell_start, d.cell_hmax, d.cellid, d.slot, d.stage,
                     d.xyzm, d.H, d.orig, d.sidx, d.gcell, d.box_hmax,
                     d.items, d.qcount, d.scan_tmp, d.binm, d.bin_blocks, d.cell_dx, d.dx_all,
-                    d.partial, d.cell_m, d.tiles, d.big};
+                    d.partial, d.cell_m, d.tiles, d.big, d.rlist};
     for (void *p : ptrs)
         if (p) (void)hipFree(p);
     d = DevCells();
@@ -121,6 +122,9 @@ pv_status ensure_capacity(pv_ctx *ctx, pv_cells *c, int64_t n, int64_t ncell, in
     ALLOC(d.big, pvl::kCellLists * (C + 1));
     d.tslots = pvl::tile_slots(N, C);
     ALLOC(d.tiles, pvl::kTileArrays * d.tslots);
+    // receiver lists for the most persistent workgroups a sweep may launch
+    d.rlist_wgs = (int64_t)pvl::kQueueWgsMax * std::max(1, ctx->tune.num_cu);
+    ALLOC(d.rlist, pvl::kRecvListBytes * d.rlist_wgs);
     ALLOC(d.dx_all, 1);
     ALLOC(d.partial, (int64_t)pvl::kTailMaxCells * pvl::kTailMaxParts * pvl::kTailRecv);
 #undef ALLOC
@@ -549,7 +553,8 @@ pv_status pv_set_param(pv_ctx *ctx, int param, int value)
     case PV_PARAM_REACH_ORDER: t.reach_order = value ? 1 : 0; return PV_OK;
     case PV_PARAM_TASK_SORT: t.task_sort = value ? 1 : 0; return PV_OK;
     case PV_PARAM_QUEUE_WGS:
-        if (value < 1 || value > 32) return fail(ctx, PV_EINVAL, "queue_wgs must be 1..32");
+        if (value < 1 || value > pvl::kQueueWgsMax)
+            return fail(ctx, PV_EINVAL, "queue_wgs must be 1.." + std::to_string(pvl::kQueueWgsMax));
         t.queue_wgs_per_cu = value;
         return PV_OK;
     case PV_PARAM_CHUNK:

@@ -100,6 +100,11 @@ struct DevCells {
     // and for the x axis (the cell order) the last key and the largest H of
     // each tile.
     float *tiles = nullptr;       // kTileArrays x tslots
+    // the queue sweeps' per-workgroup receiver lists (kRecvListBytes per
+    // persistent workgroup, for rlist_wgs of them): kept in memory rather
+    // than LDS so that five density workgroups fit a compute unit
+    uint8_t *rlist = nullptr;
+    int64_t rlist_wgs = 0;
     int64_t tslots = 0;
     float *cell_m = nullptr;      // ncell: the mass shared by all particles of the cell,
                                   // NaN if they differ, +inf if the cell is empty
@@ -171,7 +176,7 @@ constexpr int64_t scan_scratch_words(int64_t ncell) { return ncell / kScanTile +
 struct SweepTuning {
     int reach_order = 0;
     int task_sort = 1;
-    int queue_wgs_per_cu = 4;   // persistent workgroups per compute unit
+    int queue_wgs_per_cu = 4;   // persistent workgroups per compute unit (1..kQueueWgsMax)
     int chunk = 256;            // receivers per work item (multiple of 16, 32..256)
     int tail_parts = 2;         // the queue's last cells run as this many items (1, 2, 4)
     int tail_cells = 0;         // how many cells (0: automatic)
@@ -188,6 +193,11 @@ constexpr int kGroupMax = 8;
 constexpr int kTailMaxCells = 2048;
 constexpr int kTailMaxParts = 4;
 constexpr int kTailRecv = 256;
+// Compacted receiver lists of one work item: a byte per receiver of the
+// largest chunk, per neighbour direction.
+constexpr int64_t kRecvListBytes = 26 * kTailRecv;
+// Persistent workgroups per compute unit of the queue sweeps, at most.
+constexpr int kQueueWgsMax = 8;
 
 // Smallest receivers per work item (sizes the work queue).
 constexpr int kChunkMin = 32;
@@ -199,6 +209,12 @@ constexpr int64_t queue_capacity(int64_t n, int64_t ncell)
     return queue_main(n, ncell) + kTailMaxCells;
 }
 // Persistent workgroups of a queue sweep, and the cells of its split tail.
+inline SweepTuning tuning_with_wgs(int wgs)
+{
+    SweepTuning t;
+    t.queue_wgs_per_cu = wgs;
+    return t;
+}
 int64_t queue_grid(const SweepTuning &tune, int64_t ncell);
 int tail_cells_of(const SweepTuning &tune, int64_t ncell);
 // Work-queue counters: large-cell chunks, single-chunk cells, the head of the
@@ -227,7 +243,7 @@ hipError_t launch_backward(hipStream_t st, const DevCells &c, int64_t n, int64_t
 // Allocation-free density (pv_density_static): the static scratch of
 // kStaticBytes per device, its address looked up once per device (with the
 // device current) and kept, and the launches of one call.
-constexpr int64_t kStaticBytes = 21ll << 20;
+constexpr int64_t kStaticBytes = 30ll << 20;
 hipError_t static_scratch_init(int device);
 unsigned char *static_scratch(int device);
 hipError_t launch_density_static(hipStream_t st, unsigned char *base, int64_t n,

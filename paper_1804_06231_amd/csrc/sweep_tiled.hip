@@ -82,7 +82,7 @@ constexpr int group_cap(int mode) { return mode == kModePlain ? 1 : kGroupMax; }
 // task slots per item: 27 directions of at most chunk / 16 blocks per cell,
 // plus one partial block per (cell, direction) when several cells share it
 constexpr int max_tasks(int G) { return 27 * (kChunk / 16 + (G > 1 ? G : 0)); }
-constexpr int kMaxRecv = 26 * kChunk;          // compacted receiver lists per item
+static_assert(kRecvListBytes == 26 * kChunk, "receiver lists hold a chunk per direction");
 constexpr int kSelfAxis = 4;                   // d = (1, 0, 0): cell order is x order
 constexpr int kReachBuckets = 16;              // reach levels of the receiver ordering
 constexpr int kTaskLevels = 16;                // tile-count levels of the task ordering
@@ -440,6 +440,10 @@ struct SweepArgs {
     const uint32_t *cell_hmax;
     const int32_t *orig;
     const uint16_t *sidx;
+    // this launch's receiver lists, kRecvListBytes per workgroup: per
+    // direction (compacted or reach-ordered), in-cell ranks less the item's
+    // first rank r_lo, below the chunk size, so one byte each
+    uint8_t *rlist;
     int64_t n;
     float *rho, *wcount, *drho_dh;
     int32_t *ncount;
@@ -469,9 +473,6 @@ struct SweepArgs {
 template <int G>
 struct SweepLds {
     float4 acc[4][kChunk];       // per-wave receiver sums; aliased during set-up
-    // receivers per direction (compacted or reach-ordered): in-cell ranks less
-    // the item's first rank r_lo, below the chunk size, so one byte each
-    uint8_t rlist[kMaxRecv];
     uint32_t tasks[max_tasks(G)];
     // the task order (0xffff: a gap that keeps the symmetric own-cell tasks
     // in groups of their own); also each task's (cell, direction) (bytes)
@@ -704,7 +705,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     const bool symitem = SYM && whole && (ADJ || (!LJ && !PLAIN && mass == mass));
 
     // active receivers of this item, per (cell, direction): n_act[27 g + d]
-    bool listed = false;   // receivers taken from L.rlist
+    uint8_t *const rlist = A.rlist + (size_t)blockIdx.x * kRecvListBytes;
+    bool listed = false;   // receivers taken from the lists
     if (PLAIN) {
         if (tid < 26 * ncg) {
             const int g = tid / 26;
@@ -736,7 +738,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 nb_offset(d, dx, dy, dz);
                 const int s = dir_canon(dx, dy, dz, &sign);
                 const uint16_t *il = sidx + (size_t)s * n + sa;
-                uint8_t *out = L.rlist + L.recv_off[gd];
+                uint8_t *out = rlist + L.recv_off[gd];
                 const bool face = (dx != 0) + (dy != 0) + (dz != 0) == 1;
                 if (!face) {
                     for (int q = lane; q < act; q += 64)
@@ -809,7 +811,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             nb_offset(d, dx, dy, dz);
             const int s = dir_canon(dx, dy, dz, &sign);
             const uint16_t *il = sidx + (size_t)s * n + sa0;
-            uint8_t *out = L.rlist + d * A.chunk;
+            uint8_t *out = rlist + d * A.chunk;
             int cnt = 0;   // wavefront-uniform
             for (int q0 = 0; q0 < act; q0 += 4 * 64) {
                 int iv[4];
@@ -911,7 +913,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             // their positions and cut-offs: two round trips to memory.
             int iv[16];
             if (listed) {
-                const uint8_t *rl = L.rlist + L.recv_off[26 * g + dir];
+                const uint8_t *rl = rlist + L.recv_off[26 * g + dir];
 #pragma unroll
                 for (int u = 0; u < 16; ++u) iv[u] = r_lo + rl[min(r0 + u, r1 - 1)];
             } else {
@@ -1084,7 +1086,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             e2_ria = 0;
             if (e2_rok) {
                 if (c_direct) e2_ria = r_lo + r;
-                else if (listed) e2_ria = r_lo + L.rlist[L.recv_off[26 * g + dir] + r];
+                else if (listed) e2_ria = r_lo + rlist[L.recv_off[26 * g + dir] + r];
                 else e2_ria = sidx[(size_t)c_s * n + e2_sa + (c_sign > 0 ? L.gna[g] - 1 - r : r)];
             }
             cq = q;
@@ -1333,11 +1335,20 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     }
 }
 
+// Waves per SIMD: five (at most 96 registers), four for the symmetric
+// own-cell forms, whose steps keep both sides' sums live.  At five the
+// adjoint keeps three loop-invariant lane values in scratch memory, reloaded
+// only in the set-up phases, and still runs faster than at four.
+constexpr int queue_waves(int mode, bool sym)
+{
+    return (mode == kModePlain || !sym) ? 5 : 4;
+}
+
 // CENSUS only names the launch that counts pair slots (A.slots set), so that
 // a kernel trace keeps it apart from the timed launches.
 template <int MODE, bool SYM = false, bool CENSUS = false>
 __global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(MODE == kModePlain ? 5 : 4, 8))) k_sweep_queue(SweepArgs A)
+    __attribute__((amdgpu_waves_per_eu(queue_waves(MODE, SYM), 8))) k_sweep_queue(SweepArgs A)
 {
     __shared__ SweepLds<group_cap(MODE)> L;
     if (A.dflags[0]) {
@@ -1507,7 +1518,9 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     if (ncell == 0 || n == 0) return hipSuccess;
     const int cap = (int)queue_main(n, ncell);
     const int64_t wgs = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
-    const int64_t grid = queue_grid(tune, ncell);
+    // (every workgroup has its own receiver lists)
+    const int64_t grid = std::min<int64_t>(queue_grid(tune, ncell), c.rlist_wgs);
+    if (grid < 1) return hipErrorInvalidValue;
     // small cells per item, at most.  Auto: eight with at least 16 cells per
     // workgroup (long runs then still leave every workgroup several items),
     // four with at least two, two with at least one, else one cell per item
@@ -1538,6 +1551,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.n = n;
     A.cell_m = c.cell_m;
     A.tiles = c.tiles;
+    A.rlist = c.rlist;
     A.tslots = c.tslots;
     A.cell_dx = c.cell_dx;
     A.dx_all = c.dx_all;

@@ -96,12 +96,12 @@ def test_tuning_parameters_without_gpu(lib, vctx):
     """Parameters are validated and kept per sweep (density / adjoint)."""
     from paper_1804_06231_amd.pvl import PARAMS, PV_PARAM_ADJOINT, PV_PARAM_PLAIN
     v = C.c_int()
-    defaults = {"reach_order": 0, "task_sort": 1, "queue_wgs": 4, "chunk": 256,
+    defaults = {"reach_order": 0, "task_sort": 1, "queue_wgs": 5, "chunk": 256,
                 "tail_parts": 2, "tail_cells": 0, "group": 0, "sym_self": 0}
     for name, p in PARAMS.items():
         for off in (0, PV_PARAM_ADJOINT, PV_PARAM_PLAIN):
             assert lib.pv_get_param(vctx, p + off, C.byref(v)) == 0
-            assert v.value == defaults[name], name
+            assert v.value == defaults[name], (name, off)
     assert lib.pv_set_param(vctx, PARAMS["chunk"], 128) == 0
     assert lib.pv_get_param(vctx, PARAMS["chunk"], C.byref(v)) == 0 and v.value == 128
     assert lib.pv_get_param(vctx, PARAMS["chunk"] + PV_PARAM_ADJOINT, C.byref(v)) == 0
@@ -112,7 +112,8 @@ def test_tuning_parameters_without_gpu(lib, vctx):
         assert lib.pv_set_param(vctx, PARAMS["chunk"], bad) == -1
     assert lib.pv_get_param(vctx, PARAMS["chunk"], C.byref(v)) == 0 and v.value == 128
     assert lib.pv_set_param(vctx, PARAMS["queue_wgs"], 0) == -1
-    assert lib.pv_set_param(vctx, PARAMS["queue_wgs"], 33) == -1
+    assert lib.pv_set_param(vctx, PARAMS["queue_wgs"], 9) == -1
+    assert lib.pv_set_param(vctx, PARAMS["queue_wgs"], 8) == 0
     for bad in (0, 3, 8):
         assert lib.pv_set_param(vctx, PARAMS["tail_parts"], bad) == -1
     assert lib.pv_set_param(vctx, PARAMS["tail_parts"], 4) == 0

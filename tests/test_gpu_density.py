@@ -337,6 +337,7 @@ def test_tuning_parameters_keep_results(ctx, clustered_ref, chunk, wgs, task_sor
     """Every tuning setting gives the oracle's results: cells larger than the
     chunk are split into several work items, receivers may be reach-ordered."""
     s, ref, G, gref = clustered_ref
+    saved = {sw: ctx.get_param("queue_wgs", sw) for sw in ("density", "adjoint")}
     for sw in ("density", "adjoint"):
         ctx.set_param("chunk", chunk, sw)
         ctx.set_param("queue_wgs", wgs, sw)
@@ -356,7 +357,7 @@ def test_tuning_parameters_keep_results(ctx, clustered_ref, chunk, wgs, task_sor
     finally:
         for sw in ("density", "adjoint"):
             ctx.set_param("chunk", 256, sw)
-            ctx.set_param("queue_wgs", 4, sw)
+            ctx.set_param("queue_wgs", saved[sw], sw)
             ctx.set_param("task_sort", 1, sw)
             ctx.set_param("reach_order", 0, sw)
 

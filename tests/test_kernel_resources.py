@@ -29,16 +29,22 @@ def test_report_covers_the_kernels(report):
         assert k in names, k
 
 
+# The adjoint sweep at five waves per SIMD keeps three loop-invariant lane
+# values in scratch memory (reloaded only in its set-up phases), and measured
+# faster so than at four waves without; that is the one spill allowed.
+ALLOWED_SCRATCH = {"_ZN3pvl13k_sweep_queueILi2ELb0ELb0EEEvNS_9SweepArgsE": 16}
+
+
 def test_no_kernel_spills(report):
-    spills = {k: v["ScratchSize"] for k, v in _pvl(report).items() if v.get("ScratchSize", 0)}
+    spills = {k: v["ScratchSize"] for k, v in _pvl(report).items()
+              if v.get("ScratchSize", 0) > ALLOWED_SCRATCH.get(k, 0)}
     assert not spills, spills
 
 
 def test_sweep_occupancy(report):
-    # the pruned sweeps run four waves per SIMD (four persistent workgroups
-    # per compute unit), the plain comparator five
+    # five waves per SIMD (five persistent workgroups per compute unit), four
+    # for the symmetric own-cell forms
     for k, v in _pvl(report).items():
-        if "k_sweep_queueILi1E" in k:
-            assert v["Occupancy"] >= 5, (k, v)
-        elif "k_sweep_queue" in k:
-            assert v["Occupancy"] >= 4, (k, v)
+        if "k_sweep_queue" in k:
+            sym = "Lb1ELb0E" in k
+            assert v["Occupancy"] >= (4 if sym else 5), (k, v)
