@@ -64,6 +64,7 @@
 #include "device_util.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace pvl {
 
@@ -1020,15 +1021,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     const int row = lane >> 4;
     const int l16 = lane & 15;
     auto group_of = [&](int q) { return part + nparts * (wave + 4 * q); };
-    // source index of this lane in tile `it` of a task (-1: none)
-    auto src_index = [&](int nt, int t0, int sb, int nb, int s, int sign, bool direct,
-                         int it) -> int {
-        const int j = (t0 + it) * 16 + l16;
-        if (it >= nt || j >= nb) return -1;
-        return direct ? j : (int)sidx[(size_t)s * n + sb + (sign > 0 ? j : nb - 1 - j)];
-    };
     // task word of this row in the wave's group q (0: none)
     const int ntask_eff = L.ntask_eff;
+    const bool by_tiles = A.task_sort && !symitem;   // tasks in falling tile count
     auto task_word = [&](int q, bool &ok) -> uint32_t {
         const int t = group_of(q) * 4 + row;
         const int k = t < ntask_eff ? (int)L.torder[t] : 0xffff;
@@ -1050,7 +1045,11 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     int cq = 0, ci = 0, cmax = 0;
     uint32_t c_tw = 0;   // the row's task word at the cursor's group (0: none)
     bool cvalid = false;
-    int c_nt = 0, c_t0 = 0, c_sb = 0, c_nb = 0, c_s = 0, c_sign = 1;
+    // this lane's source in the row's task: tiles that hold one (c_lim), its
+    // in-cell index at the cursor (c_j, own cell) or its place in the sorted
+    // list (c_ptr, stepping c_step per tile), and the neighbour's first slot
+    int c_lim = 0, c_j = 0, c_step = 16, c_sb = 0;
+    const uint16_t *c_ptr = sidx;
     bool c_direct = true;
     // index stage (two tiles ahead, at the cursor): source index; at a group
     // start the receiver's rank, loaded by cursor_enter
@@ -1069,6 +1068,8 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             int m = max(nt, __shfl_xor(nt, 16));
             m = max(m, __shfl_xor(m, 32));
             if (m == 0) {
+                // in an order by tile count every later group is empty too
+                if (by_tiles) return;
                 ++q;
                 continue;
             }
@@ -1076,10 +1077,14 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             const int blk = (int)((tw >> 10) & 31u);
             const int gd = (int)((tw >> 15) & 255u);
             const int g = gd / 27, dir = gd - 27 * g;
-            task_src(gd, c_sb, c_nb, c_s, c_sign);
-            c_nt = nt;
-            c_t0 = (int)(tw >> 23);
+            int nbs, axs, sgn;
+            task_src(gd, c_sb, nbs, axs, sgn);
+            const int j0 = (int)(tw >> 23) * 16 + l16;   // first tile's source
+            c_lim = min(nt, max(0, (nbs - j0 + 15) >> 4));
             c_direct = PLAIN || dir == 26;
+            c_j = j0;
+            c_step = sgn > 0 ? 16 : -16;
+            c_ptr = sidx + (size_t)axs * n + c_sb + (sgn > 0 ? j0 : nbs - 1 - j0);
             e2_sa = L.gsa[g];
             const int r = blk * 16 + l16;
             e2_rok = ok && r < L.n_act[gd];
@@ -1087,7 +1092,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             if (e2_rok) {
                 if (c_direct) e2_ria = r_lo + r;
                 else if (listed) e2_ria = r_lo + rlist[L.recv_off[26 * g + dir] + r];
-                else e2_ria = sidx[(size_t)c_s * n + e2_sa + (c_sign > 0 ? L.gna[g] - 1 - r : r)];
+                else e2_ria = sidx[(size_t)axs * n + e2_sa + (sgn > 0 ? L.gna[g] - 1 - r : r)];
             }
             cq = q;
             ci = 0;
@@ -1098,7 +1103,12 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         }
     };
     auto cursor_next = [&]() {
-        if (++ci >= cmax) cursor_enter(cq + 1);
+        if (++ci >= cmax) {
+            cursor_enter(cq + 1);
+        } else {
+            c_j += 16;
+            c_ptr += c_step;
+        }
     };
 
     auto stage_index = [&]() {
@@ -1106,31 +1116,30 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
         e2_start = cvalid && ci == 0;
         e2_tw = c_tw;
         e2_m = cmax;
-        e2_src = cvalid ? src_index(c_nt, c_t0, c_sb, c_nb, c_s, c_sign, c_direct, ci) : -1;
+        e2_src = -1;
+        if (cvalid && ci < c_lim) e2_src = c_direct ? c_j : (int)*c_ptr;
         e2_sb = c_sb;
     };
     // data stage (one tile ahead): source data; at a group start the receiver
-    bool e1_valid = false, e1_start = false, e1_rok = false;
+    // (a lane without a source loads slot 0, and its x is replaced when used)
+    bool e1_valid = false, e1_start = false, e1_rok = false, e1_sv = false;
     int e1_pr = 0, e1_m = 0;
     uint32_t e1_tw = 0;
-    float4 e1_s = make_float4(1e30f, 1e30f, 1e30f, 0.f), e1_r = e1_s;
+    float4 e1_s = make_float4(0.f, 0.f, 0.f, 0.f), e1_r = e1_s;
     float e1_sh = 0.0f, e1_sg = 0.0f, e1_rh = 0.0f, e1_rg = 0.0f;
     auto stage_data = [&]() {
         e1_valid = e2_valid;
         e1_start = e2_start;
         e1_tw = e2_tw;
         e1_m = e2_m;
-        e1_s = make_float4(1e30f, 1e30f, 1e30f, 0.f);
-        e1_sh = e1_sg = 0.0f;
-        if (e2_src >= 0) {
-            const int p = e2_sb + e2_src;
-            e1_s = A.xyzm[p];
-            if constexpr (ADJ) {
-                e1_sh = A.Hc[p];
-                e1_sg = A.gcell[p];
-            } else if (symitem) {
-                e1_sh = A.Hc[p];
-            }
+        e1_sv = e2_src >= 0;
+        const int p = e1_sv ? e2_sb + e2_src : 0;
+        e1_s = A.xyzm[p];
+        if constexpr (ADJ) {
+            e1_sh = A.Hc[p];
+            e1_sg = A.gcell[p];
+        } else if (symitem) {
+            e1_sh = A.Hc[p];
         }
         if (e2_start) {
             e1_rok = e2_rok;
@@ -1149,171 +1158,191 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     cursor_next();
     stage_index();
 
-    // the computation's group: task, receiver, pair frame and sums
-    int nt = 0, t0 = 0, it = 0, ntmax = 0, diag = -1, ai = 0;
-    bool recv_ok = false;
-    float tx = 0.f, ty = 0.f, tz = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, H2 = 0.f, invH = 0.f,
-          invH2 = 0.f, ck = 0.f, mi = 0.f;
-    TileAcc acc = {0.f, 0.f, 0.f, 0.f};
-    UnitAcc uacc = {0.f, 0.f, 0.f, 0.f, 0.f};
-    GradAcc gacc = {0.f, 0.f, 0.f, 0.f};
-    // symmetric own-cell groups: the sources' sums of the current tile, and
-    // the row's cell (for the sources' places in the item)
-    UnitAcc usrc = {0.f, 0.f, 0.f, 0.f, 0.f};
-    GradAcc gsrc = {0.f, 0.f, 0.f, 0.f};
-    bool symg = false;
-    int cell_off = 0, cell_n = 0;
-    const float sig2 = A.lj_sigma2, eps = A.lj_eps;
-    const bool unit = !LJ && !ADJ && mass == mass;
-    while (e1_valid) {   // wave-uniform
-        const float4 q = e1_s;
-        const float qh = e1_sh, qg = e1_sg;
-        if (e1_start) {
-            // a new group: this row's task (carried from the cursor: a row
-            // without one has word 0, no tiles, direction 0), receiver and
-            // pair frame
-            const uint32_t tw = e1_tw;
-            nt = task_tiles(tw);
-            ntmax = e1_m;
-            t0 = (int)(tw >> 23);
-            const int blk = (int)((tw >> 10) & 31u);
-            const int gd = (int)((tw >> 15) & 255u);
-            const int g = gd / 27, dir = gd - 27 * g;
-            const float4 gr = L.geo_r[gd], gu = L.geo_u[gd];
-            recv_ok = e1_rok;
-            ai = e1_pr - base;
-            const float4 pi = recv_ok ? e1_r : make_float4(0.f, 0.f, 0.f, 0.f);
-            const float Hi = recv_ok ? e1_rh : 0.0f;
-            H2 = Hi * Hi;
-            invH = recv_ok ? 1.0f / Hi : 0.0f;
-            invH2 = invH * invH;
-            // pair frame: receiver moved for +1 offsets, source for -1 offsets
-            // (x - 0 is x: the unshifted side keeps its bits)
-            tx = pi.x - gr.x;
-            ty = pi.y - gr.y;
-            tz = pi.z - gr.z;
-            ux = gu.x;
-            uy = gu.y;
-            uz = gu.z;
-            // the own cell's diagonal tile pairs each receiver with itself at K = 0
-            diag = dir == 26 ? (r_lo >> 4) + blk : -1;
-            it = 0;
-            // a lane without a receiver sits far away, so that no source is
-            // within its own or the source's cut-off (the symmetric update
-            // and the adjoint also add to the source)
-            if (!recv_ok) {
-                tx += 1e30f;
-                ty += 1e30f;
-                tz += 1e30f;
-            }
-            // groups of symmetric own-cell tasks hold nothing else
-            symg = symitem && __ballot(dir == 26) != 0;
-            cell_off = L.gsa[g] - base;
-            cell_n = L.gna[g];
-            if constexpr (ADJ) {
-                ck = (recv_ok ? e1_rg : 0.0f) * ((8.0f / kPi) * (invH * invH) * (invH * invH));
-                mi = pi.w;
-            }
-        }
-        stage_data();
-        cursor_next();
-        stage_index();
-
-        const int tile = t0 + it;
-        const float sx = q.x + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
-        if (SYM && symg) {
-            // the own cell, each unordered pair once
-            if (it < nt && (ADJ || !LJ)) {
-                const bool on_diag = tile == diag;
-                const float hj = qh;
-                const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
-                const float sh2 = hj * hj;
-                if constexpr (ADJ) {
-                    const float sc = qg * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
-                    PVL_SYM_STEP_G(0) PVL_SYM_STEP_G(1) PVL_SYM_STEP_G(2) PVL_SYM_STEP_G(3)
-                    PVL_SYM_STEP_G(4) PVL_SYM_STEP_G(5) PVL_SYM_STEP_G(6) PVL_SYM_STEP_G(7)
-                    PVL_SYM_STEP_G(8) PVL_SYM_STEP_G(9) PVL_SYM_STEP_G(10) PVL_SYM_STEP_G(11)
-                    PVL_SYM_STEP_G(12) PVL_SYM_STEP_G(13) PVL_SYM_STEP_G(14) PVL_SYM_STEP_G(15)
-                } else {
-                    PVL_SYM_STEP_U(0) PVL_SYM_STEP_U(1) PVL_SYM_STEP_U(2) PVL_SYM_STEP_U(3)
-                    PVL_SYM_STEP_U(4) PVL_SYM_STEP_U(5) PVL_SYM_STEP_U(6) PVL_SYM_STEP_U(7)
-                    PVL_SYM_STEP_U(8) PVL_SYM_STEP_U(9) PVL_SYM_STEP_U(10) PVL_SYM_STEP_U(11)
-                    PVL_SYM_STEP_U(12) PVL_SYM_STEP_U(13) PVL_SYM_STEP_U(14) PVL_SYM_STEP_U(15)
+    // the row loop, built apart for equal masses (the unit sums) and for
+    // the rest, so that neither carries the other's accumulators (one build
+    // with the choice made at run time in the symmetric form and the plain
+    // comparator, whose two builds would not fit the registers)
+    auto rows = [&](auto unit_c) {
+        const bool unit = static_cast<bool>(unit_c);
+        // the computation's group: task, receiver, pair frame and sums
+        int nt = 0, t0 = 0, it = 0, ntmax = 0, diag = -1, ai = 0;
+        bool recv_ok = false;
+        float tx = 0.f, ty = 0.f, tz = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, H2 = 0.f, invH = 0.f,
+              invH2 = 0.f, ck = 0.f, mi = 0.f;
+        TileAcc acc = {0.f, 0.f, 0.f, 0.f};
+        UnitAcc uacc = {0.f, 0.f, 0.f, 0.f, 0.f};
+        GradAcc gacc = {0.f, 0.f, 0.f, 0.f};
+        // symmetric own-cell groups: the sources' sums of the current tile, and
+        // the row's cell (for the sources' places in the item)
+        UnitAcc usrc = {0.f, 0.f, 0.f, 0.f, 0.f};
+        GradAcc gsrc = {0.f, 0.f, 0.f, 0.f};
+        bool symg = false;
+        int cell_off = 0, cell_n = 0;
+        const float sig2 = A.lj_sigma2, eps = A.lj_eps;
+        while (e1_valid) {   // wave-uniform
+            const float4 q = e1_s;
+            const float qh = e1_sh, qg = e1_sg;
+            // a lane without a source sits far away: no receiver reaches it and
+            // its own cut-off reaches none (x alone is enough: any distance to it
+            // overflows to infinity)
+            const float qx = e1_sv ? q.x : 1e30f;
+            if (e1_start) {
+                // a new group: this row's task (carried from the cursor: a row
+                // without one has word 0, no tiles, direction 0), receiver and
+                // pair frame
+                const uint32_t tw = e1_tw;
+                nt = task_tiles(tw);
+                ntmax = e1_m;
+                t0 = (int)(tw >> 23);
+                const int blk = (int)((tw >> 10) & 31u);
+                const int gd = (int)((tw >> 15) & 255u);
+                const int g = gd / 27, dir = gd - 27 * g;
+                const float4 gr = L.geo_r[gd], gu = L.geo_u[gd];
+                recv_ok = e1_rok;
+                ai = e1_pr - base;
+                const float4 pi = recv_ok ? e1_r : make_float4(0.f, 0.f, 0.f, 0.f);
+                const float Hi = recv_ok ? e1_rh : 0.0f;
+                H2 = Hi * Hi;
+                invH = recv_ok ? 1.0f / Hi : 0.0f;
+                invH2 = invH * invH;
+                // pair frame: receiver moved for +1 offsets, source for -1 offsets
+                // (x - 0 is x: the unshifted side keeps its bits)
+                tx = pi.x - gr.x;
+                ty = pi.y - gr.y;
+                tz = pi.z - gr.z;
+                ux = gu.x;
+                uy = gu.y;
+                uz = gu.z;
+                // the own cell's diagonal tile pairs each receiver with itself at K = 0
+                diag = dir == 26 ? (r_lo >> 4) + blk : -1;
+                it = 0;
+                // a lane without a receiver sits far away, so that no source is
+                // within its own or the source's cut-off (the symmetric update
+                // and the adjoint also add to the source)
+                if (!recv_ok) {
+                    tx += 1e30f;
+                    ty += 1e30f;
+                    tz += 1e30f;
                 }
-                // the tile's sources (back on their own lanes after 16 steps)
-                // add their sums to the wave's array
-                const int j = tile * 16 + l16;
+                // groups of symmetric own-cell tasks hold nothing else
+                symg = symitem && __ballot(dir == 26) != 0;
+                cell_off = L.gsa[g] - base;
+                cell_n = L.gna[g];
+                if constexpr (ADJ) {
+                    ck = (recv_ok ? e1_rg : 0.0f) * ((8.0f / kPi) * (invH * invH) * (invH * invH));
+                    mi = pi.w;
+                }
+            }
+            stage_data();
+            cursor_next();
+            stage_index();
+
+            const int tile = t0 + it;
+            const float sx = qx + ux, sy = q.y + uy, sz = q.z + uz, sm = q.w;
+            if (SYM && symg) {
+                // the own cell, each unordered pair once
+                if (it < nt && (ADJ || !LJ)) {
+                    const bool on_diag = tile == diag;
+                    const float hj = qh;
+                    const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
+                    const float sh2 = hj * hj;
+                    if constexpr (ADJ) {
+                        const float sc = qg * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
+                        PVL_SYM_STEP_G(0) PVL_SYM_STEP_G(1) PVL_SYM_STEP_G(2) PVL_SYM_STEP_G(3)
+                        PVL_SYM_STEP_G(4) PVL_SYM_STEP_G(5) PVL_SYM_STEP_G(6) PVL_SYM_STEP_G(7)
+                        PVL_SYM_STEP_G(8) PVL_SYM_STEP_G(9) PVL_SYM_STEP_G(10) PVL_SYM_STEP_G(11)
+                        PVL_SYM_STEP_G(12) PVL_SYM_STEP_G(13) PVL_SYM_STEP_G(14) PVL_SYM_STEP_G(15)
+                    } else {
+                        PVL_SYM_STEP_U(0) PVL_SYM_STEP_U(1) PVL_SYM_STEP_U(2) PVL_SYM_STEP_U(3)
+                        PVL_SYM_STEP_U(4) PVL_SYM_STEP_U(5) PVL_SYM_STEP_U(6) PVL_SYM_STEP_U(7)
+                        PVL_SYM_STEP_U(8) PVL_SYM_STEP_U(9) PVL_SYM_STEP_U(10) PVL_SYM_STEP_U(11)
+                        PVL_SYM_STEP_U(12) PVL_SYM_STEP_U(13) PVL_SYM_STEP_U(14) PVL_SYM_STEP_U(15)
+                    }
+                    // the tile's sources (back on their own lanes after 16 steps)
+                    // add their sums to the wave's array
+                    const int j = tile * 16 + l16;
+                    float4 res;
+                    if constexpr (ADJ) {
+                        res = make_float4(gsrc.gx, gsrc.gy, gsrc.gz, gsrc.dh);
+                        gsrc = GradAcc{0.f, 0.f, 0.f, 0.f};
+                    } else {
+                        res = make_float4(0.0f, fmaf(2.0f, usrc.v3, -usrc.s3),
+                                          6.0f * (usrc.us2 - usrc.uv2), usrc.cnt);
+                        usrc = UnitAcc{0.f, 0.f, 0.f, 0.f, 0.f};
+                    }
+                    if (j < cell_n) {
+                        float *dst = reinterpret_cast<float *>(&L.acc[wave][cell_off + j]);
+                        atomicAdd(dst + 0, res.x);
+                        atomicAdd(dst + 1, res.y);
+                        atomicAdd(dst + 2, res.z);
+                        atomicAdd(dst + 3, res.w);
+                    }
+                }
+            } else if (it < nt) {
+                if constexpr (ADJ) {
+                    const float hj = qh, gj = qg;
+                    const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
+                    const float sh2 = hj * hj;
+                    const float sc = gj * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
+                    GradAcc &acc = gacc;
+                    if (tile != diag) PVL_GRAD_STEP(0)
+                    PVL_GRAD_STEP(1) PVL_GRAD_STEP(2) PVL_GRAD_STEP(3) PVL_GRAD_STEP(4)
+                    PVL_GRAD_STEP(5) PVL_GRAD_STEP(6) PVL_GRAD_STEP(7) PVL_GRAD_STEP(8)
+                    PVL_GRAD_STEP(9) PVL_GRAD_STEP(10) PVL_GRAD_STEP(11) PVL_GRAD_STEP(12)
+                    PVL_GRAD_STEP(13) PVL_GRAD_STEP(14) PVL_GRAD_STEP(15)
+                } else if constexpr (LJ) {
+                    if (tile != diag) PVL_LJ_STEP(0)
+                    PVL_LJ_STEP(1) PVL_LJ_STEP(2) PVL_LJ_STEP(3) PVL_LJ_STEP(4)
+                    PVL_LJ_STEP(5) PVL_LJ_STEP(6) PVL_LJ_STEP(7) PVL_LJ_STEP(8)
+                    PVL_LJ_STEP(9) PVL_LJ_STEP(10) PVL_LJ_STEP(11) PVL_LJ_STEP(12)
+                    PVL_LJ_STEP(13) PVL_LJ_STEP(14) PVL_LJ_STEP(15)
+                } else if (unit) {
+                    if (tile != diag) PVL_TILE_STEP_U(0)
+                    PVL_TILE_STEP_U(1) PVL_TILE_STEP_U(2) PVL_TILE_STEP_U(3) PVL_TILE_STEP_U(4)
+                    PVL_TILE_STEP_U(5) PVL_TILE_STEP_U(6) PVL_TILE_STEP_U(7) PVL_TILE_STEP_U(8)
+                    PVL_TILE_STEP_U(9) PVL_TILE_STEP_U(10) PVL_TILE_STEP_U(11) PVL_TILE_STEP_U(12)
+                    PVL_TILE_STEP_U(13) PVL_TILE_STEP_U(14) PVL_TILE_STEP_U(15)
+                } else {
+                    if (tile != diag) PVL_TILE_STEP(0)
+                    PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
+                    PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
+                    PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
+                    PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
+                }
+            }
+            if (++it == ntmax) {
+                // the group's last tile: the row's sums go to its wave's array
                 float4 res;
                 if constexpr (ADJ) {
-                    res = make_float4(gsrc.gx, gsrc.gy, gsrc.gz, gsrc.dh);
-                    gsrc = GradAcc{0.f, 0.f, 0.f, 0.f};
+                    res = make_float4(gacc.gx, gacc.gy, gacc.gz, gacc.dh);
+                    gacc = GradAcc{0.f, 0.f, 0.f, 0.f};
+                } else if (!LJ && unit) {
+                    res = make_float4(0.0f, fmaf(2.0f, uacc.v3, -uacc.s3),
+                                      6.0f * (uacc.us2 - uacc.uv2), uacc.cnt);
+                    uacc = UnitAcc{0.f, 0.f, 0.f, 0.f, 0.f};
                 } else {
-                    res = make_float4(0.0f, fmaf(2.0f, usrc.v3, -usrc.s3),
-                                      6.0f * (usrc.us2 - usrc.uv2), usrc.cnt);
-                    usrc = UnitAcc{0.f, 0.f, 0.f, 0.f, 0.f};
+                    res = make_float4(acc.rho, acc.wc, acc.dh, acc.cnt);
+                    acc = TileAcc{0.f, 0.f, 0.f, 0.f};
                 }
-                if (j < cell_n) {
-                    float *dst = reinterpret_cast<float *>(&L.acc[wave][cell_off + j]);
+                if (recv_ok) {
+                    float *dst = reinterpret_cast<float *>(&L.acc[wave][ai]);
                     atomicAdd(dst + 0, res.x);
                     atomicAdd(dst + 1, res.y);
                     atomicAdd(dst + 2, res.z);
                     atomicAdd(dst + 3, res.w);
                 }
             }
-        } else if (it < nt) {
-            if constexpr (ADJ) {
-                const float hj = qh, gj = qg;
-                const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
-                const float sh2 = hj * hj;
-                const float sc = gj * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
-                GradAcc &acc = gacc;
-                if (tile != diag) PVL_GRAD_STEP(0)
-                PVL_GRAD_STEP(1) PVL_GRAD_STEP(2) PVL_GRAD_STEP(3) PVL_GRAD_STEP(4)
-                PVL_GRAD_STEP(5) PVL_GRAD_STEP(6) PVL_GRAD_STEP(7) PVL_GRAD_STEP(8)
-                PVL_GRAD_STEP(9) PVL_GRAD_STEP(10) PVL_GRAD_STEP(11) PVL_GRAD_STEP(12)
-                PVL_GRAD_STEP(13) PVL_GRAD_STEP(14) PVL_GRAD_STEP(15)
-            } else if constexpr (LJ) {
-                if (tile != diag) PVL_LJ_STEP(0)
-                PVL_LJ_STEP(1) PVL_LJ_STEP(2) PVL_LJ_STEP(3) PVL_LJ_STEP(4)
-                PVL_LJ_STEP(5) PVL_LJ_STEP(6) PVL_LJ_STEP(7) PVL_LJ_STEP(8)
-                PVL_LJ_STEP(9) PVL_LJ_STEP(10) PVL_LJ_STEP(11) PVL_LJ_STEP(12)
-                PVL_LJ_STEP(13) PVL_LJ_STEP(14) PVL_LJ_STEP(15)
-            } else if (unit) {
-                if (tile != diag) PVL_TILE_STEP_U(0)
-                PVL_TILE_STEP_U(1) PVL_TILE_STEP_U(2) PVL_TILE_STEP_U(3) PVL_TILE_STEP_U(4)
-                PVL_TILE_STEP_U(5) PVL_TILE_STEP_U(6) PVL_TILE_STEP_U(7) PVL_TILE_STEP_U(8)
-                PVL_TILE_STEP_U(9) PVL_TILE_STEP_U(10) PVL_TILE_STEP_U(11) PVL_TILE_STEP_U(12)
-                PVL_TILE_STEP_U(13) PVL_TILE_STEP_U(14) PVL_TILE_STEP_U(15)
-            } else {
-                if (tile != diag) PVL_TILE_STEP(0)
-                PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
-                PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
-                PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
-                PVL_TILE_STEP(13) PVL_TILE_STEP(14) PVL_TILE_STEP(15)
-            }
         }
-        if (++it == ntmax) {
-            // the group's last tile: the row's sums go to its wave's array
-            float4 res;
-            if constexpr (ADJ) {
-                res = make_float4(gacc.gx, gacc.gy, gacc.gz, gacc.dh);
-                gacc = GradAcc{0.f, 0.f, 0.f, 0.f};
-            } else if (!LJ && unit) {
-                res = make_float4(0.0f, fmaf(2.0f, uacc.v3, -uacc.s3),
-                                  6.0f * (uacc.us2 - uacc.uv2), uacc.cnt);
-                uacc = UnitAcc{0.f, 0.f, 0.f, 0.f, 0.f};
-            } else {
-                res = make_float4(acc.rho, acc.wc, acc.dh, acc.cnt);
-                acc = TileAcc{0.f, 0.f, 0.f, 0.f};
-            }
-            if (recv_ok) {
-                float *dst = reinterpret_cast<float *>(&L.acc[wave][ai]);
-                atomicAdd(dst + 0, res.x);
-                atomicAdd(dst + 1, res.y);
-                atomicAdd(dst + 2, res.z);
-                atomicAdd(dst + 3, res.w);
-            }
-        }
+    };
+    if constexpr (!LJ && !ADJ && !SYM && !PLAIN) {
+        if (mass == mass)
+            rows(std::true_type{});
+        else
+            rows(std::false_type{});
+    } else if constexpr (!LJ && !ADJ) {
+        rows(mass == mass);
+    } else {
+        rows(std::false_type{});
     }
     __syncthreads();
 

@@ -29,10 +29,16 @@ def test_report_covers_the_kernels(report):
         assert k in names, k
 
 
-# The adjoint sweep at five waves per SIMD keeps three loop-invariant lane
-# values in scratch memory (reloaded only in its set-up phases), and measured
-# faster so than at four waves without; that is the one spill allowed.
-ALLOWED_SCRATCH = {"_ZN3pvl13k_sweep_queueILi2ELb0ELb0EEEvNS_9SweepArgsE": 16}
+# At five waves per SIMD the adjoint sweep and the density sweep (whose row
+# loop is built twice, for equal and for differing masses) keep a few
+# loop-invariant lane values in scratch memory, reloaded once per work item
+# outside the row loop; both measured faster so than at four waves without.
+# Those are the spills allowed.
+ALLOWED_SCRATCH = {
+    "_ZN3pvl13k_sweep_queueILi2ELb0ELb0EEEvNS_9SweepArgsE": 16,
+    "_ZN3pvl13k_sweep_queueILi0ELb0ELb0EEEvNS_9SweepArgsE": 32,
+    "_ZN3pvl13k_sweep_queueILi0ELb0ELb1EEEvNS_9SweepArgsE": 32,
+}
 
 
 def test_no_kernel_spills(report):
