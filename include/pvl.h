@@ -229,6 +229,16 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[3]);
  *                         and the density sweep where masses are equal;
  *                         0: every receiver gathers from its own cell.
  *                         Default 0.
+ *   PV_PARAM_XCD_RANGES   1: the work queue's single-chunk items are cut into
+ *                         eight ranges of consecutive cells, one per
+ *                         accelerator complex die (XCD: its own L2 cache;
+ *                         workgroups go to the dies in turn by index), and a
+ *                         workgroup takes items from its die's range first,
+ *                         then from the next ranges, so that each L2 holds
+ *                         the neighbourhood of one region; 0: one queue in
+ *                         cell order for all.  The symmetric density form
+ *                         (PV_PARAM_SYM_SELF) always takes the one queue.
+ *                         Default 0.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,
@@ -239,6 +249,7 @@ typedef enum {
     PV_PARAM_TAIL_CELLS = 6,
     PV_PARAM_GROUP = 7,
     PV_PARAM_SYM_SELF = 8,
+    PV_PARAM_XCD_RANGES = 9,
     PV_PARAM_ADJOINT = 16,
     PV_PARAM_PLAIN = 32
 } pv_param;

@@ -578,6 +578,7 @@ pv_status pv_set_param(pv_ctx *ctx, int param, int value)
         t.group = value;
         return PV_OK;
     case PV_PARAM_SYM_SELF: t.sym_self = value ? 1 : 0; return PV_OK;
+    case PV_PARAM_XCD_RANGES: t.xcd_ranges = value ? 1 : 0; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -595,6 +596,7 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value)
     case PV_PARAM_TAIL_CELLS: *value = t.tail_cells; return PV_OK;
     case PV_PARAM_GROUP: *value = t.group; return PV_OK;
     case PV_PARAM_SYM_SELF: *value = t.sym_self; return PV_OK;
+    case PV_PARAM_XCD_RANGES: *value = t.xcd_ranges; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }

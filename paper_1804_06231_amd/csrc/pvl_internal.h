@@ -182,6 +182,7 @@ struct SweepTuning {
     int tail_cells = 0;         // how many cells (0: automatic)
     int group = 0;              // small cells per work item, at most (1..8; 0: automatic)
     int sym_self = 0;           // own cells by the symmetric pair update
+    int xcd_ranges = 0;         // each XCD first takes its own eighth of the queue
     int num_cu = 256;           // compute units of the device
 };
 
@@ -218,8 +219,11 @@ inline SweepTuning tuning_with_wgs(int wgs)
 int64_t queue_grid(const SweepTuning &tune, int64_t ncell);
 int tail_cells_of(const SweepTuning &tune, int64_t ncell);
 // Work-queue counters: large-cell chunks, single-chunk cells, the head of the
-// dynamic queue, and the split tail cells.
-constexpr int kQueueCounters = 4;
+// dynamic queue, the split tail cells, then (XCD ranges) the heads of the
+// large-cell chunks, of the tail items and of the kXcds ranges of the
+// single-chunk items.
+constexpr int kXcds = 8;   // accelerator complex dies of the device
+constexpr int kQueueCounters = 6 + kXcds;
 
 hipError_t launch_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell, int algo,
                         float *rho, float *wcount, float *drho_dh, int32_t *ncount,

@@ -461,6 +461,10 @@ struct SweepArgs {
     const int2 *items;   // queue: [0, nbig) large-cell chunks, [cap - nsmall, cap) cells
     const int *qcount;   // [0] nbig, [1] nsmall
     int *head;           // items taken after the first static round
+    // XCD ranges: heads of the large-cell chunks [0], of the tail items [1]
+    // and of the kXcds ranges of the single-chunk items [2 + r]
+    int *xq;
+    int xcd_ranges;
     int cap;
     int tail_cells;      // single-chunk cells among the last tail_cells cells ...
     int tail_parts;      // ... run last, as this many items each (1: no split)
@@ -500,6 +504,7 @@ struct SweepLds {
     float ghmax[G], gdx[G];
     int mbad[4];         // per wave: a mass differs from the first cell's
     int item;
+    int qphase, qstep;   // thread 0's place in the order of the XCD ranges
     int ntask_eff;       // entries of the task order, gaps included
 };
 
@@ -1065,8 +1070,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             bool ok;
             const uint32_t tw = task_word(q, ok);
             const int nt = ok ? task_tiles(tw) : 0;
-            int m = max(nt, __shfl_xor(nt, 16));
-            m = max(m, __shfl_xor(m, 32));
+            // the longest row's tiles (a row's lanes share its task)
+            const int m = max(max(__builtin_amdgcn_readlane(nt, 0), __builtin_amdgcn_readlane(nt, 16)),
+                              max(__builtin_amdgcn_readlane(nt, 32), __builtin_amdgcn_readlane(nt, 48)));
             if (m == 0) {
                 // in an order by tile count every later group is empty too
                 if (by_tiles) return;
@@ -1200,10 +1206,13 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 const float4 gr = L.geo_r[gd], gu = L.geo_u[gd];
                 recv_ok = e1_rok;
                 ai = e1_pr - base;
-                const float4 pi = recv_ok ? e1_r : make_float4(0.f, 0.f, 0.f, 0.f);
+                // a lane without a receiver sits far away, so that no source
+                // is within its own or the source's cut-off (the symmetric
+                // update and the adjoint also add to the source)
+                const float4 pi = recv_ok ? e1_r : make_float4(1e30f, 1e30f, 1e30f, 0.f);
                 const float Hi = recv_ok ? e1_rh : 0.0f;
                 H2 = Hi * Hi;
-                invH = recv_ok ? 1.0f / Hi : 0.0f;
+                invH = recv_ok ? __builtin_amdgcn_rcpf(Hi) : 0.0f;   // v_rcp_f32, 1 ulp
                 invH2 = invH * invH;
                 // pair frame: receiver moved for +1 offsets, source for -1 offsets
                 // (x - 0 is x: the unshifted side keeps its bits)
@@ -1216,14 +1225,6 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 // the own cell's diagonal tile pairs each receiver with itself at K = 0
                 diag = dir == 26 ? (r_lo >> 4) + blk : -1;
                 it = 0;
-                // a lane without a receiver sits far away, so that no source is
-                // within its own or the source's cut-off (the symmetric update
-                // and the adjoint also add to the source)
-                if (!recv_ok) {
-                    tx += 1e30f;
-                    ty += 1e30f;
-                    tz += 1e30f;
-                }
                 // groups of symmetric own-cell tasks hold nothing else
                 symg = symitem && __ballot(dir == 26) != 0;
                 cell_off = L.gsa[g] - base;
@@ -1397,7 +1398,46 @@ __global__ void __launch_bounds__(kBlock)
     const int ntail = A.qcount[3];
     const int nwhole = nbig + nsmall;
     const int nitems = nwhole + ntail * A.tail_parts;
+    // XCD ranges: the large-cell chunks first (one queue), then the
+    // single-chunk items, cut into kXcds ranges of consecutive cells; a
+    // workgroup starts on its die's range (workgroups are dealt to the dies
+    // in turn by index) and moves on to the next ranges as they run dry, so
+    // that each die's L2 holds one region's neighbourhood; then the tail
+    // items (one queue).  Thread 0 keeps its place in this order in LDS.
+    // (The symmetric density form takes the one queue: with the ranges its
+    // registers overflow.)
+    constexpr bool XCD = !(SYM && MODE == kModeSorted);
+    auto next_xcd = [&A]() -> int {
+        const int xcd = (int)(blockIdx.x % kXcds);
+        const int nb = A.qcount[0], ns = A.qcount[1];
+        while (true) {
+            if (L.qphase == 0) {
+                const int i = atomicAdd(&A.xq[0], 1);
+                if (i < nb) return i;
+                L.qphase = 1;
+            } else if (L.qphase == 1) {
+                const int r = (xcd + L.qstep) % kXcds;
+                const int lo = (int)((int64_t)ns * r / kXcds);
+                const int hi = (int)((int64_t)ns * (r + 1) / kXcds);
+                const int i = atomicAdd(&A.xq[2 + r], 1);
+                if (lo + i < hi) return nb + lo + i;
+                if (++L.qstep == kXcds) L.qphase = 2;
+            } else {
+                const int i = atomicAdd(&A.xq[1], 1);
+                return nb + ns + i;   // past the end when the tail is done
+            }
+        }
+    };
     int item = blockIdx.x;
+    if (XCD && A.xcd_ranges) {
+        if (threadIdx.x == 0) {
+            L.qphase = 0;
+            L.qstep = 0;
+            L.item = next_xcd();
+        }
+        __syncthreads();
+        item = L.item;
+    }
     while (item < nitems) {
         if (item < nwhole) {
             const int2 w = item < nbig ? A.items[item] : A.items[A.cap - nsmall + (item - nbig)];
@@ -1409,7 +1449,8 @@ __global__ void __launch_bounds__(kBlock)
             sweep_item<MODE, SYM>(A, L, w.x, 0, j - slot * A.tail_parts, A.tail_parts, slot);
         }
         __syncthreads();
-        if (threadIdx.x == 0) L.item = (int)gridDim.x + atomicAdd(A.head, 1);
+        if (threadIdx.x == 0)
+            L.item = (XCD && A.xcd_ranges) ? next_xcd() : (int)gridDim.x + atomicAdd(A.head, 1);
         __syncthreads();
         item = L.item;
     }
@@ -1587,6 +1628,8 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.items = c.items;
     A.qcount = c.qcount;
     A.head = c.qcount + 2;
+    A.xq = c.qcount + 4;
+    A.xcd_ranges = tune.xcd_ranges;
     A.cap = cap;
     A.partial = c.partial;
     A.reach_order = tune.reach_order;

@@ -395,6 +395,42 @@ def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
             ctx.set_param("tail_cells", 0, sw)
 
 
+@pytest.mark.parametrize("parts", [1, 4])
+def test_xcd_ranges_keep_results(ctx, clustered_ref, parts):
+    """Work items taken by die ranges (large-cell chunks first, then each
+    die's range of single-chunk items, then the split tail) give results
+    bit-identical to the one queue in every sweep, and the oracle's."""
+    s, ref, G, gref = clustered_ref
+    sweeps = ("density", "plain", "adjoint")
+    g = torch.from_numpy(G).to(dev())
+    outs = {}
+    try:
+        for x in (0, 1):
+            for sw in sweeps:
+                ctx.set_param("xcd_ranges", x, sw)
+                ctx.set_param("tail_parts", parts, sw)
+            res = []
+            for algo in ("plain", "sorted"):
+                _flush(f"xcd ranges={x} parts={parts} {algo}")
+                c1, out = run_density(ctx, s, algo)
+                compare_density(out, ref, label=f"xcd {x} {algo}")
+                res.extend(out)
+            gp, gh = ctx.density_backward(c1, g)
+            ctx.check()
+            res.extend([gp.cpu().numpy(), gh.cpu().numpy()])
+            outs[x] = res
+        for a, b in zip(outs[0], outs[1]):
+            assert np.array_equal(a, b)
+        gp, gh = outs[1][-2], outs[1][-1]
+        ex = np.max(np.abs(gp - gref["gx"]) / np.maximum(gref["gx_abs"], 1e-300))
+        eh = np.max(np.abs(gh - gref["gh"]) / np.maximum(gref["gh_abs"], 1e-300))
+        assert ex < 1e-5 and eh < 1e-5, (ex, eh)
+    finally:
+        for sw in sweeps:
+            ctx.set_param("xcd_ranges", 0, sw)
+            ctx.set_param("tail_parts", 2, sw)
+
+
 @pytest.mark.parametrize("group", [1, 3, 8, 0])
 def test_cell_groups_keep_results(ctx, clustered_ref, group):
     """Runs of small cells swept as one work item (up to `group` cells of a
