@@ -239,6 +239,14 @@ pv_status pv_census(pv_ctx *ctx, int64_t counts[3]);
  *                         cell order for all.  The symmetric density form
  *                         (PV_PARAM_SYM_SELF) always takes the one queue.
  *                         Default 0.
+ *   PV_PARAM_TAIL_SPLIT   how a split tail cell (PV_PARAM_TAIL_PARTS) is
+ *                         shared: 0: every part takes every
+ *                         PV_PARAM_TAIL_PARTS-th group of the cell's row
+ *                         tasks, over all its receivers, and the shares are
+ *                         added afterwards; 1: every part takes a range of
+ *                         the cell's receivers (whole tiles of 16) and
+ *                         writes their outputs itself, doing the set-up for
+ *                         its receivers alone.  Default 0.
  * Out-of-range values return PV_EINVAL and leave the setting unchanged. */
 typedef enum {
     PV_PARAM_REACH_ORDER = 1,
@@ -250,6 +258,7 @@ typedef enum {
     PV_PARAM_GROUP = 7,
     PV_PARAM_SYM_SELF = 8,
     PV_PARAM_XCD_RANGES = 9,
+    PV_PARAM_TAIL_SPLIT = 10,
     PV_PARAM_ADJOINT = 16,
     PV_PARAM_PLAIN = 32
 } pv_param;
@@ -262,7 +271,8 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value);
  * on `cells` for every combination of the
  * parameters above (chunk 64/128/256, 1..8 workgroups per compute unit, task
  * order, receiver order), then the tail split (2 or 4 parts of the last 256,
- * 512 or 1024 cells) and then the small-cell groups (1, 2, 4 or 8 cells per
+ * 512 or 1024 cells, by task groups or by receivers) and then the
+ * small-cell groups (1, 2, 4 or 8 cells per
  * item; not for the plain sweep) on top of the best, `reps` timed runs each
  * after one warm-up, and keeps the fastest on the context.  times_ms (host, may be NULL) receives the mean
  * time of the setting in place before the call and of the chosen one.  The

@@ -579,6 +579,7 @@ pv_status pv_set_param(pv_ctx *ctx, int param, int value)
         return PV_OK;
     case PV_PARAM_SYM_SELF: t.sym_self = value ? 1 : 0; return PV_OK;
     case PV_PARAM_XCD_RANGES: t.xcd_ranges = value ? 1 : 0; return PV_OK;
+    case PV_PARAM_TAIL_SPLIT: t.tail_split = value ? 1 : 0; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -597,6 +598,7 @@ pv_status pv_get_param(pv_ctx *ctx, int param, int *value)
     case PV_PARAM_GROUP: *value = t.group; return PV_OK;
     case PV_PARAM_SYM_SELF: *value = t.sym_self; return PV_OK;
     case PV_PARAM_XCD_RANGES: *value = t.xcd_ranges; return PV_OK;
+    case PV_PARAM_TAIL_SPLIT: *value = t.tail_split; return PV_OK;
     }
     return fail(ctx, PV_EINVAL, "unknown parameter");
 }
@@ -675,19 +677,21 @@ pv_status pv_autotune(pv_ctx *ctx, const pv_cells *cells, int target, const floa
         const pvl::SweepTuning base = best;
         static const int parts[] = {2, 4};
         static const int tails[] = {256, 512, 1024};
-        for (int p : parts)
-            for (int tc : tails) {
-                if (e != hipSuccess) break;
-                pvl::SweepTuning t = base;
-                t.tail_parts = p;
-                t.tail_cells = tc;
-                float ms = 0.0f;
-                e = time_of(t, &ms);
-                if (e == hipSuccess && ms < best_ms) {
-                    best_ms = ms;
-                    best = t;
+        for (int sp = 0; sp < 2; ++sp)
+            for (int p : parts)
+                for (int tc : tails) {
+                    if (e != hipSuccess) break;
+                    pvl::SweepTuning t = base;
+                    t.tail_parts = p;
+                    t.tail_cells = tc;
+                    t.tail_split = sp;
+                    float ms = 0.0f;
+                    e = time_of(t, &ms);
+                    if (e == hipSuccess && ms < best_ms) {
+                        best_ms = ms;
+                        best = t;
+                    }
                 }
-            }
     }
     // then the small-cell groups (the plain sweep takes one cell per item)
     if (!plain) {

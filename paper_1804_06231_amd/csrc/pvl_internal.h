@@ -183,6 +183,7 @@ struct SweepTuning {
     int group = 0;              // small cells per work item, at most (1..8; 0: automatic)
     int sym_self = 0;           // own cells by the symmetric pair update
     int xcd_ranges = 0;         // each XCD first takes its own eighth of the queue
+    int tail_split = 0;         // tail parts: 0 share the task groups, 1 the receivers
     int num_cu = 256;           // compute units of the device
 };
 

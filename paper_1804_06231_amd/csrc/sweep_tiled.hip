@@ -468,6 +468,7 @@ struct SweepArgs {
     int cap;
     int tail_cells;      // single-chunk cells among the last tail_cells cells ...
     int tail_parts;      // ... run last, as this many items each (1: no split)
+    int tail_split;      // 0: the parts share the task groups; 1: the receivers
     float4 *partial;     // sums of the split items: [tail cell][part][receiver]
     int reach_order;
     int task_sort;
@@ -569,7 +570,8 @@ __device__ __forceinline__ int wave_scan(int m, int lane, V value, E emit)
     return run;
 }
 
-// One work item.  chunk >= 0: receivers [chunk * A.chunk, ...) of cell a; an
+// One work item.  chunk >= 0: receivers [chunk * csize, ...) of cell a (csize
+// a multiple of 16: A.chunk, or a tail cell's share of its receivers); an
 // item split into nparts > 1 parts (tail slot `slot`) runs every nparts-th
 // group of tasks and leaves its sums in A.partial for k_tail_combine.
 // chunk < 0: the -chunk consecutive cells a, a + 1, ... of one row of cells
@@ -578,7 +580,7 @@ __device__ __forceinline__ int wave_scan(int m, int lane, V value, E emit)
 // first receiver's position.
 template <int MODE, bool SYM>
 __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int a, int chunk,
-                           int part, int nparts, int slot)
+                           int part, int nparts, int slot, int csize)
 {
     constexpr bool PLAIN = MODE == kModePlain;
     constexpr bool ADJ = MODE == kModeAdjoint;
@@ -590,11 +592,11 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
     if (chunk < 0) chunk = 0;
     const int sa0 = A.start[a];
     const int na0 = A.start[a + 1] - sa0;
-    const int r_lo = chunk * A.chunk;
+    const int r_lo = chunk * csize;
     // the item's receivers: positions [base, base + nrt) of the cell order
     const int base = sa0 + r_lo;
-    const int nrt = ncg > 1 ? A.start[a + ncg] - sa0 : min(r_lo + A.chunk, na0) - r_lo;
-    const bool whole = na0 <= A.chunk;   // grouped cells are single-chunk
+    const int nrt = ncg > 1 ? A.start[a + ncg] - sa0 : min(r_lo + csize, na0) - r_lo;
+    const bool whole = na0 <= csize;   // grouped cells are single-chunk
     const BoxDesc &B = A.box[A.cell_box[a]];
     const CellGeom ga = cell_geom(B, a);
     const float slack = 1.52587890625e-5f * (B.edge[0] + B.edge[1] + B.edge[2]);
@@ -817,7 +819,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             nb_offset(d, dx, dy, dz);
             const int s = dir_canon(dx, dy, dz, &sign);
             const uint16_t *il = sidx + (size_t)s * n + sa0;
-            uint8_t *out = rlist + d * A.chunk;
+            uint8_t *out = rlist + d * csize;
             int cnt = 0;   // wavefront-uniform
             for (int q0 = 0; q0 < act; q0 += 4 * 64) {
                 int iv[4];
@@ -840,7 +842,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             }
             if (lane == 0) {
                 L.n_act[d] = cnt;
-                L.recv_off[d] = d * A.chunk;
+                L.recv_off[d] = d * csize;
             }
         }
     }
@@ -1439,15 +1441,33 @@ __global__ void __launch_bounds__(kBlock)
         item = L.item;
     }
     while (item < nitems) {
+        // the item's cell (or first cell), chunk, part of a split tail cell
+        // and receivers per chunk
+        int ca, ch, part = 0, nparts = 1, slot = 0, cs = A.chunk;
+        bool run = true;
         if (item < nwhole) {
             const int2 w = item < nbig ? A.items[item] : A.items[A.cap - nsmall + (item - nbig)];
-            sweep_item<MODE, SYM>(A, L, w.x, w.y, 0, 1, 0);
+            ca = w.x;
+            ch = w.y;
         } else {
             const int j = item - nwhole;
-            const int slot = j / A.tail_parts;
-            const int2 w = A.items[A.cap + slot];
-            sweep_item<MODE, SYM>(A, L, w.x, 0, j - slot * A.tail_parts, A.tail_parts, slot);
+            slot = j / A.tail_parts;
+            ca = A.items[A.cap + slot].x;
+            const int p = j - slot * A.tail_parts;
+            if (A.tail_split) {
+                // part p of the cell's receivers, in whole tiles; it writes
+                // its receivers' outputs itself
+                const int na = A.start[ca + 1] - A.start[ca];
+                cs = ((na + A.tail_parts - 1) / A.tail_parts + 15) & ~15;
+                ch = p;
+                run = p * cs < na;
+            } else {
+                ch = 0;
+                part = p;
+                nparts = A.tail_parts;
+            }
         }
+        if (run) sweep_item<MODE, SYM>(A, L, ca, ch, part, nparts, slot, cs);
         __syncthreads();
         if (threadIdx.x == 0)
             L.item = (XCD && A.xcd_ranges) ? next_xcd() : (int)gridDim.x + atomicAdd(A.head, 1);
@@ -1603,6 +1623,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     group = std::min(group, group_cap(mode));
     if (group < 1 || group > kGroupMax) return hipErrorInvalidValue;
     A.tail_parts = tune.tail_parts;
+    A.tail_split = tune.tail_split;
     A.tail_cells = tail_cells_of(tune, ncell);
     // the counters (chunks, cells, head, tail cells) start at zero
     hipError_t e = launch_zero(st, c.qcount, kQueueCounters);
@@ -1655,7 +1676,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
                            st, A);
     else
         hipLaunchKernelGGL(k_sweep_queue<kModeSorted>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
-    if (A.tail_cells > 0) {
+    if (A.tail_cells > 0 && !A.tail_split) {
         const dim3 tg((unsigned)A.tail_cells);
         if (mode == kModePlain)
             hipLaunchKernelGGL(k_tail_combine<kModePlain>, tg, dim3(kBlock), 0, st, A);

@@ -38,7 +38,7 @@ PV_STATIC_MAX_N = 131072
 PV_STATIC_MAX_CELLS = 32768
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4, "tail_parts": 5,
           "tail_cells": 6, "group": 7, "sym_self": 8,
-          "xcd_ranges": 9}
+          "xcd_ranges": 9, "tail_split": 10}
 PV_PARAM_ADJOINT = 16
 PV_PARAM_PLAIN = 32
 TUNE_TARGETS = {"density": 0, "adjoint": 1, "plain": 2}

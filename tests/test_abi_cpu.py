@@ -98,7 +98,7 @@ def test_tuning_parameters_without_gpu(lib, vctx):
     v = C.c_int()
     defaults = {"reach_order": 0, "task_sort": 1, "queue_wgs": 5, "chunk": 256,
                 "tail_parts": 2, "tail_cells": 0, "group": 0, "sym_self": 0,
-                "xcd_ranges": 0}
+                "xcd_ranges": 0, "tail_split": 0}
     for name, p in PARAMS.items():
         for off in (0, PV_PARAM_ADJOINT, PV_PARAM_PLAIN):
             assert lib.pv_get_param(vctx, p + off, C.byref(v)) == 0
@@ -128,8 +128,8 @@ def test_tuning_parameters_without_gpu(lib, vctx):
     assert lib.pv_get_param(vctx, PARAMS["group"] + PV_PARAM_ADJOINT, C.byref(v)) == 0
     assert v.value == 3
     assert lib.pv_get_param(vctx, PARAMS["group"], C.byref(v)) == 0 and v.value == 0
-    assert lib.pv_set_param(vctx, 10, 1) == -1                    # unknown
-    assert lib.pv_get_param(vctx, 10, C.byref(v)) == -1
+    assert lib.pv_set_param(vctx, 11, 1) == -1                    # unknown
+    assert lib.pv_get_param(vctx, 11, C.byref(v)) == -1
     # the autotuner validates before it needs a device
     t = (C.c_float * 2)()
     assert lib.pv_autotune(vctx, None, 0, None, 3, t) == -1

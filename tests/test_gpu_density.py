@@ -362,19 +362,22 @@ def test_tuning_parameters_keep_results(ctx, clustered_ref, chunk, wgs, task_sor
             ctx.set_param("reach_order", 0, sw)
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("parts,cells", [(1, 0), (2, 0), (4, 37), (2, 2048), (4, 0)])
-def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
-    """The queue's last cells split into parts (each a share of the cell's row
-    tasks, added in part order by a second kernel) give the oracle's results
-    in every sweep, bit-identically from run to run."""
+def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells, split):
+    """The queue's last cells split into parts (split 0: each a share of the
+    cell's row tasks, added in part order by a second kernel; split 1: each a
+    range of the cell's receivers) give the oracle's results in every sweep,
+    bit-identically from run to run."""
     s, ref, G, gref = clustered_ref
     sweeps = ("density", "plain", "adjoint")
     for sw in sweeps:
         ctx.set_param("tail_parts", parts, sw)
         ctx.set_param("tail_cells", cells, sw)
+        ctx.set_param("tail_split", split, sw)
     try:
         for algo in ("plain", "sorted"):
-            _flush(f"tail split parts={parts} cells={cells} {algo}")
+            _flush(f"tail split parts={parts} cells={cells} split={split} {algo}")
             c1, out = run_density(ctx, s, algo)
             compare_density(out, ref, label=f"tail {parts}x{cells} {algo}")
             _, out2 = run_density(ctx, s, algo, cells=c1)
@@ -393,6 +396,7 @@ def test_tail_split_keeps_results(ctx, clustered_ref, parts, cells):
         for sw in sweeps:
             ctx.set_param("tail_parts", 2, sw)
             ctx.set_param("tail_cells", 0, sw)
+            ctx.set_param("tail_split", 0, sw)
 
 
 @pytest.mark.parametrize("parts", [1, 4])
