@@ -265,6 +265,23 @@ typedef enum {
 pv_status pv_set_param(pv_ctx *ctx, int param, int value);
 pv_status pv_get_param(pv_ctx *ctx, int param, int *value);
 
+/* Kernel timing.  With enable != 0 the context records a pair of HIP events
+ * on its stream right before and after every launch of the persistent
+ * sweep kernel (the work-queue kernel of pv_density, pv_density_backward and
+ * pv_lj, without the queue set-up and the tail combine before and after
+ * it), in a ring of the last PV_KTIME_RING launches; nothing is recorded
+ * while the stream is being captured into a graph.  Enabling (again) or
+ * disabling clears the ring; the first enable creates the events.
+ * pv_kernel_times synchronises the stream and writes to ms (host, *count
+ * floats) the durations in milliseconds of the most recent launches, at
+ * most *count of them, oldest first, and sets *count to how many it wrote.
+ * For measurement (a bench's per-kernel rate); the events add a few
+ * microseconds per launch.  Errors: PV_EINVAL, PV_ESTATE (argument-checking
+ * context), PV_EHIP. */
+#define PV_KTIME_RING 64
+pv_status pv_set_kernel_timing(pv_ctx *ctx, int enable);
+pv_status pv_kernel_times(pv_ctx *ctx, float *ms, int *count);
+
 /* Autotuner.  Times the sorted-pair density sweep (PV_TUNE_DENSITY), the
  * adjoint sweep (PV_TUNE_ADJOINT, for the upstream gradient grad_rho, device,
  * n floats in original order) or the plain cell-list sweep (PV_TUNE_PLAIN)

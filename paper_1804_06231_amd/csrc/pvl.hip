@@ -32,6 +32,11 @@ struct pv_ctx {
     float *hbuf = nullptr;
     int64_t hbuf_n = 0;
     uint32_t *hres = nullptr;
+    // kernel timing (pv_set_kernel_timing): a ring of event pairs, one pair
+    // per launch of the persistent sweep kernel
+    int kt_on = 0;
+    std::vector<hipEvent_t> kt_ev;   // 2 * PV_KTIME_RING: start, stop, start, ...
+    int kt_next = 0, kt_count = 0;
 };
 
 struct pv_cells {
@@ -226,6 +231,7 @@ void pv_destroy(pv_ctx *ctx)
     if (ctx->dflags) (void)hipFree(ctx->dflags);
     if (ctx->dcensus) (void)hipFree(ctx->dcensus);
     if (ctx->hpinned) (void)hipHostFree(ctx->hpinned);
+    for (hipEvent_t ev : ctx->kt_ev) (void)hipEventDestroy(ev);
     delete ctx;
 }
 
@@ -407,6 +413,55 @@ pv_status pv_sort_cells(pv_ctx *ctx, pv_cells *cells)
     return PV_OK;
 }
 
+namespace {
+// The sweep tuning with the next event pair of the timing ring filled in
+// when kernel timing is on and the stream is not being captured.
+pvl::SweepTuning timed(pv_ctx *ctx, const pvl::SweepTuning &t)
+{
+    pvl::SweepTuning r = t;
+    if (!ctx->kt_on) return r;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(ctx->stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return r;
+    r.kt_start = ctx->kt_ev[2 * ctx->kt_next];
+    r.kt_stop = ctx->kt_ev[2 * ctx->kt_next + 1];
+    ctx->kt_next = (ctx->kt_next + 1) % PV_KTIME_RING;
+    ctx->kt_count = std::min(ctx->kt_count + 1, PV_KTIME_RING);
+    return r;
+}
+}  // namespace
+
+pv_status pv_set_kernel_timing(pv_ctx *ctx, int enable)
+{
+    if (!ctx) return PV_EINVAL;
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    if (enable && ctx->kt_ev.empty()) {
+        ctx->kt_ev.assign(2 * PV_KTIME_RING, nullptr);
+        for (hipEvent_t &ev : ctx->kt_ev) HIPCHK(ctx, hipEventCreate(&ev));
+    }
+    ctx->kt_on = enable ? 1 : 0;
+    ctx->kt_next = 0;
+    ctx->kt_count = 0;
+    return PV_OK;
+}
+
+pv_status pv_kernel_times(pv_ctx *ctx, float *ms, int *count)
+{
+    if (!ctx || !count || *count < 0 || (*count > 0 && !ms)) return PV_EINVAL;
+    if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
+    const int k = std::min(*count, ctx->kt_count);
+    *count = 0;
+    if (k == 0) return PV_OK;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int i = 0; i < k; ++i) {
+        // the k most recent pairs, oldest first
+        const int slot = ((ctx->kt_next - k + i) % PV_KTIME_RING + PV_KTIME_RING) % PV_KTIME_RING;
+        HIPCHK(ctx, hipEventElapsedTime(&ms[i], ctx->kt_ev[2 * slot], ctx->kt_ev[2 * slot + 1]));
+    }
+    *count = k;
+    return PV_OK;
+}
+
 pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rho,
                      float *wcount, float *drho_dh, int32_t *ncount)
 {
@@ -420,7 +475,7 @@ pv_status pv_density(pv_ctx *ctx, const pv_cells *cells, pv_algo algo, float *rh
     HIPCHK(ctx, pvl::launch_sweep(ctx->stream, cells->d, cells->n, cells->ncell, (int)algo, rho,
                                   wcount, drho_dh, ncount, ctx->dflags,
                                   ctx->census_on ? ctx->dcensus : nullptr,
-                                  algo == PV_PLAIN_CELL ? ctx->tune_plain : ctx->tune));
+                                  timed(ctx, algo == PV_PLAIN_CELL ? ctx->tune_plain : ctx->tune)));
     return PV_OK;
 }
 
@@ -433,7 +488,7 @@ pv_status pv_density_backward(pv_ctx *ctx, const pv_cells *cells, const float *g
     if (!cells->sorted) return fail(ctx, PV_ESTATE, "pv_sort_cells must run before the adjoint");
     if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
     HIPCHK(ctx, pvl::launch_backward(ctx->stream, cells->d, cells->n, cells->ncell, grad_rho,
-                                     grad_pos, grad_h, ctx->dflags, ctx->tune_adj));
+                                     grad_pos, grad_h, ctx->dflags, timed(ctx, ctx->tune_adj)));
     return PV_OK;
 }
 
@@ -817,7 +872,7 @@ pv_status pv_lj(pv_ctx *ctx, const pv_cells *cells, float eps, float sigma, floa
     if (!cells->sorted) return fail(ctx, PV_ESTATE, "pv_sort_cells must run before pv_lj");
     if (ctx->device < 0) return fail(ctx, PV_ESTATE, "argument-checking context has no device");
     HIPCHK(ctx, pvl::launch_lj_tiled(ctx->stream, cells->d, cells->n, cells->ncell, eps, sigma,
-                                     force, energy, ctx->dflags, ctx->tune));
+                                     force, energy, ctx->dflags, timed(ctx, ctx->tune)));
     return PV_OK;
 }
 

@@ -185,6 +185,9 @@ struct SweepTuning {
     int xcd_ranges = 0;         // each XCD first takes its own eighth of the queue
     int tail_split = 0;         // tail parts: 0 share the task groups, 1 the receivers
     int num_cu = 256;           // compute units of the device
+    // events recorded on the launch stream right before and after the
+    // persistent sweep kernel (kernel timing; both null: none)
+    hipEvent_t kt_start = nullptr, kt_stop = nullptr;
 };
 
 // Small cells per work item of the sweeps, at most.

@@ -1605,7 +1605,12 @@ int tail_cells_of(const SweepTuning &tune, int64_t ncell)
 static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell,
                                      SweepArgs A, const SweepTuning &tune, int mode)
 {
-    if (ncell == 0 || n == 0) return hipSuccess;
+    if (ncell == 0 || n == 0) {
+        // nothing to sweep: a timed launch takes no time
+        if (tune.kt_start) (void)hipEventRecord(tune.kt_start, st);
+        if (tune.kt_stop) (void)hipEventRecord(tune.kt_stop, st);
+        return hipSuccess;
+    }
     const int cap = (int)queue_main(n, ncell);
     const int64_t wgs = (int64_t)tune.queue_wgs_per_cu * tune.num_cu;
     // (every workgroup has its own receiver lists)
@@ -1656,6 +1661,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
     A.reach_order = tune.reach_order;
     A.task_sort = tune.task_sort;
     A.chunk = tune.chunk;
+    if (tune.kt_start) (void)hipEventRecord(tune.kt_start, st);
     if (mode == kModePlain && A.slots)
         hipLaunchKernelGGL((k_sweep_queue<kModePlain, false, true>), dim3((unsigned)grid),
                            dim3(kBlock), 0, st, A);
@@ -1676,6 +1682,7 @@ static hipError_t launch_queue_sweep(hipStream_t st, const DevCells &c, int64_t 
                            st, A);
     else
         hipLaunchKernelGGL(k_sweep_queue<kModeSorted>, dim3((unsigned)grid), dim3(kBlock), 0, st, A);
+    if (tune.kt_stop) (void)hipEventRecord(tune.kt_stop, st);
     if (A.tail_cells > 0 && !A.tail_split) {
         const dim3 tg((unsigned)A.tail_cells);
         if (mode == kModePlain)

@@ -32,8 +32,10 @@ EXPORTS = (
     "pv_build_cells_batched", "pv_sort_cells", "pv_density", "pv_density_backward",
     "pv_check", "pv_cells_info", "pv_cells_export", "pv_set_census", "pv_census",
     "pv_free_cells", "pv_set_param", "pv_get_param", "pv_autotune", "pv_solve_h", "pv_drift",
-    "pv_lj", "pv_autotune_grid", "pv_density_static",
+    "pv_lj", "pv_autotune_grid", "pv_density_static", "pv_set_kernel_timing",
+    "pv_kernel_times",
 )
+PV_KTIME_RING = 64
 PV_STATIC_MAX_N = 131072
 PV_STATIC_MAX_CELLS = 32768
 PARAMS = {"reach_order": 1, "task_sort": 2, "queue_wgs": 3, "chunk": 4, "tail_parts": 5,
@@ -93,6 +95,8 @@ def load_library(path: str = LIB_PATH):
         "pv_lj": ([P, P, C.c_float, C.c_float, P, P], i32),
         "pv_autotune_grid": ([P, i32, P, P, P, P, P, i32, P, P], i32),
         "pv_density_static": ([P, i64, P, P, P, P, P, i32, P, P, P, P], i32),
+        "pv_set_kernel_timing": ([P, i32], i32),
+        "pv_kernel_times": ([P, P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -327,6 +331,21 @@ class Context:
         self._sync_stream()
         self._call("pv_lj", cells.handle, float(eps), float(sigma), _ptr(f), _ptr(e))
         return f, e
+
+    def set_kernel_timing(self, enable: bool) -> None:
+        """Record HIP events around every persistent sweep kernel launch
+        (pv_set_kernel_timing); clears the record."""
+        self._sync_stream()
+        self._call("pv_set_kernel_timing", 1 if enable else 0)
+
+    def kernel_times(self, count: int = PV_KTIME_RING):
+        """Durations (ms) of the most recent timed sweep kernel launches, oldest
+        first (pv_kernel_times; synchronises the stream)."""
+        ms = (C.c_float * max(1, count))()
+        k = C.c_int(count)
+        self._sync_stream()
+        self._call("pv_kernel_times", ms, C.byref(k))
+        return [float(ms[i]) for i in range(k.value)]
 
     def drift(self, cells: Cells, disp) -> None:
         """Move the cells' particles by disp (n x 3, input order) keeping the

@@ -136,6 +136,21 @@ def test_tuning_parameters_without_gpu(lib, vctx):
     assert lib.pv_autotune(None, None, 0, None, 3, t) == -1
 
 
+def test_kernel_timing_argument_checks_without_gpu(lib, vctx):
+    """Kernel timing needs a device context; its read-back checks its
+    arguments first."""
+    n = C.c_int(4)
+    ms = (C.c_float * 4)()
+    assert lib.pv_set_kernel_timing(None, 1) == -1
+    assert lib.pv_kernel_times(None, ms, C.byref(n)) == -1
+    assert lib.pv_kernel_times(vctx, ms, None) == -1
+    assert lib.pv_kernel_times(vctx, None, C.byref(n)) == -1     # ms NULL with count > 0
+    bad = C.c_int(-1)
+    assert lib.pv_kernel_times(vctx, ms, C.byref(bad)) == -1
+    assert lib.pv_set_kernel_timing(vctx, 1) == -6                # no device (PV_ESTATE)
+    assert lib.pv_kernel_times(vctx, ms, C.byref(n)) == -6
+
+
 def test_bench_refuses_more_than_one_gpu():
     """The benchmark measures one GPU: asked for more it exits with a message
     (before touching a device)."""

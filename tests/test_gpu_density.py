@@ -504,6 +504,43 @@ def test_autotune(ctx, clustered_ref):
         c2.close()
 
 
+def test_kernel_timing(ctx, clustered_ref):
+    """The context times the persistent sweep kernel of each density call
+    with events on its stream (oldest first, at most the ring's size), leaves
+    results unchanged, records nothing once disabled, and stays out of a
+    captured graph."""
+    s, ref, G, gref = clustered_ref
+    _flush("kernel timing")
+    cells, out0 = run_density(ctx, s, "sorted")
+    outs = tuple(torch.from_numpy(x).to(dev()) for x in out0)
+    ctx.set_kernel_timing(True)
+    try:
+        for _ in range(3):
+            ctx.density(cells, "sorted", outs)
+        ts = ctx.kernel_times(8)
+        assert len(ts) == 3 and all(0.0 < t < 1000.0 for t in ts), ts
+        for x, y in zip(out0, outs):
+            assert np.array_equal(x, y.cpu().numpy())
+        assert len(ctx.kernel_times(2)) == 2
+        # a captured density call records nothing (the events stay outside)
+        torch.cuda.synchronize()
+        ctx.set_kernel_timing(True)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.density(cells, "sorted", outs)
+        torch.cuda.synchronize()
+        assert ctx.kernel_times(8) == []
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(out0, outs):
+            assert np.array_equal(x, y.cpu().numpy())
+    finally:
+        ctx.set_kernel_timing(False)
+    ctx.density(cells, "sorted", outs)
+    assert ctx.kernel_times(8) == []
+    cells.free()
+
+
 def test_autotune_cache(ctx, clustered_ref, tmp_path):
     """A tuned setting stored in the cache is applied by a later context
     without timing, for the same size class."""
