@@ -1224,8 +1224,9 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                 ux = gu.x;
                 uy = gu.y;
                 uz = gu.z;
-                // the own cell's diagonal tile pairs each receiver with itself at K = 0
-                diag = dir == 26 ? (r_lo >> 4) + blk : -1;
+                // the own cell's diagonal tile pairs each receiver with itself
+                // at K = 0: the group's tile index it of that tile (-1: none)
+                diag = dir == 26 ? (r_lo >> 4) + blk - t0 : -1;
                 it = 0;
                 // groups of symmetric own-cell tasks hold nothing else
                 symg = symitem && __ballot(dir == 26) != 0;
@@ -1245,7 +1246,7 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
             if (SYM && symg) {
                 // the own cell, each unordered pair once
                 if (it < nt && (ADJ || !LJ)) {
-                    const bool on_diag = tile == diag;
+                    const bool on_diag = it == diag;
                     const float hj = qh;
                     const float sinv = hj > 0.0f ? __builtin_amdgcn_rcpf(hj) : 0.0f;   // v_rcp_f32, 1 ulp
                     const float sh2 = hj * hj;
@@ -1288,25 +1289,25 @@ __device__ void sweep_item(const SweepArgs &A, SweepLds<group_cap(MODE)> &L, int
                     const float sh2 = hj * hj;
                     const float sc = gj * ((8.0f / kPi) * (sinv * sinv) * (sinv * sinv));
                     GradAcc &acc = gacc;
-                    if (tile != diag) PVL_GRAD_STEP(0)
+                    if (it != diag) PVL_GRAD_STEP(0)
                     PVL_GRAD_STEP(1) PVL_GRAD_STEP(2) PVL_GRAD_STEP(3) PVL_GRAD_STEP(4)
                     PVL_GRAD_STEP(5) PVL_GRAD_STEP(6) PVL_GRAD_STEP(7) PVL_GRAD_STEP(8)
                     PVL_GRAD_STEP(9) PVL_GRAD_STEP(10) PVL_GRAD_STEP(11) PVL_GRAD_STEP(12)
                     PVL_GRAD_STEP(13) PVL_GRAD_STEP(14) PVL_GRAD_STEP(15)
                 } else if constexpr (LJ) {
-                    if (tile != diag) PVL_LJ_STEP(0)
+                    if (it != diag) PVL_LJ_STEP(0)
                     PVL_LJ_STEP(1) PVL_LJ_STEP(2) PVL_LJ_STEP(3) PVL_LJ_STEP(4)
                     PVL_LJ_STEP(5) PVL_LJ_STEP(6) PVL_LJ_STEP(7) PVL_LJ_STEP(8)
                     PVL_LJ_STEP(9) PVL_LJ_STEP(10) PVL_LJ_STEP(11) PVL_LJ_STEP(12)
                     PVL_LJ_STEP(13) PVL_LJ_STEP(14) PVL_LJ_STEP(15)
                 } else if (unit) {
-                    if (tile != diag) PVL_TILE_STEP_U(0)
+                    if (it != diag) PVL_TILE_STEP_U(0)
                     PVL_TILE_STEP_U(1) PVL_TILE_STEP_U(2) PVL_TILE_STEP_U(3) PVL_TILE_STEP_U(4)
                     PVL_TILE_STEP_U(5) PVL_TILE_STEP_U(6) PVL_TILE_STEP_U(7) PVL_TILE_STEP_U(8)
                     PVL_TILE_STEP_U(9) PVL_TILE_STEP_U(10) PVL_TILE_STEP_U(11) PVL_TILE_STEP_U(12)
                     PVL_TILE_STEP_U(13) PVL_TILE_STEP_U(14) PVL_TILE_STEP_U(15)
                 } else {
-                    if (tile != diag) PVL_TILE_STEP(0)
+                    if (it != diag) PVL_TILE_STEP(0)
                     PVL_TILE_STEP(1) PVL_TILE_STEP(2) PVL_TILE_STEP(3) PVL_TILE_STEP(4)
                     PVL_TILE_STEP(5) PVL_TILE_STEP(6) PVL_TILE_STEP(7) PVL_TILE_STEP(8)
                     PVL_TILE_STEP(9) PVL_TILE_STEP(10) PVL_TILE_STEP(11) PVL_TILE_STEP(12)
