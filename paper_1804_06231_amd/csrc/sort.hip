@@ -73,6 +73,7 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
     constexpr float QMAX = (float)((1u << QB) - 1u);               // exact in fp32
     __shared__ uint32_t hist[13][NB];
     __shared__ uint32_t bword[13][MAXC];
+    __shared__ float2 axr[13];   // per axis: the cell's least key and 1 / key range
     // one cell (blockIdx.x), or LIST: the listed cells, a grid's worth at a time
     const int nitem = LIST ? list[0] : 1;
     for (int item = LIST ? (int)blockIdx.x : 0; item < nitem; item += LIST ? (int)gridDim.x : 1) {
@@ -82,6 +83,16 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
         if (cnt < min_cnt || cnt > MAXC) continue;
         const BoxDesc &B = box[cell_box[c]];
         for (int t = threadIdx.x; t < 13 * NB; t += blockDim.x) (&hist[0][0])[t] = 0u;
+        if (threadIdx.x < 13) {
+            // the cell's key range on each axis (the same for every cell of a box)
+            float e[3];
+            dir_axis((int)threadIdx.x, e);
+            const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
+                               fminf(e[2], 0.f) * B.edge[2];
+            const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
+                               fmaxf(e[2], 0.f) * B.edge[2];
+            axr[threadIdx.x] = make_float2(kmin, __builtin_amdgcn_rcpf(kmax - kmin));
+        }
         const int r = threadIdx.x;
         const bool on = r < cnt;
         const float4 p = on ? xyzm[s0 + r] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -93,15 +104,9 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
         for (int g = 0; g < 13; ++g) {
             // the key's place t in [0, 1] across the cell's key range on axis g
             if (g == kTileAxisX) continue;
-            float e[3];
-            dir_axis(g, e);
-            const float kmin = fminf(e[0], 0.f) * B.edge[0] + fminf(e[1], 0.f) * B.edge[1] +
-                               fminf(e[2], 0.f) * B.edge[2];
-            const float kmax = fmaxf(e[0], 0.f) * B.edge[0] + fmaxf(e[1], 0.f) * B.edge[1] +
-                               fmaxf(e[2], 0.f) * B.edge[2];
+            const float2 ar = axr[g];
             const float kg = proj_key(p.x, p.y, p.z, g);
-            const float t = __builtin_amdgcn_fmed3f((kg - kmin) * __builtin_amdgcn_rcpf(kmax - kmin),
-                                                    0.0f, 1.0f);
+            const float t = __builtin_amdgcn_fmed3f((kg - ar.x) * ar.y, 0.0f, 1.0f);
             w[g] = ((uint32_t)(t * QMAX) << RB) | (uint32_t)r;
             const int bb = (int)(t * (float)NB);
             b[g] = bb < NB ? bb : NB - 1;
@@ -183,14 +188,23 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
     #pragma unroll
             for (int g = 0; g < 13; ++g) {
                 const int rank = rk[g];
-                const size_t o = (size_t)g * (size_t)n + (size_t)(s0 + rank);
-                sidx[o] = (uint16_t)r;
+                // the cell's list and tile rows on this axis (uniform bases,
+                // so that each store adds only the lane's own offset)
+                uint16_t *const lg = sidx + (size_t)g * (size_t)n + s0;
+                float *const ts_g = tiles + kTileTS(g) * tslots + slot0;
+                float *const te_g = tiles + kTileTE(g) * tslots + slot0;
+                // (byte offsets as unsigned 32-bit values: a cell's rows are
+                // far below 4 GB)
+                *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(lg) + (uint32_t)(2 * rank)) =
+                    (uint16_t)r;
                 // tile summaries: the first keys of the tiles from either end
                 // (the key recomputed as before: same operations, same value)
                 const float kg = proj_key(p.x, p.y, p.z, g);
                 const int re = cnt - 1 - rank;
-                if ((rank & 15) == 0) tiles[kTileTS(g) * tslots + slot0 + (rank >> 4)] = kg;
-                if ((re & 15) == 0) tiles[kTileTE(g) * tslots + slot0 + (re >> 4)] = kg;
+                if ((rank & 15) == 0)
+                    *reinterpret_cast<float *>(reinterpret_cast<char *>(ts_g) + (uint32_t)(rank >> 2 & ~3)) = kg;
+                if ((re & 15) == 0)
+                    *reinterpret_cast<float *>(reinterpret_cast<char *>(te_g) + (uint32_t)(re >> 2 & ~3)) = kg;
                 if (g == kTileAxisX && ((rank & 15) == 15 || re == 0))
                     tiles[kTileTLX * tslots + slot0 + (rank >> 4)] = kg;
             }
