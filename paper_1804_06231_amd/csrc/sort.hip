@@ -66,7 +66,7 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
                const int32_t *__restrict__ start, const float4 *__restrict__ xyzm,
                const float *__restrict__ Hc, int64_t n, uint16_t *__restrict__ sidx,
                int64_t tslots, float *__restrict__ tiles, int min_cnt,
-               const int32_t *__restrict__ list)
+               const int32_t *__restrict__ list, int list_min)
 {
     constexpr int RB = MAXC <= 64 ? 6 : (MAXC <= 256 ? 8 : 9);   // bits of the in-cell rank
     constexpr int QB = 32 - RB < 24 ? 32 - RB : 24;                // bits of the quantised key
@@ -75,7 +75,9 @@ k_sort13_small(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell
     __shared__ uint32_t bword[13][MAXC];
     __shared__ float2 axr[13];   // per axis: the cell's least key and 1 / key range
     // one cell (blockIdx.x), or LIST: the listed cells, a grid's worth at a time
-    const int nitem = LIST ? list[0] : 1;
+    // LIST: the list's cells, unless it holds at most list_min of them
+    // (then k_sort13_large sorts them, a workgroup per cell and axis)
+    const int nitem = LIST ? (list[0] > list_min ? list[0] : 0) : 1;
     for (int item = LIST ? (int)blockIdx.x : 0; item < nitem; item += LIST ? (int)gridDim.x : 1) {
         const int c = LIST ? list[1 + item] : (int)blockIdx.x;
         const int s0 = start[c];
@@ -233,14 +235,20 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
                                                     uint16_t *__restrict__ sidx,
                                                     int64_t tslots,
                                                     float *__restrict__ tiles,
-                                                    const int32_t *__restrict__ big)
+                                                    const int32_t *__restrict__ big,
+                                                    const int32_t *__restrict__ mid, int mid_max)
 {
     __shared__ __align__(16) unsigned char lds[sort_lds_bytes(MAXCNT)];
     __shared__ float ax_kmin, ax_scale;
     const int s = blockIdx.y;   // the axis of this workgroup
-    const int nbig = big[0];
+    // the list's cells, then (mid, may be NULL) those of a second list when
+    // it holds at most mid_max cells (else that list's whole-cell kernel
+    // sorts them: few cells sort sooner a workgroup per cell and axis)
+    const int nb1 = big[0];
+    const int nb2 = mid && mid[0] <= mid_max ? mid[0] : 0;
+    const int nbig = nb1 + nb2;
     for (int item = blockIdx.x; item < nbig; item += gridDim.x) {
-        const int c = big[1 + item];
+        const int c = item < nb1 ? big[1 + item] : mid[1 + item - nb1];
         const int s0 = start[c];
         const int cnt = start[c + 1] - s0;
         const BoxDesc &B = box[cell_box[c]];
@@ -362,6 +370,10 @@ __global__ void __launch_bounds__(kBlock) k_sort13_large(const BoxDesc *__restri
 // such cells launches only a few workgroups for them.  (Larger
 // one-particle-per-thread classes measured slower than the looping kernel:
 // their LDS leaves two workgroups per compute unit.)
+// Lists of 257..512-particle cells up to this long are sorted a workgroup per
+// (cell, axis) with the large cells; longer ones a workgroup per cell.
+constexpr int kMidSplit = 64;
+
 hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t ncell)
 {
     if (ncell == 0 || n == 0) return hipSuccess;
@@ -373,23 +385,28 @@ hipError_t launch_sort13(hipStream_t st, const DevCells &c, int64_t n, int64_t n
     if (!dense)
         hipLaunchKernelGGL((k_sort13_small<64, 32, false>), dim3((unsigned)ncell), dim3(64), 0, st,
                            c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
-                           c.tslots, c.tiles, 1, (const int32_t *)nullptr);
+                           c.tslots, c.tiles, 1, (const int32_t *)nullptr, 0);
     hipLaunchKernelGGL((k_sort13_small<256, 256, false>), dim3((unsigned)ncell), dim3(256), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
-                       c.tslots, c.tiles, dense ? 1 : 65, (const int32_t *)nullptr);
-    // the cells of 257..512 particles, listed by the cell finish
+                       c.tslots, c.tiles, dense ? 1 : 65, (const int32_t *)nullptr, 0);
+    // the cells of 257..512 particles, listed by the cell finish (a long
+    // list; a short one goes with the large cells below)
+    const int32_t *mid = cell_list(lists, ncell, kListMid);
     const unsigned list_wgs = (unsigned)std::min<int64_t>(ncell, kListWgs);
     hipLaunchKernelGGL((k_sort13_small<512, 256, true>), dim3(list_wgs), dim3(512), 0, st, c.box,
                        c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx, c.tslots,
-                       c.tiles, 257, (const int32_t *)cell_list(lists, ncell, kListMid));
-    // the listed large cells, one workgroup per (cell, axis)
+                       c.tiles, 257, mid, kMidSplit);
+    // the listed large cells (and a short list of 257..512-particle cells),
+    // one workgroup per (cell, axis)
     const unsigned big_wgs = (unsigned)std::min<int64_t>(ncell, kSortLargeWgs);
     hipLaunchKernelGGL(k_sort13_large<kSortLargeMax>, dim3(big_wgs, 13), dim3(kBlock), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
-                       c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListBig));
+                       c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListBig), mid,
+                       kMidSplit);
     hipLaunchKernelGGL(k_sort13_large<PV_MAX_CELL>, dim3(big_wgs, 13), dim3(kBlock), 0, st,
                        c.box, c.cell_box, c.cell_start, c.xyzm, c.H, n, c.sidx,
-                       c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListHuge));
+                       c.tslots, c.tiles, (const int32_t *)cell_list(lists, ncell, kListHuge),
+                       (const int32_t *)nullptr, 0);
     return hipGetLastError();
 }
 
