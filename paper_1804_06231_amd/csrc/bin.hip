@@ -186,8 +186,9 @@ __global__ void __launch_bounds__(256) k_bin_columns(const BoxDesc *__restrict__
 __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, const int32_t *count, int32_t *start,
                                                 int *__restrict__ dflags)
 {
-    __shared__ int32_t part[1024];
-    const int T = blockDim.x;
+    __shared__ int32_t wsum[1024 / 64];
+    const int T = blockDim.x;   // a multiple of 64, at most 1024
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int64_t chunk = (ncell + T - 1) / T;
     int64_t b = threadIdx.x * chunk;
     int64_t e = b + chunk < ncell ? b + chunk : ncell;
@@ -197,22 +198,23 @@ __global__ void __launch_bounds__(1024) k_scan(int64_t ncell, const int32_t *cou
         sum += v;
         mx = v > mx ? v : mx;
     }
-    part[threadIdx.x] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan over the thread sums
-    for (int off = 1; off < T; off <<= 1) {
-        int32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    // inclusive scan of the thread sums: within each wavefront by shuffles,
+    // then the wavefront totals before each wavefront from LDS
+    int32_t inc = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t o = __shfl_up(inc, off);
+        if (lane >= off) inc += o;
     }
-    int32_t run = part[threadIdx.x] - sum;
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    for (int w = 0; w < wid; ++w) inc += wsum[w];
+    int32_t run = inc - sum;
     for (int64_t c = b; c < e; ++c) {
         int32_t v = count[c];
         start[c] = run;
         run += v;
     }
-    if (threadIdx.x == T - 1) start[ncell] = part[T - 1];
+    if (threadIdx.x == T - 1) start[ncell] = inc;
     if (!dflags) return;
     for (int off = 32; off > 0; off >>= 1) {
         int32_t o = __shfl_xor(mx, off);
