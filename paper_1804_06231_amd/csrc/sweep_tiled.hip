@@ -1515,19 +1515,37 @@ __global__ void __launch_bounds__(kBlock) k_tail_combine(SweepArgs A)
 // at a non-empty cell), then reserves its items' places with one atomic per
 // kind.  Items depend only on the cell counts and the box's
 // own cell numbering, not on the other boxes of a batch.
+// Places for n items of one kind, reserved for the whole wavefront with one
+// atomic: this lane's first place.  All 64 lanes must call it together.
+__device__ __forceinline__ int wave_reserve(int *counter, int n)
+{
+    const int lane = threadIdx.x & 63;
+    int inc = n;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(inc, off);
+        if (lane >= off) inc += o;
+    }
+    const int total = __shfl(inc, 63);
+    int base = 0;
+    if (lane == 0 && total) base = atomicAdd(counter, total);
+    return __shfl(base, 0) + inc - n;
+}
+
 __global__ void k_queue_items(const BoxDesc *__restrict__ box, const int32_t *__restrict__ cell_box,
                               const int32_t *__restrict__ start, int64_t ncell, int cap, int chunk,
                               int group, int64_t tail_from, int2 *__restrict__ items,
                               int *__restrict__ qcount)
 {
+    // every lane stays to the reservations (a wavefront-wide scan); a lane
+    // past the cells, or not at the first cell of a block, has an empty block
     const int64_t c0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c0 >= ncell) return;
-    int end = (int)c0 + 1;
-    if (group > 1) {
+    const bool live = c0 < ncell;
+    int end = live ? (int)c0 + 1 : (int)c0;
+    if (live && group > 1) {
         const BoxDesc &B = box[cell_box[c0]];
         const int zr = ((int)c0 - B.cell_off) % B.g[2];   // place in its z-row
-        if (zr % group != 0) return;                      // not the first of a block
-        end = (int)c0 + min(group, B.g[2] - zr);
+        end = zr % group != 0 ? (int)c0                    // not the first of a block
+                              : (int)c0 + min(group, B.g[2] - zr);
     }
     // the block's cell counts, loaded side by side
     int na[kGroupMax];
@@ -1575,9 +1593,9 @@ __global__ void k_queue_items(const BoxDesc *__restrict__ box, const int32_t *__
         }
         close_run();
         if (pass == 0) {
-            if (nsmall) base_small = atomicAdd(&qcount[1], nsmall);
-            if (nchunk) base_chunk = atomicAdd(&qcount[0], nchunk);
-            if (ntail) base_tail = atomicAdd(&qcount[3], ntail);
+            base_small = wave_reserve(&qcount[1], nsmall);
+            base_chunk = wave_reserve(&qcount[0], nchunk);
+            base_tail = wave_reserve(&qcount[3], ntail);
         }
     }
 }
